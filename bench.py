@@ -1,0 +1,191 @@
+"""Benchmark: snapshot GB/s compressed by the sketched column ID on one MI355X.
+
+A step is one pass of the whole method over the resident batch: sketch
+update over every column, column selection, coefficients and the
+reconstruction-error pass.  The timed region starts with the snapshot matrices
+already in HBM.  Prints one JSON line (rank 0).
+
+Default workload: analytic TGV 128^3 + 1e-6 noise, 512 blocks of 16^3
+(m_b = 12288 FP64), 256 snapshots, tolerance 1e-8 with k <= 32, l = 42.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="tgv128_b512_f64")
+    ap.add_argument("--cpu-sample-blocks", type=int, default=24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build measures one GPU only: the blocks are "
+                          "independent and a multi-GPU run would shard them with no exchange; "
+                          "run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+    import spid_inputs as si
+    import paper_2103_01380_amd as sp
+
+    w = si.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    A, m, n, off = si.generate(w, device=dev)
+    torch.cuda.synchronize()
+    log(args, f"generated {w.name}: {A.numel() * A.element_size() / 1e9:.2f} GB in "
+              f"{time.time() - t0:.1f}s")
+    nbytes = int((m * n.astype(np.int64)).sum()) * w.elem_bytes
+    ctx = sp.SPID(m, n, w.l, w.k_max, tol=w.tol, seed=w.omega_seed,
+                  a_dtype=w.a_dtype, prec=w.prec, lp_terms=w.lp_terms, device=dev)
+    ctx.bind(A, offsets=off)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.sketch_update(stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        ctx.select(stream)
+        if ev is not None:
+            ev[2].record(stream)
+        ctx.coeffs(stream)
+        if ev is not None:
+            ev[3].record(stream)
+        ctx.reconstruct(stream=stream)
+        if ev is not None:
+            ev[4].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    stage = np.zeros(4)
+    for e in evs:
+        for i in range(4):
+            stage[i] += e[i].elapsed_time(e[i + 1])
+    stage /= args.steps                     # ms per stage
+    ms_step = wall * 1e3 / args.steps
+    value = nbytes / (ms_step * 1e-3) / 1e9
+    rel_err = ctx.rel_error()
+    kk = ctx.k.cpu().numpy()
+    cf = float((m * n.astype(np.int64)).sum() / max(1, (kk * (m + n)).sum()))
+    log(args, f"stage ms: sketch {stage[0]:.3f} select {stage[1]:.3f} coeffs {stage[2]:.3f} "
+              f"recon {stage[3]:.3f}; step {ms_step:.3f} ms; rel err {rel_err:.3e}")
+
+    # roofline of the dominant kernel (algorithmic bytes / flops per launch)
+    sk_flops = 2.0 * w.l * float((m * n.astype(np.int64)).sum())
+    rc_flops = 2.0 * float((m * (n.astype(np.int64) - kk) * kk).sum())
+    kernels = {
+        "sketch": (stage[0], nbytes, sk_flops),
+        "reconstruct": (stage[3], nbytes, rc_flops),
+    }
+    dom = max(kernels, key=lambda x: kernels[x][0])
+    t_ms, b_alg, f_alg = kernels[dom]
+    gbs = b_alg / (t_ms * 1e-3) / 1e9
+    tfl = f_alg / (t_ms * 1e-3) / 1e12
+    peak_t = PEAK_TFLOPS["f64" if (w.prec == "f64" and dom == "sketch") else
+                         ("f64" if dom == "reconstruct" else w.prec)]
+    # bound: whichever roof is closer to the achieved rate
+    if tfl / peak_t > gbs / PEAK_HBM_GBS:
+        roof = {"bound": "mfma", "achieved": round(tfl, 3), "peak": peak_t, "unit": "TFLOP/s",
+                "frac": round(tfl / peak_t, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    roof["kernel"] = dom
+    roof["traffic"] = None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args, w, A, m, n, off)
+
+    out = {
+        "metric": "snapshot GB/s compressed at rel. err <= 1e-3 (sketched column ID: sketch + "
+                  "CPQR select + coefficients + reconstruction error)",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w.prec == "f64" else f"{w.prec}-sketch/f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "description": w.description,
+                   "nblocks": int(len(m)), "bytes": nbytes, "l": w.l, "k_max": w.k_max,
+                   "tol": w.tol},
+        "rel_error": rel_err,
+        "error_gate_1e-3": bool(rel_err <= 1e-3),
+        "compression_factor": round(cf, 3),
+        "k_mean": float(kk.mean()),
+        "stage_ms": {"sketch": round(stage[0], 4), "select": round(stage[1], 4),
+                     "coeffs": round(stage[2], 4), "reconstruct": round(stage[3], 4)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(args, w, A, m, n, off):
+    """The oracle, as it stands, on a bounded sample of the same blocks."""
+    import spid_inputs as si
+    import oracle
+    nb = len(m)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(nb, size=min(args.cpu_sample_blocks, nb), replace=False))
+    blocks = [si.block_view(A, m, n, off, int(b)) for b in sample]
+    threads = len(os.sched_getaffinity(0))
+    prec = {"f64": oracle.OMEGA_F64, "bf16": oracle.OMEGA_BF16, "fp8": oracle.OMEGA_FP8E4M3}
+    t0 = time.perf_counter()
+    res = oracle.run_batch(blocks, l=w.l, k_max=w.k_max, seed=w.omega_seed, tol=w.tol,
+                           prec=prec[w.prec], nthreads=threads)
+    dt = time.perf_counter() - t0
+    sbytes = int(sum(b.shape[0] * b.shape[1] for b in blocks)) * w.elem_bytes
+    log(args, f"cpu oracle: {len(blocks)} blocks, {threads} threads, {dt:.1f}s, "
+              f"rel err {res.rel_error:.3e}")
+    return {"value": round(sbytes / dt / 1e9, 5), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(blocks)} of {nb} blocks (seeded choice), whole method per block, "
+                      f"{dt:.1f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * spid.h -- C ABI of the MI355X (gfx950) sketched column interpolative
+ * decomposition of per-subdomain snapshot matrices.
+ *
+ * Method (arXiv 2103.01380, "Task-parallel in-situ temporal compression of
+ * large-scale CFD data"):
+ *   A_b (m_b spatial values x n_b snapshots, Section 2) is compressed per
+ *   spatial block independently (Section 3.2) into k_b selected time columns
+ *   S_b and a coefficient matrix P_b with A_b ~ A_b(:,S_b) P_b:
+ *     1. sketch      Y_b = Omega A_b, Omega l x m_b i.i.d. standard normal
+ *                    (Section 2, random projection; indices and coefficients
+ *                    of the sketch transfer to A);
+ *     2. select      rank-k column-pivoted QR of Y_b by modified Gram-Schmidt
+ *                    (Section 2, Algorithm 1 "mgsqr"), or stopped at a
+ *                    tolerance (Remark 2.1);
+ *     3. coeffs      P_b = [I_k | R11^+ R12] Z^T (Section 2, Algorithm 1);
+ *     4. reconstruct ||A_b - A_b(:,S_b) P_b||_F^2 and ||A_b||_F^2, the parts of
+ *                    the relative Frobenius error of Section 5.1.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked d_ are device (HBM) pointers, h_ are host pointers.  The
+ *     caller owns every buffer.  The library never allocates device memory:
+ *     all of its state lives in the caller's workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     The compute calls only enqueue kernels (no host synchronisation, no
+ *     allocation), so the sequence sketch -> select -> coeffs -> reconstruct
+ *     can be captured into a HIP graph.
+ *   - Host-side validation is synchronous: on error nothing is enqueued, a
+ *     negative spid_status is returned and spid_last_error() describes it.
+ *     Numerical conditions of a block never fail the batch; they are
+ *     reported per block in d_status (SPID_BLOCK_*).
+ *   - Matrices are column-major.  Block b of A is m_b x n_b with leading
+ *     dimension lda_b >= m_b, in the context's A dtype.
+ */
+#ifndef SPID_H
+#define SPID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spid_ctx spid_ctx;
+
+typedef enum {
+  SPID_OK = 0,
+  SPID_EINVAL = -1,     /* invalid argument or descriptor */
+  SPID_EWORKSPACE = -2, /* workspace too small or misaligned (256 B) */
+  SPID_EHIP = -3,       /* a HIP call or kernel launch failed */
+  SPID_ESTATE = -4      /* call out of order (e.g. select before the sketch
+                           covers every column, coeffs before select) */
+} spid_status;
+
+/* per-block numerical status written by spid_select */
+enum {
+  SPID_BLOCK_OK = 0,
+  SPID_BLOCK_RANK_DEFICIENT = 1, /* a zero pivot (or one under rank_floor):
+                                    fewer than k_max columns were taken */
+  SPID_BLOCK_NONFINITE = 2,      /* NaN/Inf in the sketch: k_b = 0 */
+  SPID_BLOCK_TOL_NOT_MET = 3     /* tolerance mode reached k_max first */
+};
+
+typedef enum { SPID_A_F64 = 0, SPID_A_F32 = 1 } spid_adtype;
+
+/* Arithmetic of the sketch product.  F64: double-precision Omega and A on the
+ * FP64 matrix cores.  BF16 / FP8E4M3: Omega is the double-precision normal
+ * rounded to nearest-even bfloat16 / OCP e4m3, A is split into lp_terms
+ * low-precision terms (hi + lo [+ lo2]) with FP32 accumulation; for FP8 every
+ * 32 consecutive rows of a column carry their own power-of-two scale (the
+ * per-block scaling).  Selection and coefficients are always FP64. */
+typedef enum { SPID_SK_F64 = 0, SPID_SK_BF16 = 1, SPID_SK_FP8E4M3 = 2 } spid_skprec;
+
+typedef struct {
+  int32_t nblocks;          /* number of spatial blocks (>= 1) */
+  const int64_t* h_m;       /* host [nblocks]: rows m_b (>= 1) */
+  const int32_t* h_n;       /* host [nblocks]: snapshots n_b (>= 1) */
+  int32_t l;                /* sketch rows, 1 <= l <= 128 */
+  int32_t k_max;            /* rank (tol == 0) or rank cap (tol > 0), <= 128;
+                               fixed rank requires k_max <= min(l, n_b) */
+  double tol;               /* 0: fixed rank.  > 0: stop after the first step
+                               with ||Y - Y(:,S)P||_F <= tol ||Y||_F (Remark
+                               2.1), k_b <= min(k_max, l, n_b) */
+  double rank_floor;        /* > 0: stop before a pivot whose squared residual
+                               norm is <= rank_floor^2 * max_j ||Y(:,j)||^2 */
+  uint64_t seed;            /* Omega seed (Philox4x32-10 key) */
+  int32_t omega_per_block;  /* 0: Omega(r,i) shared by all blocks (block b
+                               uses the prefix of m_b columns); 1: block b
+                               keys its own Omega with b+1 */
+  int32_t a_dtype;          /* spid_adtype */
+  int32_t prec;             /* spid_skprec */
+  int32_t lp_terms;         /* 1..3 split terms of A for BF16/FP8 (ignored
+                               for F64) */
+} spid_desc;
+
+/* Bytes of device workspace a descriptor needs (0 if the descriptor is
+ * invalid; spid_last_error() says why).  Host-only, no HIP call. */
+size_t spid_workspace_bytes(const spid_desc* desc);
+
+/* Create a context on the current HIP device.  `d_workspace` (256-byte
+ * aligned, >= spid_workspace_bytes) is owned by the caller and must outlive
+ * the context.  Copies the block table into the workspace with a synchronous
+ * copy (a set-up call: not for graph capture).  *out receives a host object
+ * freed by spid_destroy. */
+spid_status spid_create(const spid_desc* desc, void* d_workspace, size_t ws_bytes,
+                        spid_ctx** out);
+
+/* Bind the snapshot data: h_block_ptrs[b] is the device address of block b
+ * (column-major, m_b x n_b, A dtype), h_lda[b] >= m_b its leading dimension
+ * (elements).  Host arrays of length nblocks; synchronous set-up copy.  May
+ * be called again to rebind; it resets the sketch coverage. */
+spid_status spid_bind_A(spid_ctx* ctx, const void* const* h_block_ptrs, const int64_t* h_lda);
+
+/* Sketch update (Section 2, B = Omega A; Algorithm 5's per-step storage of a
+ * snapshot becomes a sketch update): for every block,
+ *   Y_b(:, j) = Omega_b A_b(:, j)   for j0 <= j < min(j0 + w, n_b).
+ * Overwrites those sketch columns, so repeating a call is idempotent.  Called
+ * once with (0, max n) for a resident batch, or once per arriving snapshot
+ * with w = 1. */
+spid_status spid_sketch_update(spid_ctx* ctx, int32_t j0, int32_t w, void* stream);
+
+/* Column selection (Section 2, Algorithm 1 mgsqr on the sketch; Remark 2.1):
+ * pivot = largest remaining column norm (ties: lowest column index), one
+ * modified Gram-Schmidt sweep per step, norms recomputed each step.
+ * Outputs (device): d_k[nblocks] = k_b, d_S[nblocks*k_max] = pivot columns of
+ * block b at d_S[b*k_max + t] in pivot order (-1 past k_b),
+ * d_status[nblocks].  Any output pointer may be NULL.  R is kept in the
+ * workspace for spid_coeffs.  ESTATE unless every column was sketched. */
+spid_status spid_select(spid_ctx* ctx, int32_t* d_k, int32_t* d_S, int32_t* d_status,
+                        void* stream);
+
+/* Coefficients (Section 2, Algorithm 1): P_b = [I | R11^+ R12] Z^T, FP64.
+ * d_P holds every block's k_max x n_b column-major matrix (leading dimension
+ * k_max) at element offset k_max * sum_{c<b} n_c; P_b(:, S[t]) = e_t exactly,
+ * other columns solve R11 x = R12(:, j) by back-substitution, rows >= k_b are
+ * zero.  ESTATE before spid_select. */
+spid_status spid_coeffs(spid_ctx* ctx, double* d_P, void* stream);
+
+/* Reconstruction error (Section 5.1) against the stored A:
+ *   d_err2[b] = ||A_b - A_b(:,S_b) P_b||_F^2 (FP64 sum of squares),
+ *   d_nrm2[b] = ||A_b||_F^2.
+ * d_P as written by spid_coeffs.  d_skeleton (nullable) receives A_b(:,S_b),
+ * m_b x k_max column-major in the A dtype at element offset
+ * k_max * sum_{c<b} m_c (columns >= k_b untouched).  Sums are deterministic
+ * (fixed reduction order).  ESTATE before spid_select. */
+spid_status spid_reconstruct(spid_ctx* ctx, const double* d_P, double* d_err2, double* d_nrm2,
+                             void* d_skeleton, void* stream);
+
+/* Test/diagnostic access: copy the sketch Y, widened to FP64, into d_Y
+ * (block b: l x n_b column-major at element offset l * sum_{c<b} n_c). */
+spid_status spid_copy_sketch(spid_ctx* ctx, double* d_Y, void* stream);
+
+/* Release the host object (the workspace stays the caller's). */
+spid_status spid_destroy(spid_ctx* ctx);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* spid_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPID_H */

@@ -1,0 +1,554 @@
+// spid.hip -- host side of the C ABI declared in include/spid.h: descriptor
+// validation, workspace planning, work-item tables and kernel dispatch for
+// gfx950.  Every compute entry point only enqueues kernels on the caller's
+// stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/spid.h"
+#include "spid_kernels.h"
+
+using namespace spid;
+
+namespace {
+
+thread_local std::string g_err;
+
+spid_status fail(spid_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+constexpr int kMaxL = 128;
+constexpr int kMaxK = 96;
+constexpr int kMaxN = 1024;
+constexpr int kRcRows = 256;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// tile/template choices for a descriptor
+struct Shape {
+  int MT;        // 16-row MFMA tiles covering l
+  int TN;        // 16-column tiles per wave in the sketch
+  int LMAX;      // register rows of a sketch column in the selection
+  int CPT;       // sketch columns per thread in the selection
+  int sel_thr;   // selection workgroup size
+  int KMAX;      // register skeleton width in the error pass
+};
+
+int pick_mt(int l) {
+  const int t = (l + 15) / 16;
+  if (t <= 4) return t;
+  if (t <= 6) return 6;
+  return 8;
+}
+
+int pick_lmax(int l) {
+  const int opts[] = {16, 32, 48, 56, 64, 96, 128};
+  for (int o : opts)
+    if (l <= o) return o;
+  return 128;
+}
+
+int pick_kmax(int k) {
+  const int opts[] = {8, 16, 32, 48, 64, 96};
+  for (int o : opts)
+    if (k <= o) return o;
+  return 96;
+}
+
+// Workspace plan (sizes in bytes, offsets from the workspace base)
+struct Plan {
+  Shape sh;
+  int ydt;                       // 0: Y in FP64, 1: Y in FP32
+  std::vector<BlkInfo> blk;
+  std::vector<SkItem> items;
+  std::vector<int32_t> split_blocks;
+  std::vector<RcItem> rc;
+  std::vector<int64_t> rc_first;
+  int64_t sum_n = 0, sum_m = 0, part_elems = 0;
+  int max_n = 0, max_split_n = 0;
+  size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
+      off_st, off_rcpart, total;
+};
+
+spid_status validate(const spid_desc* d) {
+  if (!d) return fail(SPID_EINVAL, "descriptor is NULL");
+  if (d->nblocks < 1) return fail(SPID_EINVAL, "nblocks must be >= 1 (got %d)", d->nblocks);
+  if (!d->h_m || !d->h_n) return fail(SPID_EINVAL, "h_m and h_n must be host arrays");
+  if (d->l < 1 || d->l > kMaxL) return fail(SPID_EINVAL, "l must be in [1, %d] (got %d)", kMaxL, d->l);
+  if (d->k_max < 1 || d->k_max > kMaxK)
+    return fail(SPID_EINVAL, "k_max must be in [1, %d] (got %d)", kMaxK, d->k_max);
+  if (!(d->tol >= 0.0)) return fail(SPID_EINVAL, "tol must be >= 0");
+  if (!(d->rank_floor >= 0.0)) return fail(SPID_EINVAL, "rank_floor must be >= 0");
+  if (d->a_dtype != SPID_A_F64 && d->a_dtype != SPID_A_F32)
+    return fail(SPID_EINVAL, "a_dtype must be SPID_A_F64 or SPID_A_F32");
+  if (d->prec != SPID_SK_F64 && d->prec != SPID_SK_BF16)
+    return fail(SPID_EINVAL, "sketch precision %d is not supported by this build", d->prec);
+  if (d->prec != SPID_SK_F64 && (d->lp_terms < 1 || d->lp_terms > 3))
+    return fail(SPID_EINVAL, "lp_terms must be 1..3 (got %d)", d->lp_terms);
+  for (int b = 0; b < d->nblocks; ++b) {
+    const int64_t m = d->h_m[b];
+    const int32_t n = d->h_n[b];
+    if (m < 1 || m >= (int64_t(1) << 31))
+      return fail(SPID_EINVAL, "block %d: m must be in [1, 2^31) (got %lld)", b, (long long)m);
+    if (n < 1 || n > kMaxN)
+      return fail(SPID_EINVAL, "block %d: n must be in [1, %d] (got %d)", b, kMaxN, n);
+    if (d->tol == 0.0 && (d->k_max > d->l || d->k_max > n))
+      return fail(SPID_EINVAL,
+                  "block %d: fixed rank k_max=%d exceeds min(l=%d, n=%d)", b, d->k_max, d->l, n);
+  }
+  return SPID_OK;
+}
+
+spid_status make_plan(const spid_desc* d, Plan& p) {
+  spid_status st = validate(d);
+  if (st != SPID_OK) return st;
+  const int nb = d->nblocks;
+  p.ydt = (d->prec == SPID_SK_F64) ? 0 : 1;
+  for (int b = 0; b < nb; ++b) {
+    p.sum_n += d->h_n[b];
+    p.sum_m += d->h_m[b];
+    p.max_n = std::max(p.max_n, (int)d->h_n[b]);
+  }
+  Shape& sh = p.sh;
+  sh.MT = pick_mt(d->l);
+  // columns per workgroup tile: 64*TN
+  if (p.ydt == 0) {
+    sh.TN = p.max_n >= 256 ? 4 : (p.max_n >= 128 ? 2 : 1);
+  } else {
+    sh.TN = p.max_n >= 256 ? 4 : (p.max_n >= 128 ? 2 : 1);
+  }
+  sh.LMAX = pick_lmax(d->l);
+  sh.CPT = (p.max_n > 512) ? 2 : 1;
+  {
+    int need = (p.max_n + sh.CPT - 1) / sh.CPT;
+    sh.sel_thr = std::max(64, (need + 63) / 64 * 64);
+  }
+  if (sh.CPT * sh.LMAX > 112)
+    return fail(SPID_EINVAL, "l=%d with n up to %d exceeds the selection register budget", d->l,
+                p.max_n);
+  sh.KMAX = pick_kmax(d->k_max);
+
+  // sketch work items: column tiles x K splits
+  const int tile_cols = 64 * sh.TN;
+  int64_t base_items = 0;
+  for (int b = 0; b < nb; ++b) base_items += (d->h_n[b] + tile_cols - 1) / tile_cols;
+  const int64_t target = 2048;
+  const int64_t min_rows = 256;
+  p.blk.resize(nb);
+  int64_t y_off = 0, r_off = 0, p_off = 0, sk_off = 0, part_off = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int64_t m = d->h_m[b];
+    const int32_t n = d->h_n[b];
+    int nsplit = 1;
+    if (base_items < target) {
+      const int64_t want = (target + base_items - 1) / base_items;
+      const int64_t cap = std::max<int64_t>(1, m / min_rows);
+      nsplit = (int)std::min(want, cap);
+    }
+    // rows per split, multiple of the chunk
+    int64_t rows = (m + nsplit - 1) / nsplit;
+    rows = (rows + kKC - 1) / kKC * kKC;
+    nsplit = (int)((m + rows - 1) / rows);
+    BlkInfo bi{};
+    bi.A = nullptr;
+    bi.lda = m;
+    bi.m = m;
+    bi.n = n;
+    bi.y_off = y_off;
+    bi.r_off = r_off;
+    bi.p_off = p_off;
+    bi.sk_off = sk_off;
+    bi.nsplit = nsplit;
+    bi.part_off = nsplit > 1 ? part_off : 0;
+    bi.vec_ok = 0;
+    p.blk[b] = bi;
+    y_off += (int64_t)d->l * n;
+    r_off += (int64_t)d->k_max * n;
+    p_off += (int64_t)d->k_max * n;
+    sk_off += (int64_t)d->k_max * m;
+    if (nsplit > 1) {
+      part_off += (int64_t)nsplit * d->l * n;
+      p.split_blocks.push_back(b);
+      p.max_split_n = std::max(p.max_split_n, (int)n);
+    }
+    for (int c0 = 0; c0 < n; c0 += tile_cols)
+      for (int s = 0; s < nsplit; ++s) {
+        SkItem it{};
+        it.blk = b;
+        it.c0 = c0;
+        it.split = s;
+        it.r0 = (int64_t)s * rows;
+        it.r1 = std::min(m, (int64_t)(s + 1) * rows);
+        p.items.push_back(it);
+      }
+    p.rc_first.push_back((int64_t)p.rc.size());
+    for (int64_t i0 = 0; i0 < m; i0 += kRcRows) {
+      RcItem r{};
+      r.blk = b;
+      r.i0 = i0;
+      p.rc.push_back(r);
+    }
+  }
+  p.rc_first.push_back((int64_t)p.rc.size());
+  p.part_elems = part_off;
+  const size_t ysz = p.ydt == 0 ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  p.off_blk = take(sizeof(BlkInfo) * nb);
+  p.off_items = take(sizeof(SkItem) * p.items.size());
+  p.off_split = take(sizeof(int32_t) * std::max<size_t>(1, p.split_blocks.size()));
+  p.off_rc = take(sizeof(RcItem) * p.rc.size());
+  p.off_rcfirst = take(sizeof(int64_t) * p.rc_first.size());
+  p.off_Y = take(ysz * (size_t)d->l * p.sum_n);
+  p.off_part = take(ysz * (size_t)std::max<int64_t>(1, p.part_elems));
+  p.off_R = take(sizeof(double) * (size_t)d->k_max * p.sum_n);
+  p.off_S = take(sizeof(int32_t) * (size_t)nb * d->k_max);
+  p.off_k = take(sizeof(int32_t) * nb);
+  p.off_st = take(sizeof(int32_t) * nb);
+  p.off_rcpart = take(sizeof(double) * 2 * p.rc.size());
+  p.total = off;
+  return SPID_OK;
+}
+
+}  // namespace
+
+struct spid_ctx {
+  spid_desc desc;
+  std::vector<int64_t> m;
+  std::vector<int32_t> n;
+  Plan plan;
+  char* ws = nullptr;
+  bool bound = false;
+  bool selected = false;
+  bool coeffs_lds_set = false;
+  std::vector<uint8_t> covered;   // per column index: sketched since bind
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+};
+
+namespace {
+
+spid_status hip_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SPID_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return SPID_OK;
+}
+
+// ---- sketch dispatch
+template <typename TA, int MT, int TN>
+void launch_sketch_t(spid_ctx* c, int j0, int j1, hipStream_t s) {
+  const Plan& p = c->plan;
+  dim3 grid((unsigned)p.items.size());
+  if (p.ydt == 0) {
+    hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN>), grid, dim3(kSkThreads), 0, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->at<double>(p.off_Y),
+                       c->at<double>(p.off_part));
+  } else {
+    hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN>), grid, dim3(kSkThreads), 0, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+                       c->at<float>(p.off_Y), c->at<float>(p.off_part));
+  }
+}
+
+template <typename TA, int MT>
+void launch_sketch_mt(spid_ctx* c, int j0, int j1, hipStream_t s) {
+  switch (c->plan.sh.TN) {
+    case 1: launch_sketch_t<TA, MT, 1>(c, j0, j1, s); break;
+    case 2: launch_sketch_t<TA, MT, 2>(c, j0, j1, s); break;
+    default: launch_sketch_t<TA, MT, 4>(c, j0, j1, s); break;
+  }
+}
+
+template <typename TA>
+void launch_sketch_a(spid_ctx* c, int j0, int j1, hipStream_t s) {
+  switch (c->plan.sh.MT) {
+    case 1: launch_sketch_mt<TA, 1>(c, j0, j1, s); break;
+    case 2: launch_sketch_mt<TA, 2>(c, j0, j1, s); break;
+    case 3: launch_sketch_mt<TA, 3>(c, j0, j1, s); break;
+    case 4: launch_sketch_mt<TA, 4>(c, j0, j1, s); break;
+    case 6: launch_sketch_mt<TA, 6>(c, j0, j1, s); break;
+    default: launch_sketch_mt<TA, 8>(c, j0, j1, s); break;
+  }
+}
+
+// ---- selection dispatch
+template <typename TY, int LMAX, int CPT>
+void launch_select_t(spid_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
+  hipLaunchKernelGGL((select_kernel<TY, LMAX, CPT>), dim3(c->desc.nblocks), dim3(p.sh.sel_thr), 0,
+                     s, c->at<BlkInfo>(p.off_blk), c->desc.l, c->desc.k_max, c->desc.tol,
+                     c->desc.rank_floor, c->at<TY>(p.off_Y), c->at<double>(p.off_R),
+                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), c->at<int32_t>(p.off_st));
+}
+
+template <typename TY, int LMAX>
+void launch_select_l(spid_ctx* c, hipStream_t s) {
+  if (c->plan.sh.CPT == 1) {
+    launch_select_t<TY, LMAX, 1>(c, s);
+  } else {
+    if constexpr (LMAX <= 56) launch_select_t<TY, LMAX, 2>(c, s);
+  }
+}
+
+template <typename TY>
+void launch_select_y(spid_ctx* c, hipStream_t s) {
+  switch (c->plan.sh.LMAX) {
+    case 16: launch_select_l<TY, 16>(c, s); break;
+    case 32: launch_select_l<TY, 32>(c, s); break;
+    case 48: launch_select_l<TY, 48>(c, s); break;
+    case 56: launch_select_l<TY, 56>(c, s); break;
+    case 64: launch_select_l<TY, 64>(c, s); break;
+    case 96: launch_select_l<TY, 96>(c, s); break;
+    default: launch_select_l<TY, 128>(c, s); break;
+  }
+}
+
+// ---- reconstruction dispatch
+template <typename TA, int KMAX>
+void launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
+  const Plan& p = c->plan;
+  hipLaunchKernelGGL((recon_kernel<TA, KMAX>), dim3((unsigned)p.rc.size()), dim3(kRcRows), 0, s,
+                     c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.k_max,
+                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
+                     static_cast<TA*>(skel), c->at<double>(p.off_rcpart));
+}
+
+template <typename TA>
+void launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
+  switch (c->plan.sh.KMAX) {
+    case 8: launch_recon_t<TA, 8>(c, P, skel, s); break;
+    case 16: launch_recon_t<TA, 16>(c, P, skel, s); break;
+    case 32: launch_recon_t<TA, 32>(c, P, skel, s); break;
+    case 48: launch_recon_t<TA, 48>(c, P, skel, s); break;
+    case 64: launch_recon_t<TA, 64>(c, P, skel, s); break;
+    default: launch_recon_t<TA, 96>(c, P, skel, s); break;
+  }
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+
+extern "C" size_t spid_workspace_bytes(const spid_desc* desc) {
+  Plan p;
+  if (make_plan(desc, p) != SPID_OK) return 0;
+  return p.total;
+}
+
+extern "C" spid_status spid_create(const spid_desc* desc, void* d_workspace, size_t ws_bytes,
+                                   spid_ctx** out) {
+  if (!out) return fail(SPID_EINVAL, "out is NULL");
+  *out = nullptr;
+  spid_ctx* c = new (std::nothrow) spid_ctx();
+  if (!c) return fail(SPID_EINVAL, "host allocation failed");
+  spid_status st = make_plan(desc, c->plan);
+  if (st != SPID_OK) {
+    delete c;
+    return st;
+  }
+  const Plan& p = c->plan;
+  if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0) {
+    delete c;
+    return fail(SPID_EWORKSPACE, "workspace must be a 256-byte aligned device pointer");
+  }
+  if (ws_bytes < p.total) {
+    delete c;
+    return fail(SPID_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, p.total);
+  }
+  c->desc = *desc;
+  c->m.assign(desc->h_m, desc->h_m + desc->nblocks);
+  c->n.assign(desc->h_n, desc->h_n + desc->nblocks);
+  c->desc.h_m = c->m.data();
+  c->desc.h_n = c->n.data();
+  c->ws = static_cast<char*>(d_workspace);
+  c->covered.assign(p.max_n, 0);
+  hipError_t e = hipMemcpy(c->ws + p.off_blk, p.blk.data(), sizeof(BlkInfo) * p.blk.size(),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->ws + p.off_items, p.items.data(), sizeof(SkItem) * p.items.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p.split_blocks.empty())
+    e = hipMemcpy(c->ws + p.off_split, p.split_blocks.data(),
+                  sizeof(int32_t) * p.split_blocks.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->ws + p.off_rc, p.rc.data(), sizeof(RcItem) * p.rc.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->ws + p.off_rcfirst, p.rc_first.data(), sizeof(int64_t) * p.rc_first.size(),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(SPID_EHIP, "spid_create: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return SPID_OK;
+}
+
+extern "C" spid_status spid_bind_A(spid_ctx* c, const void* const* h_block_ptrs,
+                                   const int64_t* h_lda) {
+  if (!c || !h_block_ptrs || !h_lda) return fail(SPID_EINVAL, "NULL argument to spid_bind_A");
+  Plan& p = c->plan;
+  const size_t es = c->desc.a_dtype == SPID_A_F64 ? 8 : 4;
+  for (int b = 0; b < c->desc.nblocks; ++b) {
+    if (!h_block_ptrs[b]) return fail(SPID_EINVAL, "block %d: NULL data pointer", b);
+    if (h_lda[b] < c->m[b])
+      return fail(SPID_EINVAL, "block %d: lda=%lld < m=%lld", b, (long long)h_lda[b],
+                  (long long)c->m[b]);
+    if (((uintptr_t)h_block_ptrs[b]) % es != 0)
+      return fail(SPID_EINVAL, "block %d: pointer not aligned to the element size", b);
+  }
+  for (int b = 0; b < c->desc.nblocks; ++b) {
+    BlkInfo& bi = p.blk[b];
+    bi.A = h_block_ptrs[b];
+    bi.lda = h_lda[b];
+    bi.vec_ok = (((uintptr_t)bi.A % 16) == 0 && ((bi.lda * (int64_t)es) % 16) == 0) ? 1 : 0;
+  }
+  hipError_t e = hipMemcpy(c->ws + p.off_blk, p.blk.data(), sizeof(BlkInfo) * p.blk.size(),
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(SPID_EHIP, "spid_bind_A: %s", hipGetErrorString(e));
+  c->bound = true;
+  c->selected = false;
+  std::fill(c->covered.begin(), c->covered.end(), 0);
+  return SPID_OK;
+}
+
+extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, void* stream) {
+  if (!c) return fail(SPID_EINVAL, "NULL context");
+  if (!c->bound) return fail(SPID_ESTATE, "spid_sketch_update before spid_bind_A");
+  if (j0 < 0 || w < 1) return fail(SPID_EINVAL, "need j0 >= 0 and w >= 1 (got %d, %d)", j0, w);
+  const Plan& p = c->plan;
+  const int j1 = (int)std::min<int64_t>((int64_t)j0 + w, p.max_n);
+  if (j0 >= p.max_n) return fail(SPID_EINVAL, "j0=%d is past every block's last column", j0);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->desc.a_dtype == SPID_A_F64)
+    launch_sketch_a<double>(c, j0, j1, s);
+  else
+    launch_sketch_a<float>(c, j0, j1, s);
+  spid_status st = hip_check("sketch kernel launch");
+  if (st != SPID_OK) return st;
+  if (!p.split_blocks.empty()) {
+    dim3 grid((unsigned)(((int64_t)c->desc.l * p.max_split_n + 255) / 256),
+              (unsigned)p.split_blocks.size());
+    if (p.ydt == 0)
+      hipLaunchKernelGGL((sketch_reduce_kernel<double>), grid, dim3(256), 0, s,
+                         c->at<BlkInfo>(p.off_blk), c->at<int32_t>(p.off_split), c->desc.l, j0,
+                         j1, c->at<double>(p.off_Y), c->at<double>(p.off_part));
+    else
+      hipLaunchKernelGGL((sketch_reduce_kernel<float>), grid, dim3(256), 0, s,
+                         c->at<BlkInfo>(p.off_blk), c->at<int32_t>(p.off_split), c->desc.l, j0,
+                         j1, c->at<float>(p.off_Y), c->at<float>(p.off_part));
+    st = hip_check("sketch reduce launch");
+    if (st != SPID_OK) return st;
+  }
+  for (int j = j0; j < j1; ++j) c->covered[j] = 1;
+  c->selected = false;
+  return SPID_OK;
+}
+
+extern "C" spid_status spid_select(spid_ctx* c, int32_t* d_k, int32_t* d_S, int32_t* d_status,
+                                   void* stream) {
+  if (!c) return fail(SPID_EINVAL, "NULL context");
+  for (int j = 0; j < c->plan.max_n; ++j)
+    if (!c->covered[j])
+      return fail(SPID_ESTATE, "spid_select: sketch column %d has not been computed", j);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->plan.ydt == 0)
+    launch_select_y<double>(c, s);
+  else
+    launch_select_y<float>(c, s);
+  spid_status st = hip_check("select kernel launch");
+  if (st != SPID_OK) return st;
+  if (d_k || d_S || d_status) {
+    const int64_t tot = std::max<int64_t>((int64_t)c->desc.nblocks * c->desc.k_max,
+                                          c->desc.nblocks);
+    hipLaunchKernelGGL(select_export_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       c->desc.nblocks, c->desc.k_max, c->at<int32_t>(c->plan.off_S),
+                       c->at<int32_t>(c->plan.off_k), c->at<int32_t>(c->plan.off_st), d_k, d_S,
+                       d_status);
+    st = hip_check("select export launch");
+    if (st != SPID_OK) return st;
+  }
+  c->selected = true;
+  return SPID_OK;
+}
+
+extern "C" spid_status spid_coeffs(spid_ctx* c, double* d_P, void* stream) {
+  if (!c || !d_P) return fail(SPID_EINVAL, "NULL argument to spid_coeffs");
+  if (!c->selected) return fail(SPID_ESTATE, "spid_coeffs before spid_select");
+  const Plan& p = c->plan;
+  const size_t lds = sizeof(double) * ((size_t)c->desc.k_max * c->desc.k_max + 64 * c->desc.k_max);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (lds > 65536 && !c->coeffs_lds_set) {
+    if (hipFuncSetAttribute((const void*)coeffs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+      return fail(SPID_EHIP, "coeffs: cannot reserve %zu bytes of LDS", lds);
+    c->coeffs_lds_set = true;
+  }
+  hipLaunchKernelGGL(coeffs_kernel, dim3(c->desc.nblocks), dim3(64), lds, s,
+                     c->at<BlkInfo>(p.off_blk), c->desc.k_max, c->at<double>(p.off_R),
+                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), d_P);
+  return hip_check("coeffs kernel launch");
+}
+
+extern "C" spid_status spid_reconstruct(spid_ctx* c, const double* d_P, double* d_err2,
+                                        double* d_nrm2, void* d_skeleton, void* stream) {
+  if (!c || !d_P || !d_err2 || !d_nrm2) return fail(SPID_EINVAL, "NULL argument to spid_reconstruct");
+  if (!c->selected) return fail(SPID_ESTATE, "spid_reconstruct before spid_select");
+  const Plan& p = c->plan;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->desc.a_dtype == SPID_A_F64)
+    launch_recon_a<double>(c, d_P, d_skeleton, s);
+  else
+    launch_recon_a<float>(c, d_P, d_skeleton, s);
+  spid_status st = hip_check("reconstruct kernel launch");
+  if (st != SPID_OK) return st;
+  hipLaunchKernelGGL(recon_reduce_kernel, dim3((c->desc.nblocks + 255) / 256), dim3(256), 0, s,
+                     c->desc.nblocks, c->at<int64_t>(p.off_rcfirst), c->at<double>(p.off_rcpart),
+                     d_err2, d_nrm2);
+  return hip_check("reconstruct reduce launch");
+}
+
+extern "C" spid_status spid_copy_sketch(spid_ctx* c, double* d_Y, void* stream) {
+  if (!c || !d_Y) return fail(SPID_EINVAL, "NULL argument to spid_copy_sketch");
+  const Plan& p = c->plan;
+  const int64_t total = (int64_t)c->desc.l * p.sum_n;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dim3 grid((unsigned)((total + 255) / 256));
+  if (p.ydt == 0)
+    hipLaunchKernelGGL((copy_sketch_kernel<double>), grid, dim3(256), 0, s, total,
+                       c->at<double>(p.off_Y), d_Y);
+  else
+    hipLaunchKernelGGL((copy_sketch_kernel<float>), grid, dim3(256), 0, s, total,
+                       c->at<float>(p.off_Y), d_Y);
+  return hip_check("copy sketch launch");
+}
+
+extern "C" spid_status spid_destroy(spid_ctx* c) {
+  delete c;
+  return SPID_OK;
+}
+
+extern "C" const char* spid_last_error(void) { return g_err.c_str(); }

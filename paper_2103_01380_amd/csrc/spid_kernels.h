@@ -1,0 +1,662 @@
+// spid_kernels.h -- gfx950 kernels of the sketched column ID.
+//
+//   sketch_kernel     Y_b(:, cols) = Omega_b A_b(:, cols) on the matrix cores,
+//                     Omega regenerated per 32-row chunk into LDS.
+//   sketch_reduce     fixed-order sum of split-K partial sketches.
+//   select_kernel     pivoted modified Gram-Schmidt on the sketch, one
+//                     workgroup per block, one sketch column per lane held in
+//                     registers, pivot search by wave + LDS reduction.
+//   coeffs_kernel     back-substitution R11 x = R12(:, j), identity columns.
+//   recon_kernel      streaming residual ||A - A(:,S) P||^2 per row tile.
+//   recon_reduce      fixed-order per-block sums of the row-tile partials.
+#pragma once
+
+#include "spid_device.h"
+
+namespace spid {
+
+// Per-block table in the workspace (filled at create / bind).
+struct BlkInfo {
+  const void* A;      // device address of block b (column-major)
+  int64_t lda;        // leading dimension (elements)
+  int64_t m;          // rows
+  int64_t y_off;      // element offset of Y_b (l x n column-major)
+  int64_t r_off;      // element offset of R_b (k_max x n row-major)
+  int64_t p_off;      // element offset of P_b (k_max x n column-major)
+  int64_t sk_off;     // element offset of the skeleton (m x k_max)
+  int64_t part_off;   // element offset of the split-K partials (nsplit x l x n)
+  int32_t n;          // columns
+  int32_t nsplit;     // K splits of the sketch (1: written straight to Y)
+  int32_t vec_ok;     // 1 if column starts are 16-byte aligned
+  int32_t pad;
+};
+
+// One sketch work item: block, 64*TN-column tile, K range [r0, r1).
+struct SkItem {
+  int32_t blk;
+  int32_t c0;
+  int32_t split;      // index of the K range
+  int32_t pad;
+  int64_t r0, r1;
+};
+
+// One reconstruction work item: block, rows [i0, i0 + 256).
+struct RcItem {
+  int32_t blk;
+  int32_t pad;
+  int64_t i0;
+};
+
+constexpr int kSkThreads = 256;   // 4 waves
+constexpr int kKC = 32;           // rows per sketch chunk
+constexpr int kOmStride = kKC + 2;  // LDS row stride (doubles) of the Omega tile
+
+// Load 8 consecutive rows [row, row+8) of column `col` of block (base, lda)
+// as doubles; rows at or past `rend` read as zero.
+template <typename TA>
+__device__ __forceinline__ void load8(const TA* __restrict__ base, int64_t lda, int64_t col,
+                                      int64_t row, int64_t rend, bool vec, double out[8]) {
+  const TA* p = base + col * lda + row;
+  if (vec && row + 8 <= rend) {
+    if constexpr (sizeof(TA) == 8) {
+      const f64x2* q = reinterpret_cast<const f64x2*>(p);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const f64x2 v = __builtin_nontemporal_load(q + h);
+        out[2 * h] = v[0];
+        out[2 * h + 1] = v[1];
+      }
+    } else {
+      const f32x4* q = reinterpret_cast<const f32x4*>(p);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f32x4 v = __builtin_nontemporal_load(q + h);
+        out[4 * h] = v[0];
+        out[4 * h + 1] = v[1];
+        out[4 * h + 2] = v[2];
+        out[4 * h + 3] = v[3];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = (row + e < rend) ? (double)p[e] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sketch, double precision: Y = Omega A on v_mfma_f64_16x16x4.
+// Workgroup = 4 waves; wave w owns columns c0 + 16*TN*w + [0, 16*TN); every
+// wave covers all MT*16 sketch rows.  Per 32-row chunk: Omega (MT*16 x 32) is
+// generated into LDS by the whole workgroup, each lane loads rows
+// 8g..8g+7 (g = lane/16) of one column per 16-column tile, and eight MFMA
+// k-steps consume them (step s pairs A row 8g+s with Omega column 8g+s).
+// ---------------------------------------------------------------------------
+template <typename TA, int MT, int TN>
+__global__ __launch_bounds__(kSkThreads) void sketch_f64_kernel(
+    const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
+    int omega_per_block, int j0, int j1, double* __restrict__ Y, double* __restrict__ part) {
+  __shared__ double om[MT * 16 * kOmStride];
+  const SkItem it = items[blockIdx.x];
+  const BlkInfo bi = blks[it.blk];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  const int ncols = bi.n;
+  const int cwave = it.c0 + wave * 16 * TN;
+  // window of columns this call updates
+  const int clo = max(j0, 0), chi = min(j1, ncols);
+  if (it.c0 >= chi || it.c0 + 64 * TN <= clo) return;   // whole tile outside (uniform)
+  const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
+  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
+  const bool vec = bi.vec_ok != 0;
+
+  // rows l .. MT*16-1 of the Omega tile stay zero
+  for (int e = tid; e < MT * 16 * kOmStride; e += kSkThreads) om[e] = 0.0;
+
+  f64x4 acc[MT][TN];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[t][u] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  const int npairs = (l + 1) >> 1;
+  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC) {
+    // 1. issue this lane's A loads (column tile u, rows k0+8g .. +7)
+    double av[TN][8];
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      const int col = cwave + 16 * u + r16;
+      if (col >= clo && col < chi) {
+        load8<TA>(A, bi.lda, col, k0 + 8 * g, it.r1, vec, av[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[u][e] = 0.0;
+      }
+    }
+    __syncthreads();   // previous chunk's MFMAs finished reading om
+    // 2. Omega chunk into LDS: pair q covers rows 2q, 2q+1
+    for (int e = tid; e < npairs * kKC; e += kSkThreads) {
+      const int q = e / kKC, kk = e - q * kKC;
+      const double2 z = omega_pair(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q);
+      om[(2 * q) * kOmStride + kk] = z.x;
+      if (2 * q + 1 < l) om[(2 * q + 1) * kOmStride + kk] = z.y;
+    }
+    __syncthreads();
+    // 3. MFMA: eight k-steps of 4
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      double ov[8];
+      const double* orow = om + (16 * t + r16) * kOmStride + 8 * g;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) ov[s] = orow[s];
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int u = 0; u < TN; ++u) acc[t][u] = mfma_f64(ov[s], av[u][s], acc[t][u]);
+    }
+  }
+  // epilogue: lane holds rows 16t + g + 4v of column cwave + 16u + r16
+  double* dst;
+  if (bi.nsplit == 1) {
+    dst = Y + bi.y_off;
+  } else {
+    dst = part + bi.part_off + (int64_t)it.split * ncols * l;
+  }
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int col = cwave + 16 * u + r16;
+    if (col < clo || col >= chi) continue;
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + g + 4 * v;
+        if (row < l) dst[(int64_t)col * l + row] = acc[t][u][v];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sketch, bfloat16 (FP32 accumulation): Omega rounded to bfloat16 in LDS; A
+// split into `terms` bfloat16 terms in registers; v_mfma_f32_16x16x32_bf16.
+// Lane (g, r16) supplies rows 8g..8g+7 of its column as the 8 k-values of one
+// MFMA; Omega row 16t+r16 supplies the same 8 k-values.
+// ---------------------------------------------------------------------------
+template <typename TA, int MT, int TN>
+__global__ __launch_bounds__(kSkThreads) void sketch_bf16_kernel(
+    const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
+    int omega_per_block, int j0, int j1, int terms, float* __restrict__ Y,
+    float* __restrict__ part) {
+  constexpr int kS = kKC + 8;   // LDS row stride in bf16 elements (80 bytes)
+  __shared__ __attribute__((aligned(16))) __bf16 om[MT * 16 * kS];
+  const SkItem it = items[blockIdx.x];
+  const BlkInfo bi = blks[it.blk];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  const int ncols = bi.n;
+  const int cwave = it.c0 + wave * 16 * TN;
+  const int clo = max(j0, 0), chi = min(j1, ncols);
+  if (it.c0 >= chi || it.c0 + 64 * TN <= clo) return;
+  const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
+  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
+  const bool vec = bi.vec_ok != 0;
+
+  for (int e = tid; e < MT * 16 * kS; e += kSkThreads) om[e] = (__bf16)0.0f;
+
+  f32x4 acc[MT][TN];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int npairs = (l + 1) >> 1;
+  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC) {
+    double av[TN][8];
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      const int col = cwave + 16 * u + r16;
+      if (col >= clo && col < chi) {
+        load8<TA>(A, bi.lda, col, k0 + 8 * g, it.r1, vec, av[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[u][e] = 0.0;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < npairs * kKC; e += kSkThreads) {
+      const int q = e / kKC, kk = e - q * kKC;
+      const double2 z = omega_pair(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q);
+      om[(2 * q) * kS + kk] = to_bf16((float)rne_bf16(z.x));
+      if (2 * q + 1 < l) om[(2 * q + 1) * kS + kk] = to_bf16((float)rne_bf16(z.y));
+    }
+    __syncthreads();
+    // split A into bfloat16 terms: hi = bf16(a), lo = bf16(a - hi), lo2 = ...
+    bf16x8 bt[3][TN];
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      float rem[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rem[e] = (float)av[u][e];
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const __bf16 x = to_bf16(rem[e]);
+          bt[h][u][e] = x;
+          rem[e] = rem[e] - (float)x;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(om + (16 * t + r16) * kS + 8 * g);
+#pragma unroll
+      for (int u = 0; u < TN; ++u) {
+        acc[t][u] = mfma_bf16(a, bt[0][u], acc[t][u]);
+        if (terms > 1) acc[t][u] = mfma_bf16(a, bt[1][u], acc[t][u]);
+        if (terms > 2) acc[t][u] = mfma_bf16(a, bt[2][u], acc[t][u]);
+      }
+    }
+  }
+  float* dst = (bi.nsplit == 1) ? (Y + bi.y_off)
+                                : (part + bi.part_off + (int64_t)it.split * ncols * l);
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int col = cwave + 16 * u + r16;
+    if (col < clo || col >= chi) continue;
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + 4 * g + v;
+        if (row < l) dst[(int64_t)col * l + row] = acc[t][u][v];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split-K reduction: Y_b(:, j) = sum over splits s (ascending) of the
+// partials, for the blocks listed in `split_blocks`, columns [j0, j1).
+// grid = (ceil(l*maxn / 256), number of split blocks)
+// ---------------------------------------------------------------------------
+template <typename TY>
+__global__ __launch_bounds__(256) void sketch_reduce_kernel(const BlkInfo* __restrict__ blks,
+                                                            const int32_t* __restrict__ split_blocks,
+                                                            int l, int j0, int j1,
+                                                            TY* __restrict__ Y,
+                                                            const TY* __restrict__ part) {
+  const int b = split_blocks[blockIdx.y];
+  const BlkInfo bi = blks[b];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)l * bi.n;
+  if (e >= total) return;
+  const int col = (int)(e / l);
+  if (col < j0 || col >= j1) return;
+  const TY* p = part + bi.part_off + e;
+  TY s = 0;
+  for (int sp = 0; sp < bi.nsplit; ++sp) s += p[(int64_t)sp * total];
+  Y[bi.y_off + e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Column selection: rank-k pivoted modified Gram-Schmidt on Y_b (l x n_b).
+// One workgroup per block; thread t owns columns t + c*blockDim (c < CPT),
+// each an LMAX-double register column (rows >= l are zero).  Per step:
+// block argmax of the residual norms (ties -> lowest index), the owner
+// writes q = w_p / ||w_p|| to LDS, every other column is orthogonalised and
+// its norm recomputed; optional tolerance stop on the residual Frobenius
+// norm.  Writes S, k, status, and R (row s = step s) for the coefficients.
+// ---------------------------------------------------------------------------
+template <typename TY, int LMAX, int CPT>
+__global__ __launch_bounds__(512) void select_kernel(
+    const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor,
+    const TY* __restrict__ Y, double* __restrict__ R, int32_t* __restrict__ S_ws,
+    int32_t* __restrict__ k_ws, int32_t* __restrict__ st_ws) {
+  __shared__ double q_lds[LMAX];
+  __shared__ double red_v[16];
+  __shared__ int red_i[16];
+  __shared__ double bc_v;
+  __shared__ double bc_rss;
+  __shared__ int bc_i;
+  const int b = blockIdx.x;
+  const BlkInfo bi = blks[b];
+  const int n = bi.n;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+  const TY* __restrict__ Yb = Y + bi.y_off;
+  double* __restrict__ Rb = R + bi.r_off;
+
+  double w[CPT][LMAX];
+  double nu[CPT];
+  bool live[CPT];     // column exists and is not selected yet
+  int bad = 0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int j = tid + c * nthr;
+    live[c] = j < n;
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < LMAX; ++r) {
+      double v = 0.0;
+      if (live[c] && r < l) v = (double)Yb[(int64_t)j * l + r];
+      if (!isfinite(v)) bad = 1;
+      w[c][r] = v;
+      acc += v * v;
+    }
+    nu[c] = live[c] ? acc : 0.0;
+  }
+  for (int e = tid; e < LMAX; e += nthr) q_lds[e] = 0.0;
+  const int any_bad = __syncthreads_or(bad);
+
+  // Frobenius norm^2 and largest column norm^2 of the sketch (fixed order)
+  double fs = 0.0, fm = 0.0;
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    fs += nu[c];
+    fm = fmax(fm, nu[c]);
+  }
+  fs = wave_sum(fs);
+  fm = wave_max(fm);
+  if (lane == 0) {
+    red_v[wave] = fs;
+    red_i[wave] = 0;
+  }
+  __syncthreads();
+  double F2 = 0.0;
+  for (int v = 0; v < nwaves; ++v) F2 += red_v[v];
+  __syncthreads();
+  if (lane == 0) red_v[wave] = fm;
+  __syncthreads();
+  double nu0max = 0.0;
+  for (int v = 0; v < nwaves; ++v) nu0max = fmax(nu0max, red_v[v]);
+  __syncthreads();
+
+  int kcap = k_max;
+  if (kcap > l) kcap = l;
+  if (kcap > n) kcap = n;
+  int status = 0, taken = 0;
+  if (any_bad) {
+    status = 2;   // SPID_BLOCK_NONFINITE
+  } else {
+    for (int s = 0; s < kcap; ++s) {
+      // ---- pivot: argmax of live residual norms
+      double bv = -1.0;
+      int bj = 0x7fffffff;
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int j = tid + c * nthr;
+        if (live[c] && (nu[c] > bv || (nu[c] == bv && j < bj))) {
+          bv = nu[c];
+          bj = j;
+        }
+      }
+      wave_argmax(bv, bj);
+      if (lane == 0) {
+        red_v[wave] = bv;
+        red_i[wave] = bj;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double v = red_v[0];
+        int i = red_i[0];
+        for (int x = 1; x < nwaves; ++x)
+          if (red_v[x] > v || (red_v[x] == v && red_i[x] < i)) {
+            v = red_v[x];
+            i = red_i[x];
+          }
+        bc_v = v;
+        bc_i = i;
+      }
+      __syncthreads();
+      const double best = bc_v;
+      const int p = bc_i;
+      if (!(best > 0.0)) {
+        status = 1;   // SPID_BLOCK_RANK_DEFICIENT
+        break;
+      }
+      if (rank_floor > 0.0 && best <= rank_floor * rank_floor * nu0max) {
+        status = 1;
+        break;
+      }
+      // ---- the owner publishes its column and its norm; q = w_p / r_ss is
+      // then formed in LDS, one row per thread
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        if (tid + c * nthr == p) {
+          double pn = 0.0;
+#pragma unroll
+          for (int r = 0; r < LMAX; ++r) {
+            pn += w[c][r] * w[c][r];
+            q_lds[r] = w[c][r];
+          }
+          const double rss = sqrt(pn);
+          bc_rss = rss;
+          Rb[(int64_t)s * n + p] = rss;
+          live[c] = false;
+          nu[c] = 0.0;
+        }
+      }
+      if (tid == 0) S_ws[(int64_t)b * k_max + s] = p;
+      __syncthreads();
+      if (tid < LMAX) q_lds[tid] = q_lds[tid] / bc_rss;
+      __syncthreads();
+      taken = s + 1;
+      // ---- orthogonalise the live columns against q, recompute norms.  The
+      // update runs on every register column with d = 0 where the column is
+      // not live (w - 0*q = w exactly), so no predicated copy of w is needed.
+      double rest = 0.0;
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int j = tid + c * nthr;
+        // q is read from LDS 8 rows at a time (scheduling fences keep the
+        // compiler from holding all LMAX q values in registers)
+        double d = 0.0;
+#pragma unroll
+        for (int r0 = 0; r0 < LMAX; r0 += 8) {
+#pragma unroll
+          for (int r = r0; r < r0 + 8; ++r) d += q_lds[r] * w[c][r];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (live[c]) Rb[(int64_t)s * n + j] = d;
+        d = live[c] ? d : 0.0;
+        // second read of q: relaxed atomic LDS loads are not merged with the
+        // first ones, so q is never held whole in registers
+        double a2 = 0.0;
+#pragma unroll
+        for (int r0 = 0; r0 < LMAX; r0 += 8) {
+#pragma unroll
+          for (int r = r0; r < r0 + 8; ++r) {
+            const double qr =
+                __hip_atomic_load(q_lds + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            w[c][r] -= d * qr;
+            a2 += w[c][r] * w[c][r];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        nu[c] = live[c] ? a2 : 0.0;
+        rest += nu[c];
+      }
+      if (tol > 0.0) {
+        rest = wave_sum(rest);
+        if (lane == 0) red_v[wave] = rest;
+        __syncthreads();
+        double tot = 0.0;
+        for (int v = 0; v < nwaves; ++v) tot += red_v[v];
+        if (sqrt(tot) <= tol * sqrt(F2)) {
+          __syncthreads();
+          break;
+        }
+        if (s == kcap - 1) status = 3;   // SPID_BLOCK_TOL_NOT_MET
+      }
+      __syncthreads();   // q_lds and red_v reused by the next step
+    }
+  }
+  if (tid == 0) {
+    k_ws[b] = taken;
+    st_ws[b] = status;
+  }
+  for (int s = taken + tid; s < k_max; s += nthr) S_ws[(int64_t)b * k_max + s] = -1;
+}
+
+// Copy per-block selection results to the caller's arrays.
+__global__ void select_export_kernel(int nblocks, int k_max, const int32_t* __restrict__ S_ws,
+                                     const int32_t* __restrict__ k_ws,
+                                     const int32_t* __restrict__ st_ws, int32_t* d_k,
+                                     int32_t* d_S, int32_t* d_status) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d_S && e < (int64_t)nblocks * k_max) d_S[e] = S_ws[e];
+  if (e < nblocks) {
+    if (d_k) d_k[e] = k_ws[e];
+    if (d_status) d_status[e] = st_ws[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coefficients: one wave per block.  R11 (k x k, R11[s][t] = R(s, S[t])) in
+// LDS; lane handles columns j = lane + 64 c; back-substitution with the
+// partial solution x in LDS (x[t][lane]).  Identity columns are exact.
+// Dynamic LDS: (k_max*k_max + 64*k_max) doubles.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void coeffs_kernel(const BlkInfo* __restrict__ blks, int k_max,
+                                                    const double* __restrict__ R,
+                                                    const int32_t* __restrict__ S_ws,
+                                                    const int32_t* __restrict__ k_ws,
+                                                    double* __restrict__ P) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x;
+  const BlkInfo bi = blks[b];
+  const int n = bi.n;
+  const int k = k_ws[b];
+  const int lane = threadIdx.x;
+  const int32_t* S = S_ws + (int64_t)b * k_max;
+  const double* Rb = R + bi.r_off;
+  double* Pb = P + bi.p_off;
+  double* r11 = sm;                    // [k][k]
+  double* x = sm + k_max * k_max;      // [k][64]
+  for (int e = lane; e < k * k; e += 64) {
+    const int s = e / k, t = e - s * k;
+    r11[e] = (t >= s) ? Rb[(int64_t)s * n + S[t]] : 0.0;
+  }
+  __syncthreads();
+  for (int j0 = 0; j0 < n; j0 += 64) {
+    const int j = j0 + lane;
+    bool sel = false;
+    int pos = -1;
+    if (j < n) {
+      for (int t = 0; t < k; ++t)
+        if (S[t] == j) {
+          sel = true;
+          pos = t;
+        }
+    }
+    if (j < n && !sel) {
+      for (int s = k - 1; s >= 0; --s) {
+        double acc = Rb[(int64_t)s * n + j];
+        for (int t = s + 1; t < k; ++t) acc -= r11[s * k + t] * x[t * 64 + lane];
+        x[s * 64 + lane] = acc / r11[s * k + s];
+      }
+    }
+    if (j < n) {
+      double* pc = Pb + (int64_t)j * k_max;
+      for (int t = 0; t < k_max; ++t) {
+        double v = 0.0;
+        if (t < k) v = sel ? (t == pos ? 1.0 : 0.0) : x[t * 64 + lane];
+        pc[t] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction error, one row per thread (256-row tiles): the thread keeps
+// its row of the skeleton A(i, S) in registers, streams the non-skeleton
+// columns j (coalesced down the column), forms A(i,S) P(:,j) in double
+// precision with P read through uniform (scalar) loads, and accumulates the
+// squared residual and the squared entries.  Skeleton columns have residual
+// exactly zero.  Per-tile partial sums go to `part` (2 doubles per item).
+// KMAX bounds k_max.
+// ---------------------------------------------------------------------------
+template <typename TA, int KMAX>
+__global__ __launch_bounds__(256) void recon_kernel(
+    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max,
+    const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
+    const double* __restrict__ P, TA* __restrict__ skel, double* __restrict__ part) {
+  __shared__ double red[8];
+  __shared__ unsigned char is_sel[1024 + 64];
+  const RcItem it = items[blockIdx.x];
+  const BlkInfo bi = blks[it.blk];
+  const int n = bi.n;
+  const int k = k_ws[it.blk];
+  const int32_t* S = S_ws + (int64_t)it.blk * k_max;
+  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
+  const double* __restrict__ Pb = P + bi.p_off;
+  const int tid = threadIdx.x;
+  const int64_t i = it.i0 + tid;
+  const bool row_ok = i < bi.m;
+  for (int j = tid; j < n; j += 256) is_sel[j] = 0;
+  __syncthreads();
+  if (tid < k) is_sel[S[tid]] = 1;
+  __syncthreads();
+
+  double as[KMAX];
+  double a2 = 0.0, e2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t) {
+    double v = 0.0;
+    if (t < k && row_ok) v = (double)A[(int64_t)S[t] * bi.lda + i];
+    as[t] = v;
+    a2 += v * v;
+    if (skel && t < k && row_ok) skel[bi.sk_off + (int64_t)t * bi.m + i] = (TA)v;
+  }
+  for (int j = 0; j < n; ++j) {
+    if (is_sel[j]) continue;
+    const double a = row_ok ? (double)A[(int64_t)j * bi.lda + i] : 0.0;
+    const double* pc = Pb + (int64_t)j * k_max;
+    double approx = 0.0;
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t)
+      if (t < k) approx += as[t] * pc[t];
+    const double r = a - approx;
+    e2 += r * r;
+    a2 += a * a;
+  }
+  // workgroup sums (fixed order)
+  const int lane = tid & 63, wave = tid >> 6;
+  e2 = wave_sum(e2);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    red[wave] = e2;
+    red[4 + wave] = a2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    part[2 * (int64_t)blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    part[2 * (int64_t)blockIdx.x + 1] = red[4] + red[5] + red[6] + red[7];
+  }
+}
+
+// Per-block sums of the row-tile partials, items of block b are the
+// contiguous range [first[b], first[b+1]).
+__global__ void recon_reduce_kernel(int nblocks, const int64_t* __restrict__ first,
+                                    const double* __restrict__ part, double* __restrict__ err2,
+                                    double* __restrict__ nrm2) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblocks) return;
+  double e = 0.0, a = 0.0;
+  for (int64_t x = first[b]; x < first[b + 1]; ++x) {
+    e += part[2 * x];
+    a += part[2 * x + 1];
+  }
+  err2[b] = e;
+  nrm2[b] = a;
+}
+
+// Widen the sketch to FP64 (diagnostics).
+template <typename TY>
+__global__ void copy_sketch_kernel(int64_t total, const TY* __restrict__ Y, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < total) out[e] = (double)Y[e];
+}
+
+}  // namespace spid
