@@ -34,7 +34,7 @@ spid_status fail(spid_status st, const char* fmt, ...) {
 constexpr int kMaxL = 128;
 constexpr int kMaxK = 96;
 constexpr int kMaxN = 1024;
-constexpr int kRcRows = 256;
+
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -43,10 +43,13 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Shape {
   int MT;        // 16-row MFMA tiles covering l
   int TN;        // 16-column tiles per wave in the sketch
+  int NW;        // waves per sketch workgroup (columns per workgroup = 16 * NW * TN)
   int LMAX;      // register rows of a sketch column in the selection
   int CPT;       // sketch columns per thread in the selection
   int sel_thr;   // selection workgroup size
   int KMAX;      // register skeleton width in the error pass
+  int KS;        // k-steps of 4 selected columns in the matrix-core error pass
+  int RC_ROWS;   // rows per error-pass work item
 };
 
 int pick_mt(int l) {
@@ -128,9 +131,13 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
   sh.MT = pick_mt(d->l);
   // columns per workgroup tile: 64*TN
   if (p.ydt == 0) {
-    sh.TN = p.max_n >= 256 ? 4 : (p.max_n >= 128 ? 2 : 1);
+    // FP64 MFMA needs two waves per SIMD: 8 waves of 1-2 column tiles
+    sh.TN = (p.max_n >= 256 && sh.MT <= 4) ? 2 : 1;
+    sh.NW = p.max_n >= 128 ? 8 : 4;
   } else {
-    sh.TN = p.max_n >= 256 ? 4 : (p.max_n >= 128 ? 2 : 1);
+    // FP32 accumulators are half the size: up to 512 columns per workgroup
+    sh.TN = p.max_n >= 512 ? 8 : (p.max_n >= 256 ? 4 : (p.max_n >= 128 ? 2 : 1));
+    sh.NW = 4;
   }
   sh.LMAX = pick_lmax(d->l);
   sh.CPT = (p.max_n > 512) ? 2 : 1;
@@ -142,9 +149,21 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
     return fail(SPID_EINVAL, "l=%d with n up to %d exceeds the selection register budget", d->l,
                 p.max_n);
   sh.KMAX = pick_kmax(d->k_max);
+  {
+    const int ks = (d->k_max + 3) / 4;
+    const int opts[] = {1, 2, 4, 8, 12, 16, 24};
+    sh.KS = 24;
+    for (int o : opts)
+      if (ks <= o) {
+        sh.KS = o;
+        break;
+      }
+    const int mtr = sh.KS <= 8 ? 4 : (sh.KS <= 16 ? 2 : 1);
+    sh.RC_ROWS = 4 * 16 * mtr;   // 4 waves x MTR 16-row tiles
+  }
 
   // sketch work items: column tiles x K splits
-  const int tile_cols = 64 * sh.TN;
+  const int tile_cols = 16 * sh.NW * sh.TN;
   int64_t base_items = 0;
   for (int b = 0; b < nb; ++b) base_items += (d->h_n[b] + tile_cols - 1) / tile_cols;
   const int64_t target = 2048;
@@ -197,7 +216,7 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
         p.items.push_back(it);
       }
     p.rc_first.push_back((int64_t)p.rc.size());
-    for (int64_t i0 = 0; i0 < m; i0 += kRcRows) {
+    for (int64_t i0 = 0; i0 < m; i0 += sh.RC_ROWS) {
       RcItem r{};
       r.blk = b;
       r.i0 = i0;
@@ -261,16 +280,24 @@ void launch_sketch_t(spid_ctx* c, int j0, int j1, hipStream_t s) {
   const Plan& p = c->plan;
   dim3 grid((unsigned)p.items.size());
   if (p.ydt == 0) {
-    hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN>), grid, dim3(kSkThreads), 0, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->at<double>(p.off_Y),
-                       c->at<double>(p.off_part));
-  } else {
-    hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN>), grid, dim3(kSkThreads), 0, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
-                       c->at<float>(p.off_Y), c->at<float>(p.off_part));
+    if constexpr (TN <= 2) {
+      if (p.sh.NW == 8)
+        hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN, 8>), grid, dim3(512), 0, s,
+                           c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                           c->desc.seed, c->desc.omega_per_block, j0, j1,
+                           c->at<double>(p.off_Y), c->at<double>(p.off_part));
+      else
+        hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN, 4>), grid, dim3(256), 0, s,
+                           c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                           c->desc.seed, c->desc.omega_per_block, j0, j1,
+                           c->at<double>(p.off_Y), c->at<double>(p.off_part));
+    }
+    return;
   }
+  hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, 4>), grid, dim3(256), 0, s,
+                     c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                     c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+                     c->at<float>(p.off_Y), c->at<float>(p.off_part));
 }
 
 template <typename TA, int MT>
@@ -278,7 +305,8 @@ void launch_sketch_mt(spid_ctx* c, int j0, int j1, hipStream_t s) {
   switch (c->plan.sh.TN) {
     case 1: launch_sketch_t<TA, MT, 1>(c, j0, j1, s); break;
     case 2: launch_sketch_t<TA, MT, 2>(c, j0, j1, s); break;
-    default: launch_sketch_t<TA, MT, 4>(c, j0, j1, s); break;
+    case 4: launch_sketch_t<TA, MT, 4>(c, j0, j1, s); break;
+    default: launch_sketch_t<TA, MT, 8>(c, j0, j1, s); break;
   }
 }
 
@@ -326,25 +354,28 @@ void launch_select_y(spid_ctx* c, hipStream_t s) {
   }
 }
 
-// ---- reconstruction dispatch
-template <typename TA, int KMAX>
+// ---- reconstruction dispatch (matrix-core kernel)
+template <typename TA, int KS, int MTR>
 void launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   const Plan& p = c->plan;
-  hipLaunchKernelGGL((recon_kernel<TA, KMAX>), dim3((unsigned)p.rc.size()), dim3(kRcRows), 0, s,
-                     c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.k_max,
-                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
-                     static_cast<TA*>(skel), c->at<double>(p.off_rcpart));
+  const size_t lds = sizeof(double) * kRcCols * 4 * KS;
+  hipLaunchKernelGGL((recon_mfma_kernel<TA, KS, MTR>), dim3((unsigned)p.rc.size()),
+                     dim3(kRcThreads), lds, s, c->at<BlkInfo>(p.off_blk),
+                     c->at<RcItem>(p.off_rc), c->desc.k_max, c->at<int32_t>(p.off_S),
+                     c->at<int32_t>(p.off_k), P, static_cast<TA*>(skel),
+                     c->at<double>(p.off_rcpart));
 }
 
 template <typename TA>
 void launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
-  switch (c->plan.sh.KMAX) {
-    case 8: launch_recon_t<TA, 8>(c, P, skel, s); break;
-    case 16: launch_recon_t<TA, 16>(c, P, skel, s); break;
-    case 32: launch_recon_t<TA, 32>(c, P, skel, s); break;
-    case 48: launch_recon_t<TA, 48>(c, P, skel, s); break;
-    case 64: launch_recon_t<TA, 64>(c, P, skel, s); break;
-    default: launch_recon_t<TA, 96>(c, P, skel, s); break;
+  switch (c->plan.sh.KS) {
+    case 1: launch_recon_t<TA, 1, 4>(c, P, skel, s); break;
+    case 2: launch_recon_t<TA, 2, 4>(c, P, skel, s); break;
+    case 4: launch_recon_t<TA, 4, 4>(c, P, skel, s); break;
+    case 8: launch_recon_t<TA, 8, 4>(c, P, skel, s); break;
+    case 12: launch_recon_t<TA, 12, 2>(c, P, skel, s); break;
+    case 16: launch_recon_t<TA, 16, 2>(c, P, skel, s); break;
+    default: launch_recon_t<TA, 24, 1>(c, P, skel, s); break;
   }
 }
 

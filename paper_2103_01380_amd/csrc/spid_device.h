@@ -58,9 +58,11 @@ __device__ __forceinline__ double2 omega_pair(uint64_t seed, uint32_t bkey, uint
 // bits), result as a double.  Valid for zero and for normal values inside
 // the bfloat16 exponent range (the normals of the sketch matrix).
 __device__ __forceinline__ double rne_bf16(double x) {
+  // keep the top 7 of the 52 stored fraction bits: add half an ulp minus one
+  // plus the kept lsb (ties to even), then clear the 45 dropped bits
   uint64_t u = (uint64_t)__double_as_longlong(x);
   const uint64_t drop = (1ull << 45) - 1ull;
-  u += drop + ((u >> 45) & 1ull);
+  u += ((1ull << 44) - 1ull) + ((u >> 45) & 1ull);
   u &= ~drop;
   return __longlong_as_double((long long)u);
 }
@@ -74,7 +76,7 @@ __device__ __forceinline__ double rne_e4m3(double x) {
   } else {
     uint64_t u = (uint64_t)__double_as_longlong(x);
     const uint64_t drop = (1ull << 49) - 1ull;
-    u += drop + ((u >> 49) & 1ull);
+    u += ((1ull << 48) - 1ull) + ((u >> 49) & 1ull);
     u &= ~drop;
     r = __longlong_as_double((long long)u);
   }

@@ -7,7 +7,8 @@
 //                     workgroup per block, one sketch column per lane held in
 //                     registers, pivot search by wave + LDS reduction.
 //   coeffs_kernel     back-substitution R11 x = R12(:, j), identity columns.
-//   recon_kernel      streaming residual ||A - A(:,S) P||^2 per row tile.
+//   recon_mfma_kernel streaming residual ||A - A(:,S) P||^2 per row tile, the
+//                     product A(:,S) P on the FP64 matrix cores.
 //   recon_reduce      fixed-order per-block sums of the row-tile partials.
 #pragma once
 
@@ -84,18 +85,36 @@ __device__ __forceinline__ void load8(const TA* __restrict__ base, int64_t lda, 
 }
 
 // ---------------------------------------------------------------------------
+// Omega chunk generation into LDS: rows 0..l-1 of columns k0..k0+31 of the
+// sketch matrix (pair q -> rows 2q, 2q+1).  Rows l..MT*16-1 stay zero.
+// ---------------------------------------------------------------------------
+template <typename TO, int STRIDE, int NTHR, typename CVT>
+__device__ __forceinline__ void gen_omega_chunk(TO* __restrict__ om, int l, uint64_t seed,
+                                                uint32_t bkey, int64_t k0, int tid, CVT cvt) {
+  const int npairs = (l + 1) >> 1;
+  for (int e = tid; e < npairs * kKC; e += NTHR) {
+    const int q = e / kKC, kk = e - q * kKC;
+    const double2 z = omega_pair(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q);
+    om[(2 * q) * STRIDE + kk] = cvt(z.x);
+    if (2 * q + 1 < l) om[(2 * q + 1) * STRIDE + kk] = cvt(z.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Sketch, double precision: Y = Omega A on v_mfma_f64_16x16x4.
-// Workgroup = 4 waves; wave w owns columns c0 + 16*TN*w + [0, 16*TN); every
-// wave covers all MT*16 sketch rows.  Per 32-row chunk: Omega (MT*16 x 32) is
-// generated into LDS by the whole workgroup, each lane loads rows
+// Workgroup = NW waves; wave w owns columns c0 + 16*TN*w + [0, 16*TN); every
+// wave covers all MT*16 sketch rows.  Per 32-row chunk each lane holds rows
 // 8g..8g+7 (g = lane/16) of one column per 16-column tile, and eight MFMA
 // k-steps consume them (step s pairs A row 8g+s with Omega column 8g+s).
+// Software pipeline: while the MFMAs of chunk c run, the A loads of chunk c+1
+// are in flight and the workgroup generates Omega of chunk c+1 into the other
+// LDS buffer; one barrier per chunk.
 // ---------------------------------------------------------------------------
-template <typename TA, int MT, int TN>
-__global__ __launch_bounds__(kSkThreads) void sketch_f64_kernel(
+template <typename TA, int MT, int TN, int NW>
+__global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
     int omega_per_block, int j0, int j1, double* __restrict__ Y, double* __restrict__ part) {
-  __shared__ double om[MT * 16 * kOmStride];
+  __shared__ double om[2][MT * 16 * kOmStride];
   const SkItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
   const int tid = threadIdx.x;
@@ -105,13 +124,13 @@ __global__ __launch_bounds__(kSkThreads) void sketch_f64_kernel(
   const int cwave = it.c0 + wave * 16 * TN;
   // window of columns this call updates
   const int clo = max(j0, 0), chi = min(j1, ncols);
-  if (it.c0 >= chi || it.c0 + 64 * TN <= clo) return;   // whole tile outside (uniform)
+  if (it.c0 >= chi || it.c0 + NW * 16 * TN <= clo) return;   // whole tile outside (uniform)
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
   const TA* __restrict__ A = static_cast<const TA*>(bi.A);
   const bool vec = bi.vec_ok != 0;
+  auto ident = [](double x) { return x; };
 
-  // rows l .. MT*16-1 of the Omega tile stay zero
-  for (int e = tid; e < MT * 16 * kOmStride; e += kSkThreads) om[e] = 0.0;
+  for (int e = tid; e < 2 * MT * 16 * kOmStride; e += 64 * NW) (&om[0][0])[e] = 0.0;
 
   f64x4 acc[MT][TN];
 #pragma unroll
@@ -119,34 +138,36 @@ __global__ __launch_bounds__(kSkThreads) void sketch_f64_kernel(
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[t][u] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  const int npairs = (l + 1) >> 1;
-  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC) {
-    // 1. issue this lane's A loads (column tile u, rows k0+8g .. +7)
-    double av[TN][8];
+  auto load_chunk = [&](int64_t k0, double (&av)[TN][8]) {
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
       const int col = cwave + 16 * u + r16;
-      if (col >= clo && col < chi) {
+      if (col >= clo && col < chi && k0 < it.r1) {
         load8<TA>(A, bi.lda, col, k0 + 8 * g, it.r1, vec, av[u]);
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) av[u][e] = 0.0;
       }
     }
-    __syncthreads();   // previous chunk's MFMAs finished reading om
-    // 2. Omega chunk into LDS: pair q covers rows 2q, 2q+1
-    for (int e = tid; e < npairs * kKC; e += kSkThreads) {
-      const int q = e / kKC, kk = e - q * kKC;
-      const double2 z = omega_pair(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q);
-      om[(2 * q) * kOmStride + kk] = z.x;
-      if (2 * q + 1 < l) om[(2 * q + 1) * kOmStride + kk] = z.y;
+  };
+
+  double av[TN][8], an[TN][8];
+  load_chunk(it.r0, av);
+  __syncthreads();   // zero fill done before generation writes
+  gen_omega_chunk<double, kOmStride, 64 * NW>(om[0], l, seed, bkey, it.r0, tid, ident);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC) {
+    const int64_t k1 = k0 + kKC;
+    const bool more = k1 < it.r1;
+    if (more) {
+      load_chunk(k1, an);
+      gen_omega_chunk<double, kOmStride, 64 * NW>(om[buf ^ 1], l, seed, bkey, k1, tid, ident);
     }
-    __syncthreads();
-    // 3. MFMA: eight k-steps of 4
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       double ov[8];
-      const double* orow = om + (16 * t + r16) * kOmStride + 8 * g;
+      const double* orow = om[buf] + (16 * t + r16) * kOmStride + 8 * g;
 #pragma unroll
       for (int s = 0; s < 8; ++s) ov[s] = orow[s];
 #pragma unroll
@@ -154,6 +175,14 @@ __global__ __launch_bounds__(kSkThreads) void sketch_f64_kernel(
 #pragma unroll
         for (int u = 0; u < TN; ++u) acc[t][u] = mfma_f64(ov[s], av[u][s], acc[t][u]);
     }
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < TN; ++u)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[u][e] = an[u][e];
+    }
+    buf ^= 1;
   }
   // epilogue: lane holds rows 16t + g + 4v of column cwave + 16u + r16
   double* dst;
@@ -176,19 +205,44 @@ __global__ __launch_bounds__(kSkThreads) void sketch_f64_kernel(
   }
 }
 
+// Load 8 consecutive rows [row, row+8) of column `col` as floats (rows at or
+// past `rend` read as zero).
+template <typename TA>
+__device__ __forceinline__ void load8f(const TA* __restrict__ base, int64_t lda, int64_t col,
+                                       int64_t row, int64_t rend, bool vec, float out[8]) {
+  const TA* p = base + col * lda + row;
+  if constexpr (sizeof(TA) == 4) {
+    if (vec && row + 8 <= rend) {
+      const f32x4* q = reinterpret_cast<const f32x4*>(p);
+      const f32x4 v0 = __builtin_nontemporal_load(q);
+      const f32x4 v1 = __builtin_nontemporal_load(q + 1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        out[e] = v0[e];
+        out[4 + e] = v1[e];
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) out[e] = (row + e < rend) ? (float)p[e] : 0.0f;
+}
+
 // ---------------------------------------------------------------------------
-// Sketch, bfloat16 (FP32 accumulation): Omega rounded to bfloat16 in LDS; A
-// split into `terms` bfloat16 terms in registers; v_mfma_f32_16x16x32_bf16.
-// Lane (g, r16) supplies rows 8g..8g+7 of its column as the 8 k-values of one
-// MFMA; Omega row 16t+r16 supplies the same 8 k-values.
+// Sketch, bfloat16 (FP32 accumulation): Omega rounded to nearest-even
+// bfloat16 in LDS; A split into `terms` bfloat16 terms in registers
+// (hi = bf16(a), lo = bf16(a - hi), lo2 = bf16(a - hi - lo));
+// v_mfma_f32_16x16x32_bf16.  Lane (g, r16) supplies rows 8g..8g+7 of its
+// column as the 8 k-values of one MFMA; Omega row 16t+r16 supplies the same 8
+// k-values.  Same software pipeline as the double-precision kernel.
 // ---------------------------------------------------------------------------
-template <typename TA, int MT, int TN>
-__global__ __launch_bounds__(kSkThreads) void sketch_bf16_kernel(
+template <typename TA, int MT, int TN, int NW>
+__global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
     int omega_per_block, int j0, int j1, int terms, float* __restrict__ Y,
     float* __restrict__ part) {
   constexpr int kS = kKC + 8;   // LDS row stride in bf16 elements (80 bytes)
-  __shared__ __attribute__((aligned(16))) __bf16 om[MT * 16 * kS];
+  __shared__ __attribute__((aligned(16))) __bf16 om[2][MT * 16 * kS];
   const SkItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
   const int tid = threadIdx.x;
@@ -197,12 +251,13 @@ __global__ __launch_bounds__(kSkThreads) void sketch_bf16_kernel(
   const int ncols = bi.n;
   const int cwave = it.c0 + wave * 16 * TN;
   const int clo = max(j0, 0), chi = min(j1, ncols);
-  if (it.c0 >= chi || it.c0 + 64 * TN <= clo) return;
+  if (it.c0 >= chi || it.c0 + NW * 16 * TN <= clo) return;
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
   const TA* __restrict__ A = static_cast<const TA*>(bi.A);
   const bool vec = bi.vec_ok != 0;
+  auto to_bf = [](double x) { return to_bf16((float)rne_bf16(x)); };
 
-  for (int e = tid; e < MT * 16 * kS; e += kSkThreads) om[e] = (__bf16)0.0f;
+  for (int e = tid; e < 2 * MT * 16 * kS; e += 64 * NW) (&om[0][0])[e] = (__bf16)0.0f;
 
   f32x4 acc[MT][TN];
 #pragma unroll
@@ -210,54 +265,61 @@ __global__ __launch_bounds__(kSkThreads) void sketch_bf16_kernel(
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const int npairs = (l + 1) >> 1;
-  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC) {
-    double av[TN][8];
+  auto load_chunk = [&](int64_t k0, float (&av)[TN][8]) {
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
       const int col = cwave + 16 * u + r16;
-      if (col >= clo && col < chi) {
-        load8<TA>(A, bi.lda, col, k0 + 8 * g, it.r1, vec, av[u]);
+      if (col >= clo && col < chi && k0 < it.r1) {
+        load8f<TA>(A, bi.lda, col, k0 + 8 * g, it.r1, vec, av[u]);
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) av[u][e] = 0.0;
+        for (int e = 0; e < 8; ++e) av[u][e] = 0.0f;
       }
     }
-    __syncthreads();
-    for (int e = tid; e < npairs * kKC; e += kSkThreads) {
-      const int q = e / kKC, kk = e - q * kKC;
-      const double2 z = omega_pair(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q);
-      om[(2 * q) * kS + kk] = to_bf16((float)rne_bf16(z.x));
-      if (2 * q + 1 < l) om[(2 * q + 1) * kS + kk] = to_bf16((float)rne_bf16(z.y));
+  };
+
+  float av[TN][8], an[TN][8];
+  load_chunk(it.r0, av);
+  __syncthreads();
+  gen_omega_chunk<__bf16, kS, 64 * NW>(om[0], l, seed, bkey, it.r0, tid, to_bf);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC) {
+    const int64_t k1 = k0 + kKC;
+    const bool more = k1 < it.r1;
+    if (more) {
+      load_chunk(k1, an);
+      gen_omega_chunk<__bf16, kS, 64 * NW>(om[buf ^ 1], l, seed, bkey, k1, tid, to_bf);
     }
-    __syncthreads();
-    // split A into bfloat16 terms: hi = bf16(a), lo = bf16(a - hi), lo2 = ...
-    bf16x8 bt[3][TN];
+    bf16x8 oa[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+      oa[t] = *reinterpret_cast<const bf16x8*>(om[buf] + (16 * t + r16) * kS + 8 * g);
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
       float rem[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rem[e] = (float)av[u][e];
-#pragma unroll
-      for (int h = 0; h < 3; ++h) {
+      for (int e = 0; e < 8; ++e) rem[e] = av[u][e];
+      for (int h = 0; h < terms; ++h) {
+        bf16x8 bt;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const __bf16 x = to_bf16(rem[e]);
-          bt[h][u][e] = x;
+          bt[e] = x;
           rem[e] = rem[e] - (float)x;
         }
+#pragma unroll
+        for (int t = 0; t < MT; ++t) acc[t][u] = mfma_bf16(oa[t], bt, acc[t][u]);
       }
     }
+    __syncthreads();
+    if (more) {
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(om + (16 * t + r16) * kS + 8 * g);
+      for (int u = 0; u < TN; ++u)
 #pragma unroll
-      for (int u = 0; u < TN; ++u) {
-        acc[t][u] = mfma_bf16(a, bt[0][u], acc[t][u]);
-        if (terms > 1) acc[t][u] = mfma_bf16(a, bt[1][u], acc[t][u]);
-        if (terms > 2) acc[t][u] = mfma_bf16(a, bt[2][u], acc[t][u]);
-      }
+        for (int e = 0; e < 8; ++e) av[u][e] = an[u][e];
     }
+    buf ^= 1;
   }
   float* dst = (bi.nsplit == 1) ? (Y + bi.y_off)
                                 : (part + bi.part_off + (int64_t)it.split * ncols * l);
@@ -568,61 +630,146 @@ __global__ __launch_bounds__(64) void coeffs_kernel(const BlkInfo* __restrict__ 
   }
 }
 
+constexpr int kRcThreads = 256;
+constexpr int kRcCols = 64;
+
 // ---------------------------------------------------------------------------
-// Reconstruction error, one row per thread (256-row tiles): the thread keeps
-// its row of the skeleton A(i, S) in registers, streams the non-skeleton
-// columns j (coalesced down the column), forms A(i,S) P(:,j) in double
-// precision with P read through uniform (scalar) loads, and accumulates the
-// squared residual and the squared entries.  Skeleton columns have residual
-// exactly zero.  Per-tile partial sums go to `part` (2 doubles per item).
-// KMAX bounds k_max.
+// Reconstruction error on the matrix cores (double precision).
+// Ahat(rows, cols) = A(rows, S) P(:, cols) with v_mfma_f64_16x16x4: the
+// skeleton A(rows, S) is the A operand (16 rows x 4 selected columns per
+// k-step), P the B operand (4 x 16 columns), Ahat accumulates in D.  Rows
+// inside a 16-row tile are permuted so that lane (g, c) receives D rows
+// 4g..4g+3 (row = 4 (rho % 4) + rho / 4 for tile row rho): each lane then
+// loads 4 consecutive entries of column c for the residual (coalesced).
+// Work item = 64*MTR*... rows: a workgroup of 4 waves covers 4 * 16 * MTR
+// rows; every wave streams all non-skeleton columns 16 at a time, with the
+// coefficients of a 64-column chunk staged in LDS.  KS = k-steps (k_max / 4
+// rounded up) held in registers per 16-row tile.
 // ---------------------------------------------------------------------------
-template <typename TA, int KMAX>
-__global__ __launch_bounds__(256) void recon_kernel(
+template <typename TA, int KS, int MTR>
+__global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
     const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
     const double* __restrict__ P, TA* __restrict__ skel, double* __restrict__ part) {
+  extern __shared__ double p_lds[];   // [kRcCols][kp]
   __shared__ double red[8];
-  __shared__ unsigned char is_sel[1024 + 64];
+  __shared__ int cols[1024];
+  __shared__ unsigned char is_sel[1024];
+  __shared__ int wcount[4];
   const RcItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
   const int n = bi.n;
   const int k = k_ws[it.blk];
+  const int kp = 4 * KS;
   const int32_t* S = S_ws + (int64_t)it.blk * k_max;
   const TA* __restrict__ A = static_cast<const TA*>(bi.A);
   const double* __restrict__ Pb = P + bi.p_off;
-  const int tid = threadIdx.x;
-  const int64_t i = it.i0 + tid;
-  const bool row_ok = i < bi.m;
-  for (int j = tid; j < n; j += 256) is_sel[j] = 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  // 16-byte loads need aligned column starts and a 4-row aligned tile start
+  const bool vec = bi.vec_ok != 0 && (it.i0 % 4) == 0;
+
+  for (int j = tid; j < n; j += kRcThreads) is_sel[j] = 0;
   __syncthreads();
   if (tid < k) is_sel[S[tid]] = 1;
   __syncthreads();
+  int ncols = 0;
+  for (int base = 0; base < n; base += kRcThreads) {
+    const int j = base + tid;
+    const bool keep = j < n && !is_sel[j];
+    const uint64_t bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wave] = __popcll(bal);
+    __syncthreads();
+    int off = ncols;
+    for (int v = 0; v < wave; ++v) off += wcount[v];
+    if (keep) cols[off + before] = j;
+    int tot = 0;
+    for (int v = 0; v < 4; ++v) tot += wcount[v];
+    ncols += tot;
+    __syncthreads();
+  }
 
-  double as[KMAX];
+  // rows of this wave: tile mt covers rbase + 16 mt + [0,16)
+  const int64_t rbase = it.i0 + (int64_t)wave * 16 * MTR;
+  // A operand: lane supplies tile row rho = c16 -> actual row 4 (rho % 4) + rho / 4,
+  // k-slot g of step s -> selected column 4 s + g
+  const int arow = 4 * (c16 & 3) + (c16 >> 2);
+  double as[MTR][KS];
   double a2 = 0.0, e2 = 0.0;
 #pragma unroll
-  for (int t = 0; t < KMAX; ++t) {
-    double v = 0.0;
-    if (t < k && row_ok) v = (double)A[(int64_t)S[t] * bi.lda + i];
-    as[t] = v;
-    a2 += v * v;
-    if (skel && t < k && row_ok) skel[bi.sk_off + (int64_t)t * bi.m + i] = (TA)v;
-  }
-  for (int j = 0; j < n; ++j) {
-    if (is_sel[j]) continue;
-    const double a = row_ok ? (double)A[(int64_t)j * bi.lda + i] : 0.0;
-    const double* pc = Pb + (int64_t)j * k_max;
-    double approx = 0.0;
+  for (int mt = 0; mt < MTR; ++mt) {
+    const int64_t i = rbase + 16 * mt + arow;
 #pragma unroll
-    for (int t = 0; t < KMAX; ++t)
-      if (t < k) approx += as[t] * pc[t];
-    const double r = a - approx;
-    e2 += r * r;
-    a2 += a * a;
+    for (int s = 0; s < KS; ++s) {
+      const int t = 4 * s + g;
+      double v = 0.0;
+      if (t < k && i < bi.m) {
+        v = (double)A[(int64_t)S[t] * bi.lda + i];
+        if (skel) skel[bi.sk_off + (int64_t)t * bi.m + i] = (TA)v;
+      }
+      as[mt][s] = v;
+      a2 += v * v;
+    }
   }
-  // workgroup sums (fixed order)
-  const int lane = tid & 63, wave = tid >> 6;
+
+  for (int c0 = 0; c0 < ncols; c0 += kRcCols) {
+    const int cc = min(kRcCols, ncols - c0);
+    for (int e = tid; e < kRcCols * kp; e += kRcThreads) {
+      const int q = e / kp, t = e - q * kp;
+      p_lds[e] = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
+    }
+    __syncthreads();
+    for (int q0 = 0; q0 < cc; q0 += 16) {
+      const int q = q0 + c16;
+      const bool cok = q < cc;
+      const int64_t j = cok ? cols[c0 + q] : 0;
+      // residual operands: rows rbase + 16 mt + 4 g + v of column j
+      double av[MTR][4];
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt) {
+        const int64_t i0 = rbase + 16 * mt + 4 * g;
+        const TA* src = A + j * bi.lda + i0;
+        if (cok && vec && i0 + 4 <= bi.m) {
+          if constexpr (sizeof(TA) == 8) {
+            const f64x2 x0 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src));
+            const f64x2 x1 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src) + 1);
+            av[mt][0] = x0[0];
+            av[mt][1] = x0[1];
+            av[mt][2] = x1[0];
+            av[mt][3] = x1[1];
+          } else {
+            const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
+#pragma unroll
+            for (int v = 0; v < 4; ++v) av[mt][v] = (double)x[v];
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            av[mt][v] = (cok && i0 + v < bi.m) ? (double)src[v] : 0.0;
+        }
+      }
+      f64x4 acc[MTR];
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
+      const double* pc = p_lds + (q0 + c16) * kp + g;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const double pv = pc[4 * s];
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt) acc[mt] = mfma_f64(as[mt][s], pv, acc[mt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double r = av[mt][v] - acc[mt][v];
+          e2 += r * r;
+          a2 += av[mt][v] * av[mt][v];
+        }
+    }
+    __syncthreads();
+  }
   e2 = wave_sum(e2);
   a2 = wave_sum(a2);
   if (lane == 0) {

@@ -448,3 +448,32 @@ def tgv2d_u1(npts: int, n: int, T: float = 10.0, nu: float = 0.01, unstructured:
             f = np.sin(x1[sel]) * np.cos(x2[sel])
             out.append(np.asfortranarray(np.outer(f, np.exp(-2.0 * nu * t))))
     return out
+
+
+def turbulence_block_direct(w: Workload, b: int, modes: Modes | None = None,
+                            out_dtype=np.float32) -> np.ndarray:
+    """Block b of the turbulence-like workload evaluated directly from the mode sum
+    (no FFT), column-major m_b x n.  Modes sharing a frequency are summed first:
+    cos(k.x + phi - w t) = cos(k.x + phi) cos(w t) + sin(k.x + phi) sin(w t)."""
+    modes = modes or turbulence_modes(w.nmodes, w.kmax, w.data_seed)
+    N, B, E = w.N, w.B, w.edge
+    bx, by, bz = b % B, (b // B) % B, b // (B * B)
+    loc = np.arange(E)
+    zz, yy, xx = np.meshgrid(bz * E + loc, by * E + loc, bx * E + loc, indexing="ij")
+    pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1).astype(np.float64)
+    h = 2.0 * math.pi / N
+    arg = (pts * h) @ modes.kappa.T.astype(np.float64)              # [P, M]
+    amps, phases, offsets = _field_coeffs(modes)
+    om_u, inv = np.unique(np.round(modes.omega, 12), return_inverse=True)
+    t = w.dt * np.arange(w.n)
+    Ct = np.cos(np.outer(om_u, t))                                   # [U, n]
+    St = np.sin(np.outer(om_u, t))
+    out = np.empty((w.fields * E ** 3, w.n), dtype=np.float64)
+    for f in range(5):
+        th = arg + phases[f][None, :]
+        ind = np.zeros((len(inv), len(om_u)))
+        ind[np.arange(len(inv)), inv] = amps[f]
+        Gc = np.cos(th) @ ind                                        # [P, U]
+        Gs = np.sin(th) @ ind
+        out[f * E ** 3:(f + 1) * E ** 3] = offsets[f] + Gc @ Ct + Gs @ St
+    return np.asfortranarray(out.astype(out_dtype))
