@@ -47,9 +47,13 @@ struct Shape {
   int LMAX;      // register rows of a sketch column in the selection
   int CPT;       // sketch columns per thread in the selection
   int sel_thr;   // selection workgroup size
+  int sel_rr;    // 0: all-register selection; else register rows of the hybrid kernel
+  size_t sel_lds;  // dynamic LDS of the hybrid selection kernel
   int KMAX;      // register skeleton width in the error pass
   int KS;        // k-steps of 4 selected columns in the matrix-core error pass
   int RC_ROWS;   // rows per error-pass work item
+  int rc_bf16;   // 1: split-bfloat16 error pass (FP32 data, low-precision sketch)
+  int KS32;      // k-steps of 32 selected columns in the split-bfloat16 error pass
 };
 
 int pick_mt(int l) {
@@ -99,8 +103,9 @@ spid_status validate(const spid_desc* d) {
   if (!(d->rank_floor >= 0.0)) return fail(SPID_EINVAL, "rank_floor must be >= 0");
   if (d->a_dtype != SPID_A_F64 && d->a_dtype != SPID_A_F32)
     return fail(SPID_EINVAL, "a_dtype must be SPID_A_F64 or SPID_A_F32");
-  if (d->prec != SPID_SK_F64 && d->prec != SPID_SK_BF16)
-    return fail(SPID_EINVAL, "sketch precision %d is not supported by this build", d->prec);
+  if (d->prec != SPID_SK_F64 && d->prec != SPID_SK_BF16 && d->prec != SPID_SK_FP8E4M3)
+    return fail(SPID_EINVAL, "sketch precision must be SPID_SK_F64, _BF16 or _FP8E4M3 (got %d)",
+                d->prec);
   if (d->prec != SPID_SK_F64 && (d->lp_terms < 1 || d->lp_terms > 3))
     return fail(SPID_EINVAL, "lp_terms must be 1..3 (got %d)", d->lp_terms);
   for (int b = 0; b < d->nblocks; ++b) {
@@ -135,9 +140,11 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
     sh.TN = (p.max_n >= 256 && sh.MT <= 4) ? 2 : 1;
     sh.NW = p.max_n >= 128 ? 8 : 4;
   } else {
-    // FP32 accumulators are half the size: up to 512 columns per workgroup
-    sh.TN = p.max_n >= 512 ? 8 : (p.max_n >= 256 ? 4 : (p.max_n >= 128 ? 2 : 1));
-    sh.NW = 4;
+    // 8 waves (two per SIMD) of up to 4 column tiles: 512 columns per workgroup
+    sh.TN = p.max_n >= 512 ? 4 : (p.max_n >= 256 ? 2 : 1);
+    if (sh.MT >= 6 && sh.TN > 2) sh.TN = 2;
+    if (d->prec == SPID_SK_FP8E4M3) sh.TN = (sh.MT >= 6 || p.max_n < 256) ? 1 : 2;
+    sh.NW = p.max_n >= 128 ? 8 : 4;
   }
   sh.LMAX = pick_lmax(d->l);
   sh.CPT = (p.max_n > 512) ? 2 : 1;
@@ -145,9 +152,26 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
     int need = (p.max_n + sh.CPT - 1) / sh.CPT;
     sh.sel_thr = std::max(64, (need + 63) / 64 * 64);
   }
-  if (sh.CPT * sh.LMAX > 112)
-    return fail(SPID_EINVAL, "l=%d with n up to %d exceeds the selection register budget", d->l,
-                p.max_n);
+  sh.sel_rr = 0;
+  sh.sel_lds = 0;
+  if (sh.LMAX > 56 || p.max_n > 512) {
+    // hybrid: one column per thread, RR rows in registers, the rest in LDS
+    sh.CPT = 1;
+    sh.sel_thr = std::max(64, (p.max_n + 63) / 64 * 64);
+    const int rr_opts[] = {48, 32, 16};
+    for (int rr : rr_opts) {
+      if (sh.sel_thr > 512 && rr > 32) continue;   // 1024 threads: 128 registers per lane
+      const size_t lds = sizeof(double) * (size_t)std::max(0, d->l - rr) * sh.sel_thr;
+      if (lds <= 150 * 1024) {
+        sh.sel_rr = rr;
+        sh.sel_lds = lds;
+        break;
+      }
+    }
+    if (sh.sel_rr == 0)
+      return fail(SPID_EINVAL, "l=%d with n up to %d exceeds the selection register/LDS budget",
+                  d->l, p.max_n);
+  }
   sh.KMAX = pick_kmax(d->k_max);
   {
     const int ks = (d->k_max + 3) / 4;
@@ -160,6 +184,9 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
       }
     const int mtr = sh.KS <= 8 ? 4 : (sh.KS <= 16 ? 2 : 1);
     sh.RC_ROWS = 4 * 16 * mtr;   // 4 waves x MTR 16-row tiles
+    sh.rc_bf16 = (d->a_dtype == SPID_A_F32 && d->prec != SPID_SK_F64) ? 1 : 0;
+    sh.KS32 = (d->k_max + 31) / 32;
+    if (sh.rc_bf16) sh.RC_ROWS = 4 * 16 * (sh.KS32 == 1 ? 4 : 2);
   }
 
   // sketch work items: column tiles x K splits
@@ -294,10 +321,33 @@ void launch_sketch_t(spid_ctx* c, int j0, int j1, hipStream_t s) {
     }
     return;
   }
-  hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, 4>), grid, dim3(256), 0, s,
-                     c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                     c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
-                     c->at<float>(p.off_Y), c->at<float>(p.off_part));
+  if (c->desc.prec == SPID_SK_FP8E4M3) {
+    if constexpr (TN <= 2) {
+      if (p.sh.NW == 8)
+        hipLaunchKernelGGL((sketch_fp8_kernel<TA, MT, TN, 8>), grid, dim3(512), 0, s,
+                           c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                           c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+                           c->at<float>(p.off_Y), c->at<float>(p.off_part));
+      else
+        hipLaunchKernelGGL((sketch_fp8_kernel<TA, MT, TN, 4>), grid, dim3(256), 0, s,
+                           c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                           c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+                           c->at<float>(p.off_Y), c->at<float>(p.off_part));
+    }
+    return;
+  }
+  if constexpr (TN <= 4) {
+    if (p.sh.NW == 8)
+      hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, 8>), grid, dim3(512), 0, s,
+                         c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                         c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+                         c->at<float>(p.off_Y), c->at<float>(p.off_part));
+    else
+      hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, 4>), grid, dim3(256), 0, s,
+                         c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                         c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+                         c->at<float>(p.off_Y), c->at<float>(p.off_part));
+  }
 }
 
 template <typename TA, int MT>
@@ -305,8 +355,7 @@ void launch_sketch_mt(spid_ctx* c, int j0, int j1, hipStream_t s) {
   switch (c->plan.sh.TN) {
     case 1: launch_sketch_t<TA, MT, 1>(c, j0, j1, s); break;
     case 2: launch_sketch_t<TA, MT, 2>(c, j0, j1, s); break;
-    case 4: launch_sketch_t<TA, MT, 4>(c, j0, j1, s); break;
-    default: launch_sketch_t<TA, MT, 8>(c, j0, j1, s); break;
+    default: launch_sketch_t<TA, MT, 4>(c, j0, j1, s); break;
   }
 }
 
@@ -334,23 +383,45 @@ void launch_select_t(spid_ctx* c, hipStream_t s) {
 
 template <typename TY, int LMAX>
 void launch_select_l(spid_ctx* c, hipStream_t s) {
-  if (c->plan.sh.CPT == 1) {
-    launch_select_t<TY, LMAX, 1>(c, s);
-  } else {
-    if constexpr (LMAX <= 56) launch_select_t<TY, LMAX, 2>(c, s);
+  launch_select_t<TY, LMAX, 1>(c, s);
+}
+
+template <typename TY, int RR, int MAXTHR>
+void launch_select_hybrid_t(spid_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
+  static bool lds_set = false;   // one attribute call per instantiation and process
+  if (!lds_set && p.sh.sel_lds > 65536) {
+    if (hipFuncSetAttribute((const void*)select_hybrid_kernel<TY, RR, MAXTHR>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) != hipSuccess)
+      return;   // the launch below then fails and is reported
+    lds_set = true;
   }
+  hipLaunchKernelGGL((select_hybrid_kernel<TY, RR, MAXTHR>), dim3(c->desc.nblocks),
+                     dim3(p.sh.sel_thr), p.sh.sel_lds, s, c->at<BlkInfo>(p.off_blk), c->desc.l,
+                     c->desc.k_max, c->desc.tol, c->desc.rank_floor, c->at<TY>(p.off_Y),
+                     c->at<double>(p.off_R), c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
+                     c->at<int32_t>(p.off_st));
 }
 
 template <typename TY>
 void launch_select_y(spid_ctx* c, hipStream_t s) {
+  const Shape& sh = c->plan.sh;
+  if (sh.sel_rr) {
+    if (sh.sel_thr > 512) {
+      if (sh.sel_rr == 32) launch_select_hybrid_t<TY, 32, 1024>(c, s);
+      else launch_select_hybrid_t<TY, 16, 1024>(c, s);
+    } else {
+      if (sh.sel_rr == 48) launch_select_hybrid_t<TY, 48, 512>(c, s);
+      else if (sh.sel_rr == 32) launch_select_hybrid_t<TY, 32, 512>(c, s);
+      else launch_select_hybrid_t<TY, 16, 512>(c, s);
+    }
+    return;
+  }
   switch (c->plan.sh.LMAX) {
     case 16: launch_select_l<TY, 16>(c, s); break;
     case 32: launch_select_l<TY, 32>(c, s); break;
     case 48: launch_select_l<TY, 48>(c, s); break;
-    case 56: launch_select_l<TY, 56>(c, s); break;
-    case 64: launch_select_l<TY, 64>(c, s); break;
-    case 96: launch_select_l<TY, 96>(c, s); break;
-    default: launch_select_l<TY, 128>(c, s); break;
+    default: launch_select_l<TY, 56>(c, s); break;
   }
 }
 
@@ -366,8 +437,28 @@ void launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
                      c->at<double>(p.off_rcpart));
 }
 
+// single-precision data on the mixed path: split-bfloat16 error pass
+template <int KS32, int MTR>
+void launch_recon_bf16_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
+  const Plan& p = c->plan;
+  hipLaunchKernelGGL((recon_bf16x3_kernel<KS32, MTR>), dim3((unsigned)p.rc.size()),
+                     dim3(kRcThreads), 0, s, c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc),
+                     c->desc.k_max, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
+                     static_cast<float*>(skel), c->at<double>(p.off_rcpart));
+}
+
 template <typename TA>
 void launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
+  if constexpr (sizeof(TA) == 4) {
+    if (c->plan.sh.rc_bf16) {
+      switch (c->plan.sh.KS32) {
+        case 1: launch_recon_bf16_t<1, 4>(c, P, skel, s); break;
+        case 2: launch_recon_bf16_t<2, 2>(c, P, skel, s); break;
+        default: launch_recon_bf16_t<3, 2>(c, P, skel, s); break;
+      }
+      return;
+    }
+  }
   switch (c->plan.sh.KS) {
     case 1: launch_recon_t<TA, 1, 4>(c, P, skel, s); break;
     case 2: launch_recon_t<TA, 2, 4>(c, P, skel, s); break;

@@ -338,6 +338,170 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Sketch, OCP fp8 e4m3 (FP32 accumulation) on
+// v_mfma_scale_f32_16x16x128_f8f6f4.  Omega is the double-precision normal
+// rounded to nearest-even e4m3 (|Omega| < 448, scale 1).  Each lane supplies
+// 32 consecutive rows of one column as the 32 k-values of one MFMA; that run
+// is its own scaling block: per split term the lane picks a power of two
+// 2^E with max|residual| * 2^-E < 256, rounds residual * 2^-E to e4m3, passes
+// E as the E8M0 operand scale of the product, and subtracts what it
+// represented.  Chunk = 128 rows (one MFMA k-step), Omega double-buffered in
+// LDS as bytes.
+// ---------------------------------------------------------------------------
+constexpr int kKC8 = 128;
+constexpr int kOm8Stride = kKC8 + 16;   // bytes per Omega row in LDS
+
+template <int NTHR>
+__device__ __forceinline__ void gen_omega_chunk_e4m3(uint8_t* __restrict__ om, int l,
+                                                     uint64_t seed, uint32_t bkey, int64_t k0,
+                                                     int tid) {
+  const int npairs = (l + 1) >> 1;
+  for (int e = tid; e < npairs * kKC8; e += NTHR) {
+    const int q = e / kKC8, kk = e - q * kKC8;
+    const double2 z = omega_pair(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q);
+    om[(2 * q) * kOm8Stride + kk] = (uint8_t)to_e4m3_byte((float)rne_e4m3(z.x));
+    if (2 * q + 1 < l) om[(2 * q + 1) * kOm8Stride + kk] = (uint8_t)to_e4m3_byte((float)rne_e4m3(z.y));
+  }
+}
+
+template <typename TA>
+__device__ __forceinline__ void load32f(const TA* __restrict__ base, int64_t lda, int64_t col,
+                                        int64_t row, int64_t rend, bool vec, float out[32]) {
+  const TA* p = base + col * lda + row;
+  if constexpr (sizeof(TA) == 4) {
+    if (vec && row + 32 <= rend) {
+      const f32x4* q = reinterpret_cast<const f32x4*>(p);
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const f32x4 v = __builtin_nontemporal_load(q + h);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[4 * h + e] = v[e];
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 32; ++e) out[e] = (row + e < rend) ? (float)p[e] : 0.0f;
+}
+
+// One split term of a lane's 32 values: e4m3 bytes packed 4 per int, the
+// E8M0 scale byte, and the residual left for the next term.
+__device__ __forceinline__ i32x8 fp8_term(float res[32], int& scale_byte) {
+  float amax = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 32; ++e) amax = fmaxf(amax, fabsf(res[e]));
+  int ex = 0;
+  if (amax > 0.0f) {
+    frexpf(amax, &ex);          // amax < 2^ex
+    ex -= 8;                    // scaled magnitudes < 2^8 = 256 <= 448
+  } else {
+    ex = -127;
+  }
+  ex = max(ex, -127);
+  scale_byte = ex + 127;
+  const float down = ldexpf(1.0f, -ex), up = ldexpf(1.0f, ex);
+  i32x8 out;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int b = 0; b < 4; b += 2) {
+      const int e = 4 * w + b;
+      const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(res[e] * down, res[e + 1] * down, 0, false);
+      const float r0 = __builtin_amdgcn_cvt_f32_fp8(pk, 0);
+      const float r1 = __builtin_amdgcn_cvt_f32_fp8(pk, 1);
+      res[e] -= r0 * up;
+      res[e + 1] -= r1 * up;
+      word |= ((uint32_t)pk & 0xffffu) << (8 * b);
+    }
+    out[w] = (int)word;
+  }
+  return out;
+}
+
+template <typename TA, int MT, int TN, int NW>
+__global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
+    const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
+    int omega_per_block, int j0, int j1, int terms, float* __restrict__ Y,
+    float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) uint8_t om[2][MT * 16 * kOm8Stride];
+  const SkItem it = items[blockIdx.x];
+  const BlkInfo bi = blks[it.blk];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  const int ncols = bi.n;
+  const int cwave = it.c0 + wave * 16 * TN;
+  const int clo = max(j0, 0), chi = min(j1, ncols);
+  if (it.c0 >= chi || it.c0 + NW * 16 * TN <= clo) return;
+  const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
+  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
+  const bool vec = bi.vec_ok != 0;
+
+  for (int e = tid; e < 2 * MT * 16 * kOm8Stride; e += 64 * NW) (&om[0][0])[e] = 0;
+
+  f32x4 acc[MT][TN];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto load_chunk = [&](int64_t k0, float (&av)[TN][32]) {
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      const int col = cwave + 16 * u + r16;
+      if (col >= clo && col < chi && k0 < it.r1) {
+        load32f<TA>(A, bi.lda, col, k0 + 32 * g, it.r1, vec, av[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 32; ++e) av[u][e] = 0.0f;
+      }
+    }
+  };
+
+  float av[TN][32];
+  __syncthreads();
+  gen_omega_chunk_e4m3<64 * NW>(om[0], l, seed, bkey, it.r0, tid);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC8) {
+    const int64_t k1 = k0 + kKC8;
+    const bool more = k1 < it.r1;
+    load_chunk(k0, av);
+    if (more) gen_omega_chunk_e4m3<64 * NW>(om[buf ^ 1], l, seed, bkey, k1, tid);
+    i32x8 oa[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+      oa[t] = *reinterpret_cast<const i32x8*>(om[buf] + (16 * t + r16) * kOm8Stride + 32 * g);
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      for (int h = 0; h < terms; ++h) {
+        int sb;
+        const i32x8 bt = fp8_term(av[u], sb);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) acc[t][u] = mfma_fp8_scaled(oa[t], bt, acc[t][u], 127, sb);
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  float* dst = (bi.nsplit == 1) ? (Y + bi.y_off)
+                                : (part + bi.part_off + (int64_t)it.split * ncols * l);
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int col = cwave + 16 * u + r16;
+    if (col < clo || col >= chi) continue;
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + 4 * g + v;
+        if (row < l) dst[(int64_t)col * l + row] = acc[t][u][v];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Split-K reduction: Y_b(:, j) = sum over splits s (ascending) of the
 // partials, for the blocks listed in `split_blocks`, columns [j0, j1).
 // grid = (ceil(l*maxn / 256), number of split blocks)
@@ -561,6 +725,183 @@ __global__ __launch_bounds__(512) void select_kernel(
   for (int s = taken + tid; s < k_max; s += nthr) S_ws[(int64_t)b * k_max + s] = -1;
 }
 
+// ---------------------------------------------------------------------------
+// Column selection for sketches too large for registers alone: thread t owns
+// column t; rows [0, RR) of its sketch column live in registers, rows
+// [RR, l) in LDS laid out row-major over the threads ([r - RR][t], so a
+// wave's accesses are consecutive).  Same steps and reductions as
+// select_kernel.  Dynamic LDS: (l - RR) * blockDim doubles.
+// ---------------------------------------------------------------------------
+template <typename TY, int RR, int MAXTHR>
+__global__ __launch_bounds__(MAXTHR) void select_hybrid_kernel(
+    const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor,
+    const TY* __restrict__ Y, double* __restrict__ R, int32_t* __restrict__ S_ws,
+    int32_t* __restrict__ k_ws, int32_t* __restrict__ st_ws) {
+  extern __shared__ double wl[];          // [(l - RR)][nthr]
+  __shared__ double q_lds[128];
+  __shared__ double red_v[16];
+  __shared__ int red_i[16];
+  __shared__ double bc_v, bc_rss;
+  __shared__ int bc_i;
+  const int b = blockIdx.x;
+  const BlkInfo bi = blks[b];
+  const int n = bi.n;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+  const int lr = l > RR ? l - RR : 0;     // rows held in LDS
+  const TY* __restrict__ Yb = Y + bi.y_off;
+  double* __restrict__ Rb = R + bi.r_off;
+  const int j = tid;
+  bool live = j < n;
+
+  double w[RR];
+  int bad = 0;
+  double nu;
+  {
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      double v = 0.0;
+      if (live && r < l) v = (double)Yb[(int64_t)j * l + r];
+      if (!isfinite(v)) bad = 1;
+      w[r] = v;
+      acc += v * v;
+    }
+    for (int r = 0; r < lr; ++r) {
+      const double v = live ? (double)Yb[(int64_t)j * l + RR + r] : 0.0;
+      if (!isfinite(v)) bad = 1;
+      wl[r * nthr + tid] = v;
+      acc += v * v;
+    }
+    nu = live ? acc : 0.0;
+  }
+  for (int e = tid; e < 128; e += nthr) q_lds[e] = 0.0;
+  const int any_bad = __syncthreads_or(bad);
+
+  double fs = wave_sum(nu), fm = wave_max(nu);
+  if (lane == 0) red_v[wave] = fs;
+  __syncthreads();
+  double F2 = 0.0;
+  for (int v = 0; v < nwaves; ++v) F2 += red_v[v];
+  __syncthreads();
+  if (lane == 0) red_v[wave] = fm;
+  __syncthreads();
+  double nu0max = 0.0;
+  for (int v = 0; v < nwaves; ++v) nu0max = fmax(nu0max, red_v[v]);
+  __syncthreads();
+
+  int kcap = k_max;
+  if (kcap > l) kcap = l;
+  if (kcap > n) kcap = n;
+  int status = 0, taken = 0;
+  if (any_bad) {
+    status = 2;
+  } else {
+    for (int s = 0; s < kcap; ++s) {
+      double bv = live ? nu : -1.0;
+      int bj = live ? j : 0x7fffffff;
+      wave_argmax(bv, bj);
+      if (lane == 0) {
+        red_v[wave] = bv;
+        red_i[wave] = bj;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double v = red_v[0];
+        int i = red_i[0];
+        for (int x = 1; x < nwaves; ++x)
+          if (red_v[x] > v || (red_v[x] == v && red_i[x] < i)) {
+            v = red_v[x];
+            i = red_i[x];
+          }
+        bc_v = v;
+        bc_i = i;
+      }
+      __syncthreads();
+      const double best = bc_v;
+      const int p = bc_i;
+      if (!(best > 0.0)) {
+        status = 1;
+        break;
+      }
+      if (rank_floor > 0.0 && best <= rank_floor * rank_floor * nu0max) {
+        status = 1;
+        break;
+      }
+      if (j == p) {
+        double pn = 0.0;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+          pn += w[r] * w[r];
+          q_lds[r] = w[r];
+        }
+        for (int r = 0; r < lr; ++r) {
+          const double v = wl[r * nthr + tid];
+          pn += v * v;
+          q_lds[RR + r] = v;
+        }
+        const double rss = sqrt(pn);
+        bc_rss = rss;
+        Rb[(int64_t)s * n + p] = rss;
+        live = false;
+        nu = 0.0;
+      }
+      if (tid == 0) S_ws[(int64_t)b * k_max + s] = p;
+      __syncthreads();
+      if (tid < RR + lr) q_lds[tid] = q_lds[tid] / bc_rss;
+      __syncthreads();
+      taken = s + 1;
+      double d = 0.0;
+#pragma unroll
+      for (int r0 = 0; r0 < RR; r0 += 8) {
+#pragma unroll
+        for (int r = r0; r < r0 + 8 && r < RR; ++r) d += q_lds[r] * w[r];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      for (int r = 0; r < lr; ++r) d += q_lds[RR + r] * wl[r * nthr + tid];
+      if (live) Rb[(int64_t)s * n + j] = d;
+      d = live ? d : 0.0;
+      double a2 = 0.0;
+#pragma unroll
+      for (int r0 = 0; r0 < RR; r0 += 8) {
+#pragma unroll
+        for (int r = r0; r < r0 + 8 && r < RR; ++r) {
+          const double qr =
+              __hip_atomic_load(q_lds + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          w[r] -= d * qr;
+          a2 += w[r] * w[r];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      for (int r = 0; r < lr; ++r) {
+        double v = wl[r * nthr + tid];
+        v -= d * q_lds[RR + r];
+        wl[r * nthr + tid] = v;
+        a2 += v * v;
+      }
+      nu = live ? a2 : 0.0;
+      if (tol > 0.0) {
+        const double rest = wave_sum(nu);
+        if (lane == 0) red_v[wave] = rest;
+        __syncthreads();
+        double tot = 0.0;
+        for (int v = 0; v < nwaves; ++v) tot += red_v[v];
+        if (sqrt(tot) <= tol * sqrt(F2)) {
+          __syncthreads();
+          break;
+        }
+        if (s == kcap - 1) status = 3;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    k_ws[b] = taken;
+    st_ws[b] = status;
+  }
+  for (int s = taken + tid; s < k_max; s += nthr) S_ws[(int64_t)b * k_max + s] = -1;
+}
+
 // Copy per-block selection results to the caller's arrays.
 __global__ void select_export_kernel(int nblocks, int k_max, const int32_t* __restrict__ S_ws,
                                      const int32_t* __restrict__ k_ws,
@@ -766,6 +1107,165 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
           const double r = av[mt][v] - acc[mt][v];
           e2 += r * r;
           a2 += av[mt][v] * av[mt][v];
+        }
+    }
+    __syncthreads();
+  }
+  e2 = wave_sum(e2);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    red[wave] = e2;
+    red[4 + wave] = a2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    part[2 * (int64_t)blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    part[2 * (int64_t)blockIdx.x + 1] = red[4] + red[5] + red[6] + red[7];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction error for single-precision data on the bfloat16 matrix
+// cores.  A(rows, S) and P are split into three bfloat16 terms each
+// (hi + mid + lo carries all 24 bits of a float), and
+// Ahat = A(rows,S) P is accumulated in FP32 from the six term products whose
+// weight is at least 2^-16 (hi*hi, hi*mid, mid*hi, hi*lo, mid*mid, lo*hi)
+// with v_mfma_f32_16x16x32_bf16.  The residual is formed in FP32 and its
+// square accumulated in FP64.  Lane (g, c) of the bf16 MFMA output holds rows
+// 4g..4g+3 of column c, so each lane loads 16 contiguous bytes per tile.
+// KS32 = k-steps of 32 selected columns; a workgroup of 4 waves covers
+// 4 * 16 * MTR rows.  The chunk's P terms are staged in LDS as bfloat16.
+// ---------------------------------------------------------------------------
+template <int KS32, int MTR>
+__global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
+    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max,
+    const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
+    const double* __restrict__ P, float* __restrict__ skel, double* __restrict__ part) {
+  constexpr int KP = 32 * KS32;
+  __shared__ __attribute__((aligned(16))) __bf16 pt[3][kRcCols][KP];
+  __shared__ double red[8];
+  __shared__ int cols[1024];
+  __shared__ unsigned char is_sel[1024];
+  __shared__ int wcount[4];
+  const RcItem it = items[blockIdx.x];
+  const BlkInfo bi = blks[it.blk];
+  const int n = bi.n;
+  const int k = k_ws[it.blk];
+  const int32_t* S = S_ws + (int64_t)it.blk * k_max;
+  const float* __restrict__ A = static_cast<const float*>(bi.A);
+  const double* __restrict__ Pb = P + bi.p_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const bool vec = bi.vec_ok != 0 && (it.i0 % 4) == 0;
+
+  for (int j = tid; j < n; j += kRcThreads) is_sel[j] = 0;
+  __syncthreads();
+  if (tid < k) is_sel[S[tid]] = 1;
+  __syncthreads();
+  int ncols = 0;
+  for (int base = 0; base < n; base += kRcThreads) {
+    const int j = base + tid;
+    const bool keep = j < n && !is_sel[j];
+    const uint64_t bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wave] = __popcll(bal);
+    __syncthreads();
+    int off = ncols;
+    for (int v = 0; v < wave; ++v) off += wcount[v];
+    if (keep) cols[off + before] = j;
+    int tot = 0;
+    for (int v = 0; v < 4; ++v) tot += wcount[v];
+    ncols += tot;
+    __syncthreads();
+  }
+
+  const int64_t rbase = it.i0 + (int64_t)wave * 16 * MTR;
+  // A operand: tile row c16, selected columns 32 ks + 8 g + v, three terms
+  bf16x8 at[MTR][KS32][3];
+  double a2 = 0.0, e2 = 0.0;
+#pragma unroll
+  for (int mt = 0; mt < MTR; ++mt) {
+    const int64_t i = rbase + 16 * mt + c16;
+#pragma unroll
+    for (int ks = 0; ks < KS32; ++ks) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int t = 32 * ks + 8 * g + v;
+        float x = 0.0f;
+        if (t < k && i < bi.m) {
+          x = A[(int64_t)S[t] * bi.lda + i];
+          if (skel) skel[bi.sk_off + (int64_t)t * bi.m + i] = x;
+        }
+        a2 += (double)x * (double)x;
+        const __bf16 h = to_bf16(x);
+        const float r1 = x - (float)h;
+        const __bf16 md = to_bf16(r1);
+        const __bf16 lo = to_bf16(r1 - (float)md);
+        at[mt][ks][0][v] = h;
+        at[mt][ks][1][v] = md;
+        at[mt][ks][2][v] = lo;
+      }
+    }
+  }
+
+  for (int c0 = 0; c0 < ncols; c0 += kRcCols) {
+    const int cc = min(kRcCols, ncols - c0);
+    for (int e = tid; e < kRcCols * KP; e += kRcThreads) {
+      const int q = e / KP, t = e - q * KP;
+      const double pv = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
+      const __bf16 h = to_bf16((float)pv);
+      const double r1 = pv - (double)(float)h;
+      const __bf16 md = to_bf16((float)r1);
+      const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
+      pt[0][q][t] = h;
+      pt[1][q][t] = md;
+      pt[2][q][t] = lo;
+    }
+    __syncthreads();
+    for (int q0 = 0; q0 < cc; q0 += 16) {
+      const int q = q0 + c16;
+      const bool cok = q < cc;
+      const int64_t j = cok ? cols[c0 + q] : 0;
+      float av[MTR][4];
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt) {
+        const int64_t i0 = rbase + 16 * mt + 4 * g;
+        const float* src = A + j * bi.lda + i0;
+        if (cok && vec && i0 + 4 <= bi.m) {
+          const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
+#pragma unroll
+          for (int v = 0; v < 4; ++v) av[mt][v] = x[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) av[mt][v] = (cok && i0 + v < bi.m) ? src[v] : 0.0f;
+        }
+      }
+      f32x4 acc[MTR];
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS32; ++ks) {
+        const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(&pt[0][q0 + c16][32 * ks + 8 * g]);
+        const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(&pt[1][q0 + c16][32 * ks + 8 * g]);
+        const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(&pt[2][q0 + c16][32 * ks + 8 * g]);
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt) {
+          // smallest terms first
+          acc[mt] = mfma_bf16(at[mt][ks][2], p0, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][1], p1, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][0], p2, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][1], p0, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][0], p1, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][0], p0, acc[mt]);
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float r = av[mt][v] - acc[mt][v];
+          e2 += (double)r * (double)r;
+          a2 += (double)av[mt][v] * (double)av[mt][v];
         }
     }
     __syncthreads();

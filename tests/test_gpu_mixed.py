@@ -87,3 +87,68 @@ def test_bf16_split_term_sketch_accuracy_orders():
     print("sketch rel err by terms", errs)
     assert errs[0] > errs[1] > errs[2]
     assert errs[0] < 2e-2 and errs[1] < 1e-4 and errs[2] < 1e-5
+
+
+def test_turbulence_8cubed_blocks_fp8():
+    """Blocks of the 32768-block workload (8^3 x 5 fields, n = 384), k = 64, l = 96, e4m3 sketch
+    with three split terms and per-32-row power-of-two scales."""
+    w = si.WORKLOADS["turb256_b32768_fp8_stream"]
+    modes = si.turbulence_modes(w.nmodes, w.kmax, w.data_seed)
+    blocks = [si.turbulence_block_direct(w, b, modes) for b in (0, 20000)]
+    g = gpu_run(blocks, w.l, w.k_max, w.omega_seed, prec="fp8", lp_terms=3)
+    o = oracle_run(blocks, w.l, w.k_max, w.omega_seed, prec="fp8")
+    e_gpu, e_ora, r2 = _gates(blocks, g, o, gamma=1e-2, y_rtol=2e-4)
+    print(f"fp8 e_gpu={e_gpu:.3e} e_oracle={e_ora:.3e} R2={r2:.3e}")
+    assert e_ora <= 5e-4 and e_gpu <= 1e-3 and r2 <= 1e-3
+
+
+def test_fp8_split_term_sketch_accuracy_orders():
+    rng = np.random.default_rng(23)
+    blocks = [np.asfortranarray((rng.standard_normal((3000, 40)) *
+                                 np.exp(rng.uniform(-5, 5, (3000, 1)))).astype(np.float32))]
+    o = oracle_run(blocks, 20, 8, 5, prec="fp8")
+    errs = []
+    for terms in (1, 2, 3):
+        g = gpu_run(blocks, 20, 8, 5, prec="fp8", lp_terms=terms)
+        scale = np.abs(o.Y[0]).max()
+        errs.append(np.abs(g.Y[0] - o.Y[0]).max() / scale)
+    print("fp8 sketch rel err by terms", errs)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[0] < 1e-1 and errs[1] < 3e-3 and errs[2] < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_wide_blocks_hybrid_selection(prec):
+    """n up to 1000 and l = 50 (the uneven workload's limits): selection keeps part of the
+    sketch in LDS."""
+    rng = np.random.default_rng(24)
+    dt = np.float64 if prec == "f64" else np.float32
+    blocks = []
+    for (m, n, r) in [(1600, 1000, 30), (640, 700, 12), (3000, 130, 40)]:
+        U = np.linalg.qr(rng.standard_normal((m, r)))[0]
+        V = np.linalg.qr(rng.standard_normal((n, r)))[0]
+        blocks.append(np.asfortranarray(((U * 10.0 ** (-0.25 * np.arange(r))) @ V.T).astype(dt)))
+    g = gpu_run(blocks, 50, 40, 12, tol=1e-4, prec=prec, lp_terms=2)
+    o = oracle_run(blocks, 50, 40, 12, tol=1e-4, prec=prec)
+    if prec == "f64":
+        from _harness import compare
+        compare(g, o)
+    else:
+        e_gpu, e_ora, r2 = _gates(blocks, g, o)
+        assert e_gpu <= 1e-3 and r2 <= 1e-3
+
+
+def test_tall_sketch_hybrid_selection_f64():
+    """l = 96, n = 384 in double precision: the selection's hybrid register/LDS kernel
+    against the oracle by the FP64 gap rule."""
+    rng = np.random.default_rng(25)
+    blocks = []
+    for (m, n, r) in [(2560, 384, 80), (3000, 200, 50)]:
+        U = np.linalg.qr(rng.standard_normal((m, r)))[0]
+        V = np.linalg.qr(rng.standard_normal((n, r)))[0]
+        blocks.append(np.asfortranarray((U * 10.0 ** (-0.05 * np.arange(r))) @ V.T))
+    from _harness import compare
+    g = gpu_run(blocks, 96, 64, 13)
+    o = oracle_run(blocks, 96, 64, 13)
+    st = compare(g, o)
+    assert min(st["prefix"]) >= 10
