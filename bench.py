@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--cpu-max-blocks", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one step into a HIP graph and time graph replays")
     return ap.parse_args()
 
 
@@ -103,6 +105,24 @@ def main():
         for i in range(4):
             stage[i] += e[i].elapsed_time(e[i + 1])
     stage /= args.steps                     # ms per stage
+    graph_ms = None
+    if args.graph:
+        # one step captured into a HIP graph, replayed for the same number of steps
+        graph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(stream)
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(graph, stream=cap):
+                ctx.run(stream=cap)
+        stream.wait_stream(cap)
+        graph.replay()
+        torch.cuda.synchronize()
+        t0g = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0g) * 1e3 / args.steps
+        log(args, f"graph replay: {graph_ms:.3f} ms per step")
     ms_step = wall * 1e3 / args.steps
     value = nbytes / (ms_step * 1e-3) / 1e9
     rel_err = ctx.rel_error()
@@ -159,6 +179,7 @@ def main():
         "error_gate_1e-3": bool(rel_err <= 1e-3),
         "compression_factor": round(cf, 3),
         "k_mean": float(kk.mean()),
+        "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 4),
         "stage_ms": {"sketch": round(stage[0], 4), "select": round(stage[1], 4),
                      "coeffs": round(stage[2], 4), "reconstruct": round(stage[3], 4)},
         "roofline": roof,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -191,21 +192,22 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
 
   // sketch work items: column tiles x K splits
   const int tile_cols = 16 * sh.NW * sh.TN;
-  int64_t base_items = 0;
-  for (int b = 0; b < nb; ++b) base_items += (d->h_n[b] + tile_cols - 1) / tile_cols;
-  const int64_t target = 2048;
+  // Cost-balanced K splits: an item's cost ~ rows x columns it streams.  A
+  // block is split along K when its column tiles exceed the target item cost
+  // (total / kTargetItems), keeping at least min_rows rows per split.
+  double total_cost = 0.0;
+  for (int b = 0; b < nb; ++b) total_cost += (double)d->h_m[b] * d->h_n[b];
+  const int64_t kTargetItems = 2048;
   const int64_t min_rows = 256;
+  const double target_cost = std::max(total_cost / kTargetItems, (double)min_rows * tile_cols);
   p.blk.resize(nb);
   int64_t y_off = 0, r_off = 0, p_off = 0, sk_off = 0, part_off = 0;
   for (int b = 0; b < nb; ++b) {
     const int64_t m = d->h_m[b];
     const int32_t n = d->h_n[b];
-    int nsplit = 1;
-    if (base_items < target) {
-      const int64_t want = (target + base_items - 1) / base_items;
-      const int64_t cap = std::max<int64_t>(1, m / min_rows);
-      nsplit = (int)std::min(want, cap);
-    }
+    const double tile_cost = (double)m * std::min(n, tile_cols);
+    int nsplit = (int)std::ceil(tile_cost / target_cost);
+    nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nsplit, m / min_rows));
     // rows per split, multiple of the chunk
     int64_t rows = (m + nsplit - 1) / nsplit;
     rows = (rows + kKC - 1) / kKC * kKC;
@@ -252,6 +254,12 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
   }
   p.rc_first.push_back((int64_t)p.rc.size());
   p.part_elems = part_off;
+  // longest items first (the hardware dispatches workgroups in grid order)
+  std::stable_sort(p.items.begin(), p.items.end(), [&](const SkItem& a, const SkItem& b2) {
+    const int64_t ca = (a.r1 - a.r0) * std::min<int64_t>(tile_cols, d->h_n[a.blk] - a.c0);
+    const int64_t cb = (b2.r1 - b2.r0) * std::min<int64_t>(tile_cols, d->h_n[b2.blk] - b2.c0);
+    return ca > cb;
+  });
   const size_t ysz = p.ydt == 0 ? 8 : 4;
   size_t off = 0;
   auto take = [&](size_t bytes) {

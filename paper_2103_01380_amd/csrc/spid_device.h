@@ -12,6 +12,7 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWave = 64;
@@ -127,7 +128,9 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 //   bf16 16x16x32: A lane l slot v -> (row l%16, k 8(l/16)+v); B likewise with
 //                 col l%16; D lane l slot v -> (row 4(l/16)+v, col l%16).
 //   f8f6f4 16x16x128 (e4m3, E8M0 scales): A lane l byte v -> (row l%16,
-//                 k 32(l/16)+v); B likewise; D as bf16.
+//                 k 16(l/16)+v for v < 16, 64+16(l/16)+v-16 for v >= 16); B
+//                 likewise with col l%16; the scale of K block kb (32 k-values)
+//                 of row/column c comes from lane c+16kb; D as bf16.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);

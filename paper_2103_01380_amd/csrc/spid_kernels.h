@@ -340,13 +340,12 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
 // ---------------------------------------------------------------------------
 // Sketch, OCP fp8 e4m3 (FP32 accumulation) on
 // v_mfma_scale_f32_16x16x128_f8f6f4.  Omega is the double-precision normal
-// rounded to nearest-even e4m3 (|Omega| < 448, scale 1).  Each lane supplies
-// 32 consecutive rows of one column as the 32 k-values of one MFMA; that run
-// is its own scaling block: per split term the lane picks a power of two
-// 2^E with max|residual| * 2^-E < 256, rounds residual * 2^-E to e4m3, passes
-// E as the E8M0 operand scale of the product, and subtracts what it
-// represented.  Chunk = 128 rows (one MFMA k-step), Omega double-buffered in
-// LDS as bytes.
+// rounded to nearest-even e4m3 (|Omega| < 448, scale 1).  A chunk is 128 rows
+// (one MFMA k-step); every 32 consecutive rows of a column form one scaling
+// block: per split term its power of two 2^E (max|residual| * 2^-E < 256) is
+// agreed between the two lanes holding its halves, passed as the E8M0 operand
+// scale of the product, the residual * 2^-E is rounded to e4m3 and what it
+// represented is subtracted.  Omega is double-buffered in LDS as bytes.
 // ---------------------------------------------------------------------------
 constexpr int kKC8 = 128;
 constexpr int kOm8Stride = kKC8 + 16;   // bytes per Omega row in LDS
@@ -364,57 +363,91 @@ __device__ __forceinline__ void gen_omega_chunk_e4m3(uint8_t* __restrict__ om, i
   }
 }
 
+// The f8f6f4 16x16x128 operand layout (checked on the device): lane group g
+// = lane/16 holds k = 16g..16g+15 in bytes 0..15 and k = 64+16g..64+16g+15 in
+// bytes 16..31; the E8M0 scale of K block kb (k = 32kb..32kb+31) for row or
+// column c is taken from lane c + 16 kb.  Chunk row r of the sketch is k = r.
+// Load the lane's two 16-row runs of one column as floats (rows at or past
+// `rend` read as zero).
 template <typename TA>
 __device__ __forceinline__ void load32f(const TA* __restrict__ base, int64_t lda, int64_t col,
-                                        int64_t row, int64_t rend, bool vec, float out[32]) {
-  const TA* p = base + col * lda + row;
-  if constexpr (sizeof(TA) == 4) {
-    if (vec && row + 32 <= rend) {
-      const f32x4* q = reinterpret_cast<const f32x4*>(p);
+                                        int64_t k0, int g, int64_t rend, bool vec,
+                                        float out[32]) {
 #pragma unroll
-      for (int h = 0; h < 8; ++h) {
-        const f32x4 v = __builtin_nontemporal_load(q + h);
+  for (int h = 0; h < 2; ++h) {
+    const int64_t row = k0 + 64 * h + 16 * g;
+    const TA* p = base + col * lda + row;
+    bool done = false;
+    if constexpr (sizeof(TA) == 4) {
+      if (vec && row + 16 <= rend) {
+        const f32x4* q = reinterpret_cast<const f32x4*>(p);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) out[4 * h + e] = v[e];
+        for (int w = 0; w < 4; ++w) {
+          const f32x4 v = __builtin_nontemporal_load(q + w);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) out[16 * h + 4 * w + e] = v[e];
+        }
+        done = true;
       }
-      return;
+    }
+    if (!done) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) out[16 * h + e] = (row + e < rend) ? (float)p[e] : 0.0f;
     }
   }
-#pragma unroll
-  for (int e = 0; e < 32; ++e) out[e] = (row + e < rend) ? (float)p[e] : 0.0f;
 }
 
-// One split term of a lane's 32 values: e4m3 bytes packed 4 per int, the
-// E8M0 scale byte, and the residual left for the next term.
-__device__ __forceinline__ i32x8 fp8_term(float res[32], int& scale_byte) {
-  float amax = 0.0f;
+// Power-of-two exponent E with amax * 2^-E < 256 (<= 448, the e4m3 maximum);
+// -127 for an all-zero block.
+__device__ __forceinline__ int fp8_block_exp(float amax) {
+  if (!(amax > 0.0f)) return -127;
+  int ex;
+  frexpf(amax, &ex);   // amax < 2^ex
+  return max(ex - 8, -127);
+}
+
+// One split term of a lane's 32 values (two 16-value halves, each in its own
+// 32-row K block): e4m3 bytes packed 4 per int with each half scaled by its
+// block's power of two, the residual left for the next term, and the E8M0
+// scale byte of K block g that this lane supplies to the MFMA.
+__device__ __forceinline__ i32x8 fp8_term(float res[32], int g, int& scale_byte) {
+  float h0 = 0.0f, h1 = 0.0f;
 #pragma unroll
-  for (int e = 0; e < 32; ++e) amax = fmaxf(amax, fabsf(res[e]));
-  int ex = 0;
-  if (amax > 0.0f) {
-    frexpf(amax, &ex);          // amax < 2^ex
-    ex -= 8;                    // scaled magnitudes < 2^8 = 256 <= 448
-  } else {
-    ex = -127;
+  for (int e = 0; e < 16; ++e) {
+    h0 = fmaxf(h0, fabsf(res[e]));
+    h1 = fmaxf(h1, fabsf(res[16 + e]));
   }
-  ex = max(ex, -127);
-  scale_byte = ex + 127;
-  const float down = ldexpf(1.0f, -ex), up = ldexpf(1.0f, ex);
+  // block maxima: first halves of lane groups {0,1} -> block 0, {2,3} -> block 1,
+  // second halves {0,1} -> block 2, {2,3} -> block 3
+  h0 = fmaxf(h0, __shfl_xor(h0, 16, kWave));
+  h1 = fmaxf(h1, __shfl_xor(h1, 16, kWave));
+  const float o0 = __shfl_xor(h0, 32, kWave);
+  const float o1 = __shfl_xor(h1, 32, kWave);
+  const bool lo_pair = g < 2;
+  const float b0 = lo_pair ? h0 : o0, b1 = lo_pair ? o0 : h0;
+  const float b2 = lo_pair ? h1 : o1, b3 = lo_pair ? o1 : h1;
+  const int e_first = fp8_block_exp(lo_pair ? b0 : b1);
+  const int e_second = fp8_block_exp(lo_pair ? b2 : b3);
+  const float bg = g == 0 ? b0 : (g == 1 ? b1 : (g == 2 ? b2 : b3));
+  scale_byte = fp8_block_exp(bg) + 127;
   i32x8 out;
 #pragma unroll
-  for (int w = 0; w < 8; ++w) {
-    uint32_t word = 0;
+  for (int hh = 0; hh < 2; ++hh) {
+    const int ex = hh ? e_second : e_first;
+    const float down = ldexpf(1.0f, -ex), up = ldexpf(1.0f, ex);
 #pragma unroll
-    for (int b = 0; b < 4; b += 2) {
-      const int e = 4 * w + b;
-      const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(res[e] * down, res[e + 1] * down, 0, false);
-      const float r0 = __builtin_amdgcn_cvt_f32_fp8(pk, 0);
-      const float r1 = __builtin_amdgcn_cvt_f32_fp8(pk, 1);
-      res[e] -= r0 * up;
-      res[e + 1] -= r1 * up;
-      word |= ((uint32_t)pk & 0xffffu) << (8 * b);
+    for (int w = 0; w < 4; ++w) {
+      uint32_t word = 0;
+#pragma unroll
+      for (int b = 0; b < 4; b += 2) {
+        const int e = 16 * hh + 4 * w + b;
+        const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(res[e] * down, res[e + 1] * down, 0, false);
+        res[e] -= __builtin_amdgcn_cvt_f32_fp8(pk, 0) * up;
+        res[e + 1] -= __builtin_amdgcn_cvt_f32_fp8(pk, 1) * up;
+        word |= ((uint32_t)pk & 0xffffu) << (8 * b);
+      }
+      out[4 * hh + w] = (int)word;
     }
-    out[w] = (int)word;
   }
   return out;
 }
@@ -451,7 +484,7 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
     for (int u = 0; u < TN; ++u) {
       const int col = cwave + 16 * u + r16;
       if (col >= clo && col < chi && k0 < it.r1) {
-        load32f<TA>(A, bi.lda, col, k0 + 32 * g, it.r1, vec, av[u]);
+        load32f<TA>(A, bi.lda, col, k0, g, it.r1, vec, av[u]);
       } else {
 #pragma unroll
         for (int e = 0; e < 32; ++e) av[u][e] = 0.0f;
@@ -471,13 +504,17 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
     if (more) gen_omega_chunk_e4m3<64 * NW>(om[buf ^ 1], l, seed, bkey, k1, tid);
     i32x8 oa[MT];
 #pragma unroll
-    for (int t = 0; t < MT; ++t)
-      oa[t] = *reinterpret_cast<const i32x8*>(om[buf] + (16 * t + r16) * kOm8Stride + 32 * g);
+    for (int t = 0; t < MT; ++t) {
+      const uint8_t* orow = om[buf] + (16 * t + r16) * kOm8Stride;
+      const i32x4 lo = *reinterpret_cast<const i32x4*>(orow + 16 * g);
+      const i32x4 hi = *reinterpret_cast<const i32x4*>(orow + 64 + 16 * g);
+      oa[t] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
       for (int h = 0; h < terms; ++h) {
         int sb;
-        const i32x8 bt = fp8_term(av[u], sb);
+        const i32x8 bt = fp8_term(av[u], g, sb);
 #pragma unroll
         for (int t = 0; t < MT; ++t) acc[t][u] = mfma_fp8_scaled(oa[t], bt, acc[t][u], 127, sb);
       }
