@@ -144,7 +144,7 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
     // 8 waves (two per SIMD) of up to 4 column tiles: 512 columns per workgroup
     sh.TN = p.max_n >= 512 ? 4 : (p.max_n >= 256 ? 2 : 1);
     if (sh.MT >= 6 && sh.TN > 2) sh.TN = 2;
-    if (d->prec == SPID_SK_FP8E4M3) sh.TN = (sh.MT >= 6 || p.max_n < 256) ? 1 : 2;
+    if (d->prec == SPID_SK_FP8E4M3) sh.TN = 1;
     sh.NW = p.max_n >= 128 ? 8 : 4;
   }
   sh.LMAX = pick_lmax(d->l);
@@ -183,11 +183,11 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
         sh.KS = o;
         break;
       }
-    const int mtr = sh.KS <= 8 ? 4 : (sh.KS <= 16 ? 2 : 1);
+    const int mtr = sh.KS <= 2 ? 4 : (sh.KS <= 16 ? 2 : 1);
     sh.RC_ROWS = 4 * 16 * mtr;   // 4 waves x MTR 16-row tiles
     sh.rc_bf16 = (d->a_dtype == SPID_A_F32 && d->prec != SPID_SK_F64) ? 1 : 0;
     sh.KS32 = (d->k_max + 31) / 32;
-    if (sh.rc_bf16) sh.RC_ROWS = 4 * 16 * (sh.KS32 == 1 ? 4 : 2);
+    if (sh.rc_bf16) sh.RC_ROWS = 4 * 16 * 2;
   }
 
   // sketch work items: column tiles x K splits
@@ -294,6 +294,8 @@ struct spid_ctx {
   bool bound = false;
   bool selected = false;
   bool coeffs_lds_set = false;
+  bool all_vec = false;            // every block's column starts are 16-byte aligned
+  bool all_vec4 = false;           // ... and every m is a multiple of 4
   std::vector<uint8_t> covered;   // per column index: sketched since bind
   template <typename T>
   T* at(size_t off) const {
@@ -310,51 +312,41 @@ spid_status hip_check(const char* what) {
 }
 
 // ---- sketch dispatch
+template <typename TA, int MT, int TN, int NW, bool VEC>
+void launch_sketch_k(spid_ctx* c, int j0, int j1, hipStream_t s) {
+  const Plan& p = c->plan;
+  dim3 grid((unsigned)p.items.size()), block(64 * NW);
+  if (p.ydt == 0) {
+    hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN, NW, VEC>), grid, block, 0, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->at<double>(p.off_Y),
+                       c->at<double>(p.off_part));
+  } else if (c->desc.prec == SPID_SK_FP8E4M3) {
+    hipLaunchKernelGGL((sketch_fp8_kernel<TA, MT, TN, NW, VEC>), grid, block, 0, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+                       c->at<float>(p.off_Y), c->at<float>(p.off_part));
+  } else {
+    hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, NW, VEC>), grid, block, 0, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
+                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+                       c->at<float>(p.off_Y), c->at<float>(p.off_part));
+  }
+}
+
+// instantiated (TN, NW) pairs: FP64 path 8 waves x 1-2 tiles or 4 waves x 1
+// tile; low-precision paths 8 waves x 1-4 tiles or 4 waves x 1 tile
 template <typename TA, int MT, int TN>
 void launch_sketch_t(spid_ctx* c, int j0, int j1, hipStream_t s) {
-  const Plan& p = c->plan;
-  dim3 grid((unsigned)p.items.size());
-  if (p.ydt == 0) {
-    if constexpr (TN <= 2) {
-      if (p.sh.NW == 8)
-        hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN, 8>), grid, dim3(512), 0, s,
-                           c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                           c->desc.seed, c->desc.omega_per_block, j0, j1,
-                           c->at<double>(p.off_Y), c->at<double>(p.off_part));
-      else
-        hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN, 4>), grid, dim3(256), 0, s,
-                           c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                           c->desc.seed, c->desc.omega_per_block, j0, j1,
-                           c->at<double>(p.off_Y), c->at<double>(p.off_part));
+  const bool vec = c->all_vec;
+  if (c->plan.sh.NW == 8) {
+    if (vec) launch_sketch_k<TA, MT, TN, 8, true>(c, j0, j1, s);
+    else launch_sketch_k<TA, MT, TN, 8, false>(c, j0, j1, s);
+  } else {
+    if constexpr (TN == 1) {
+      if (vec) launch_sketch_k<TA, MT, 1, 4, true>(c, j0, j1, s);
+      else launch_sketch_k<TA, MT, 1, 4, false>(c, j0, j1, s);
     }
-    return;
-  }
-  if (c->desc.prec == SPID_SK_FP8E4M3) {
-    if constexpr (TN <= 2) {
-      if (p.sh.NW == 8)
-        hipLaunchKernelGGL((sketch_fp8_kernel<TA, MT, TN, 8>), grid, dim3(512), 0, s,
-                           c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                           c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
-                           c->at<float>(p.off_Y), c->at<float>(p.off_part));
-      else
-        hipLaunchKernelGGL((sketch_fp8_kernel<TA, MT, TN, 4>), grid, dim3(256), 0, s,
-                           c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                           c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
-                           c->at<float>(p.off_Y), c->at<float>(p.off_part));
-    }
-    return;
-  }
-  if constexpr (TN <= 4) {
-    if (p.sh.NW == 8)
-      hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, 8>), grid, dim3(512), 0, s,
-                         c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                         c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
-                         c->at<float>(p.off_Y), c->at<float>(p.off_part));
-    else
-      hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, 4>), grid, dim3(256), 0, s,
-                         c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                         c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
-                         c->at<float>(p.off_Y), c->at<float>(p.off_part));
   }
 }
 
@@ -433,26 +425,46 @@ void launch_select_y(spid_ctx* c, hipStream_t s) {
   }
 }
 
-// ---- reconstruction dispatch (matrix-core kernel)
+// ---- reconstruction dispatch (matrix-core kernels)
+// one attribute call per kernel instantiation for dynamic LDS above 64 KiB
+template <typename K>
+bool allow_lds(K kernel, size_t bytes) {
+  static bool done = false;
+  if (done || bytes <= 65536) return true;
+  done = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes) == hipSuccess;
+  return done;
+}
+
 template <typename TA, int KS, int MTR>
 void launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   const Plan& p = c->plan;
   const size_t lds = sizeof(double) * kRcCols * 4 * KS;
-  hipLaunchKernelGGL((recon_mfma_kernel<TA, KS, MTR>), dim3((unsigned)p.rc.size()),
-                     dim3(kRcThreads), lds, s, c->at<BlkInfo>(p.off_blk),
-                     c->at<RcItem>(p.off_rc), c->desc.k_max, c->at<int32_t>(p.off_S),
-                     c->at<int32_t>(p.off_k), P, static_cast<TA*>(skel),
-                     c->at<double>(p.off_rcpart));
+  auto launch = [&](auto kern) {
+    if (!allow_lds(kern, lds)) return;
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), lds, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.k_max,
+                       c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
+                       static_cast<TA*>(skel), c->at<double>(p.off_rcpart));
+  };
+  if (c->all_vec4) launch(recon_mfma_kernel<TA, KS, MTR, true>);
+  else launch(recon_mfma_kernel<TA, KS, MTR, false>);
 }
 
 // single-precision data on the mixed path: split-bfloat16 error pass
 template <int KS32, int MTR>
 void launch_recon_bf16_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   const Plan& p = c->plan;
-  hipLaunchKernelGGL((recon_bf16x3_kernel<KS32, MTR>), dim3((unsigned)p.rc.size()),
-                     dim3(kRcThreads), 0, s, c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc),
-                     c->desc.k_max, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
-                     static_cast<float*>(skel), c->at<double>(p.off_rcpart));
+  const size_t lds = sizeof(__bf16) * 3 * kRcCols * 32 * KS32;
+  auto launch = [&](auto kern) {
+    if (!allow_lds(kern, lds)) return;
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), lds, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.k_max,
+                       c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
+                       static_cast<float*>(skel), c->at<double>(p.off_rcpart));
+  };
+  if (c->all_vec4) launch(recon_bf16x3_kernel<KS32, MTR, true>);
+  else launch(recon_bf16x3_kernel<KS32, MTR, false>);
 }
 
 template <typename TA>
@@ -460,7 +472,7 @@ void launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   if constexpr (sizeof(TA) == 4) {
     if (c->plan.sh.rc_bf16) {
       switch (c->plan.sh.KS32) {
-        case 1: launch_recon_bf16_t<1, 4>(c, P, skel, s); break;
+        case 1: launch_recon_bf16_t<1, 2>(c, P, skel, s); break;
         case 2: launch_recon_bf16_t<2, 2>(c, P, skel, s); break;
         default: launch_recon_bf16_t<3, 2>(c, P, skel, s); break;
       }
@@ -470,8 +482,8 @@ void launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   switch (c->plan.sh.KS) {
     case 1: launch_recon_t<TA, 1, 4>(c, P, skel, s); break;
     case 2: launch_recon_t<TA, 2, 4>(c, P, skel, s); break;
-    case 4: launch_recon_t<TA, 4, 4>(c, P, skel, s); break;
-    case 8: launch_recon_t<TA, 8, 4>(c, P, skel, s); break;
+    case 4: launch_recon_t<TA, 4, 2>(c, P, skel, s); break;
+    case 8: launch_recon_t<TA, 8, 2>(c, P, skel, s); break;
     case 12: launch_recon_t<TA, 12, 2>(c, P, skel, s); break;
     case 16: launch_recon_t<TA, 16, 2>(c, P, skel, s); break;
     default: launch_recon_t<TA, 24, 1>(c, P, skel, s); break;
@@ -556,6 +568,10 @@ extern "C" spid_status spid_bind_A(spid_ctx* c, const void* const* h_block_ptrs,
     bi.lda = h_lda[b];
     bi.vec_ok = (((uintptr_t)bi.A % 16) == 0 && ((bi.lda * (int64_t)es) % 16) == 0) ? 1 : 0;
   }
+  c->all_vec = true;
+  for (const BlkInfo& bi : p.blk) c->all_vec = c->all_vec && bi.vec_ok;
+  c->all_vec4 = c->all_vec;
+  for (const BlkInfo& bi : p.blk) c->all_vec4 = c->all_vec4 && (bi.m % 4 == 0);
   hipError_t e = hipMemcpy(c->ws + p.off_blk, p.blk.data(), sizeof(BlkInfo) * p.blk.size(),
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(SPID_EHIP, "spid_bind_A: %s", hipGetErrorString(e));

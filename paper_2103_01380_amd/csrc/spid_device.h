@@ -10,7 +10,9 @@ namespace spid {
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
@@ -91,6 +93,15 @@ __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 // e4m3 byte of a float (hardware conversion, round to nearest even).
 __device__ __forceinline__ uint32_t to_e4m3_byte(float x) {
   return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xffu;
+}
+
+// Workgroup barrier that orders LDS only: waits for this wave's LDS accesses
+// (lgkmcnt) and not for outstanding global loads, so prefetched A values stay
+// in flight across it.  The "memory" clobber keeps the compiler from moving
+// memory accesses across the barrier; register uses of in-flight loads still
+// get their own vmcnt waits from the compiler.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // ---------------------------------------------------------------------------

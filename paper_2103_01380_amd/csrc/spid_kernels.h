@@ -12,6 +12,8 @@
 //   recon_reduce      fixed-order per-block sums of the row-tile partials.
 #pragma once
 
+#include <type_traits>
+
 #include "spid_device.h"
 
 namespace spid {
@@ -52,36 +54,63 @@ constexpr int kSkThreads = 256;   // 4 waves
 constexpr int kKC = 32;           // rows per sketch chunk
 constexpr int kOmStride = kKC + 2;  // LDS row stride (doubles) of the Omega tile
 
-// Load 8 consecutive rows [row, row+8) of column `col` of block (base, lda)
-// as doubles; rows at or past `rend` read as zero.
-template <typename TA>
-__device__ __forceinline__ void load8(const TA* __restrict__ base, int64_t lda, int64_t col,
-                                      int64_t row, int64_t rend, bool vec, double out[8]) {
-  const TA* p = base + col * lda + row;
-  if (vec && row + 8 <= rend) {
-    if constexpr (sizeof(TA) == 8) {
-      const f64x2* q = reinterpret_cast<const f64x2*>(p);
+// Loads of A for the sketch kernels.  Full chunks use straight-line loads
+// (no branches: the column is clamped to a valid one and the values of an
+// invalid column are zeroed by selection), so the compiler can keep the
+// prefetched chunk in flight with partial vmcnt waits; only the ragged last
+// chunk of a work item takes the checked path.
+//
+// A lane reads NP pieces of W consecutive rows of one column, piece p
+// starting at row + p * STEP.  The four lanes sharing a column (g = 0..3)
+// start at row + W g, so every load instruction of a 16-column group reads
+// one contiguous run of 4 W elements per column.  VEC: aligned column starts
+// (16 bytes) and W-aligned rows, so the pieces are 8- or 16-byte vectors.
+template <typename TA, int NP, int W, int STEP, bool VEC, typename TO>
+__device__ __forceinline__ void load_pieces_full(const TA* __restrict__ cb, int64_t row, bool ok,
+                                                 TO out[NP * W]) {
+  constexpr int kBytes = W * (int)sizeof(TA);
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const f64x2 v = __builtin_nontemporal_load(q + h);
-        out[2 * h] = v[0];
-        out[2 * h + 1] = v[1];
+  for (int pc = 0; pc < NP; ++pc) {
+    const TA* p = cb + row + pc * STEP;
+    if constexpr (VEC && kBytes % 16 == 0 && sizeof(TA) == 8) {
+#pragma unroll
+      for (int h = 0; h < W / 2; ++h) {
+        const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p) + h);
+        out[W * pc + 2 * h] = ok ? (TO)v[0] : (TO)0;
+        out[W * pc + 2 * h + 1] = ok ? (TO)v[1] : (TO)0;
       }
-    } else {
-      const f32x4* q = reinterpret_cast<const f32x4*>(p);
+    } else if constexpr (VEC && kBytes % 16 == 0 && sizeof(TA) == 4) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const f32x4 v = __builtin_nontemporal_load(q + h);
-        out[4 * h] = v[0];
-        out[4 * h + 1] = v[1];
-        out[4 * h + 2] = v[2];
-        out[4 * h + 3] = v[3];
+      for (int h = 0; h < W / 4; ++h) {
+        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p) + h);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[W * pc + 4 * h + e] = ok ? (TO)v[e] : (TO)0;
+      }
+    } else if constexpr (VEC && kBytes == 8 && sizeof(TA) == 4) {
+      const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+      out[2 * pc] = ok ? (TO)v[0] : (TO)0;
+      out[2 * pc + 1] = ok ? (TO)v[1] : (TO)0;
+    } else {
+#pragma unroll
+      for (int e = 0; e < W; ++e) {
+        const TA v = __builtin_nontemporal_load(p + e);
+        out[W * pc + e] = ok ? (TO)v : (TO)0;
       }
     }
-  } else {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) out[e] = (row + e < rend) ? (double)p[e] : 0.0;
   }
+}
+
+// The same for a ragged chunk: rows at or past `rend` read as zero.
+template <typename TA, int NP, int W, int STEP, typename TO>
+__device__ __forceinline__ void load_pieces_tail(const TA* __restrict__ cb, int64_t row,
+                                                 int64_t rend, bool ok, TO out[NP * W]) {
+#pragma unroll
+  for (int pc = 0; pc < NP; ++pc)
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const int64_t r = row + pc * STEP + e;
+      out[W * pc + e] = (ok && r < rend) ? (TO)cb[r] : (TO)0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -101,33 +130,59 @@ __device__ __forceinline__ void gen_omega_chunk(TO* __restrict__ om, int l, uint
 }
 
 // ---------------------------------------------------------------------------
+// Common set-up of a sketch work item: the lane's columns (clamped to a valid
+// column, with a validity flag), the updated column window, the Omega key.
+// ---------------------------------------------------------------------------
+template <typename TA, int TN>
+struct SkLane {
+  const TA* cb[TN];   // column starts (clamped)
+  bool ok[TN];        // column inside the block and inside [j0, j1)
+  int col[TN];
+};
+
+template <typename TA, int TN>
+__device__ __forceinline__ bool sk_setup(const BlkInfo& bi, const SkItem& it, int cwave, int r16,
+                                         int span, int j0, int j1, SkLane<TA, TN>& ln) {
+  const int clo = max(j0, 0), chi = min(j1, bi.n);
+  if (it.c0 >= chi || it.c0 + span <= clo) return false;   // whole tile outside (uniform)
+  const TA* A = static_cast<const TA*>(bi.A);
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int col = cwave + 16 * u + r16;
+    ln.col[u] = col;
+    ln.ok[u] = col >= clo && col < chi;
+    ln.cb[u] = A + (int64_t)(ln.ok[u] ? col : clo) * bi.lda;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // Sketch, double precision: Y = Omega A on v_mfma_f64_16x16x4.
 // Workgroup = NW waves; wave w owns columns c0 + 16*TN*w + [0, 16*TN); every
 // wave covers all MT*16 sketch rows.  Per 32-row chunk each lane holds rows
-// 8g..8g+7 (g = lane/16) of one column per 16-column tile, and eight MFMA
-// k-steps consume them (step s pairs A row 8g+s with Omega column 8g+s).
-// Software pipeline: while the MFMAs of chunk c run, the A loads of chunk c+1
-// are in flight and the workgroup generates Omega of chunk c+1 into the other
-// LDS buffer; one barrier per chunk.
+// 8h + 2g + e (h = 0..3, e = 0..1, g = lane/16) of one column per 16-column
+// tile, so each load instruction reads 64 contiguous bytes per column, and
+// eight MFMA k-steps consume them (step 2h+e pairs that A row with the same
+// Omega column).
+// Software pipeline over the full chunks (two register buffers, two LDS
+// buffers): while chunk c's MFMAs run, chunk c+1's loads are in flight and the
+// workgroup generates chunk c+1's Omega; one LDS-only barrier per chunk.  The
+// ragged last chunk is handled after the loop.
 // ---------------------------------------------------------------------------
-template <typename TA, int MT, int TN, int NW>
+template <typename TA, int MT, int TN, int NW, bool VEC>
 __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
     int omega_per_block, int j0, int j1, double* __restrict__ Y, double* __restrict__ part) {
-  __shared__ double om[2][MT * 16 * kOmStride];
+  __shared__ __attribute__((aligned(16))) double om[2][MT * 16 * kOmStride];
   const SkItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r16 = lane & 15;
-  const int ncols = bi.n;
   const int cwave = it.c0 + wave * 16 * TN;
-  // window of columns this call updates
-  const int clo = max(j0, 0), chi = min(j1, ncols);
-  if (it.c0 >= chi || it.c0 + NW * 16 * TN <= clo) return;   // whole tile outside (uniform)
+  SkLane<TA, TN> ln;
+  if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
-  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
-  const bool vec = bi.vec_ok != 0;
   auto ident = [](double x) { return x; };
 
   for (int e = tid; e < 2 * MT * 16 * kOmStride; e += 64 * NW) (&om[0][0])[e] = 0.0;
@@ -138,105 +193,91 @@ __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[t][u] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  auto load_chunk = [&](int64_t k0, double (&av)[TN][8]) {
+  auto load_full = [&](int64_t k0, double (&a)[TN][8]) {
 #pragma unroll
-    for (int u = 0; u < TN; ++u) {
-      const int col = cwave + 16 * u + r16;
-      if (col >= clo && col < chi && k0 < it.r1) {
-        load8<TA>(A, bi.lda, col, k0 + 8 * g, it.r1, vec, av[u]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[u][e] = 0.0;
-      }
-    }
+    for (int u = 0; u < TN; ++u)
+      load_pieces_full<TA, 4, 2, 8, VEC>(ln.cb[u], k0 + 2 * g, ln.ok[u], a[u]);
   };
-
-  double av[TN][8], an[TN][8];
-  load_chunk(it.r0, av);
-  __syncthreads();   // zero fill done before generation writes
-  gen_omega_chunk<double, kOmStride, 64 * NW>(om[0], l, seed, bkey, it.r0, tid, ident);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC) {
-    const int64_t k1 = k0 + kKC;
-    const bool more = k1 < it.r1;
-    if (more) {
-      load_chunk(k1, an);
-      gen_omega_chunk<double, kOmStride, 64 * NW>(om[buf ^ 1], l, seed, bkey, k1, tid, ident);
-    }
+  auto mfma_chunk = [&](const double* __restrict__ omb, double (&a)[TN][8]) {
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       double ov[8];
-      const double* orow = om[buf] + (16 * t + r16) * kOmStride + 8 * g;
+      const double* orow = omb + (16 * t + r16) * kOmStride + 2 * g;
 #pragma unroll
-      for (int s = 0; s < 8; ++s) ov[s] = orow[s];
+      for (int h = 0; h < 4; ++h) {
+        const f64x2 pv = *reinterpret_cast<const f64x2*>(orow + 8 * h);
+        ov[2 * h] = pv[0];
+        ov[2 * h + 1] = pv[1];
+      }
 #pragma unroll
       for (int s = 0; s < 8; ++s)
 #pragma unroll
-        for (int u = 0; u < TN; ++u) acc[t][u] = mfma_f64(ov[s], av[u][s], acc[t][u]);
+        for (int u = 0; u < TN; ++u) acc[t][u] = mfma_f64(ov[s], a[u][s], acc[t][u]);
     }
-    __syncthreads();
-    if (more) {
+  };
+
+  const int64_t nfull = (it.r1 - it.r0) / kKC;
+  const int64_t klast = it.r0 + (nfull - 1) * kKC;      // start of the last full chunk
+  double a0[TN][8], a1[TN][8];
+  __syncthreads();                                      // zero fill before generation
+  if (nfull > 0) {
+    load_full(it.r0, a0);
+    gen_omega_chunk<double, kOmStride, 64 * NW>(om[0], l, seed, bkey, it.r0, tid, ident);
+  }
+  lds_barrier();
+  // one pipeline step: prefetch (clamped: redundant on the last chunk), Omega of
+  // the next chunk, MFMAs of this chunk
+  auto step = [&](double (&cur)[TN][8], double (&nxt)[TN][8], int b, int64_t k0) {
+    const int64_t k1 = min(k0 + kKC, klast);
+    load_full(k1, nxt);
+    gen_omega_chunk<double, kOmStride, 64 * NW>(om[b ^ 1], l, seed, bkey, k1, tid, ident);
+    mfma_chunk(om[b], cur);
+    lds_barrier();
+  };
+  int64_t c = 0;
+  for (; c + 2 <= nfull; c += 2) {
+    step(a0, a1, 0, it.r0 + c * kKC);
+    step(a1, a0, 1, it.r0 + (c + 1) * kKC);
+  }
+  if (c < nfull) step(a0, a1, 0, it.r0 + c * kKC);
+  // ragged last chunk
+  const int64_t kt = it.r0 + nfull * kKC;
+  if (kt < it.r1) {
+    const int b = (int)(nfull & 1);
+    gen_omega_chunk<double, kOmStride, 64 * NW>(om[b], l, seed, bkey, kt, tid, ident);
 #pragma unroll
-      for (int u = 0; u < TN; ++u)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[u][e] = an[u][e];
-    }
-    buf ^= 1;
+    for (int u = 0; u < TN; ++u)
+      load_pieces_tail<TA, 4, 2, 8>(ln.cb[u], kt + 2 * g, it.r1, ln.ok[u], a0[u]);
+    lds_barrier();
+    mfma_chunk(om[b], a0);
   }
   // epilogue: lane holds rows 16t + g + 4v of column cwave + 16u + r16
-  double* dst;
-  if (bi.nsplit == 1) {
-    dst = Y + bi.y_off;
-  } else {
-    dst = part + bi.part_off + (int64_t)it.split * ncols * l;
-  }
+  double* dst = (bi.nsplit == 1) ? (Y + bi.y_off)
+                                 : (part + bi.part_off + (int64_t)it.split * bi.n * l);
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
-    const int col = cwave + 16 * u + r16;
-    if (col < clo || col >= chi) continue;
+    if (!ln.ok[u]) continue;
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * t + g + 4 * v;
-        if (row < l) dst[(int64_t)col * l + row] = acc[t][u][v];
+        if (row < l) dst[(int64_t)ln.col[u] * l + row] = acc[t][u][v];
       }
   }
-}
-
-// Load 8 consecutive rows [row, row+8) of column `col` as floats (rows at or
-// past `rend` read as zero).
-template <typename TA>
-__device__ __forceinline__ void load8f(const TA* __restrict__ base, int64_t lda, int64_t col,
-                                       int64_t row, int64_t rend, bool vec, float out[8]) {
-  const TA* p = base + col * lda + row;
-  if constexpr (sizeof(TA) == 4) {
-    if (vec && row + 8 <= rend) {
-      const f32x4* q = reinterpret_cast<const f32x4*>(p);
-      const f32x4 v0 = __builtin_nontemporal_load(q);
-      const f32x4 v1 = __builtin_nontemporal_load(q + 1);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        out[e] = v0[e];
-        out[4 + e] = v1[e];
-      }
-      return;
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < 8; ++e) out[e] = (row + e < rend) ? (float)p[e] : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
 // Sketch, bfloat16 (FP32 accumulation): Omega rounded to nearest-even
 // bfloat16 in LDS; A split into `terms` bfloat16 terms in registers
 // (hi = bf16(a), lo = bf16(a - hi), lo2 = bf16(a - hi - lo));
-// v_mfma_f32_16x16x32_bf16.  Lane (g, r16) supplies rows 8g..8g+7 of its
-// column as the 8 k-values of one MFMA; Omega row 16t+r16 supplies the same 8
-// k-values.  Same software pipeline as the double-precision kernel.
+// v_mfma_f32_16x16x32_bf16.  Lane (g, r16) supplies rows 16h + 4g + e
+// (h = 0..1, e = 0..3) of its column as the 8 k-values of one MFMA (64
+// contiguous bytes per column and load instruction); Omega row 16t+r16
+// supplies the same rows.  Same software pipeline as the double-precision
+// kernel.
 // ---------------------------------------------------------------------------
-template <typename TA, int MT, int TN, int NW>
+template <typename TA, int MT, int TN, int NW, bool VEC>
 __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
     int omega_per_block, int j0, int j1, int terms, float* __restrict__ Y,
@@ -248,13 +289,10 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r16 = lane & 15;
-  const int ncols = bi.n;
   const int cwave = it.c0 + wave * 16 * TN;
-  const int clo = max(j0, 0), chi = min(j1, ncols);
-  if (it.c0 >= chi || it.c0 + NW * 16 * TN <= clo) return;
+  SkLane<TA, TN> ln;
+  if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
-  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
-  const bool vec = bi.vec_ok != 0;
   auto to_bf = [](double x) { return to_bf16((float)rne_bf16(x)); };
 
   for (int e = tid; e < 2 * MT * 16 * kS; e += 64 * NW) (&om[0][0])[e] = (__bf16)0.0f;
@@ -265,41 +303,25 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  auto load_chunk = [&](int64_t k0, float (&av)[TN][8]) {
+  auto load_full = [&](int64_t k0, float (&a)[TN][8]) {
 #pragma unroll
-    for (int u = 0; u < TN; ++u) {
-      const int col = cwave + 16 * u + r16;
-      if (col >= clo && col < chi && k0 < it.r1) {
-        load8f<TA>(A, bi.lda, col, k0 + 8 * g, it.r1, vec, av[u]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[u][e] = 0.0f;
-      }
-    }
+    for (int u = 0; u < TN; ++u)
+      load_pieces_full<TA, 2, 4, 16, VEC>(ln.cb[u], k0 + 4 * g, ln.ok[u], a[u]);
   };
-
-  float av[TN][8], an[TN][8];
-  load_chunk(it.r0, av);
-  __syncthreads();
-  gen_omega_chunk<__bf16, kS, 64 * NW>(om[0], l, seed, bkey, it.r0, tid, to_bf);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC) {
-    const int64_t k1 = k0 + kKC;
-    const bool more = k1 < it.r1;
-    if (more) {
-      load_chunk(k1, an);
-      gen_omega_chunk<__bf16, kS, 64 * NW>(om[buf ^ 1], l, seed, bkey, k1, tid, to_bf);
-    }
+  auto mfma_chunk = [&](const __bf16* __restrict__ omb, float (&a)[TN][8]) {
     bf16x8 oa[MT];
 #pragma unroll
-    for (int t = 0; t < MT; ++t)
-      oa[t] = *reinterpret_cast<const bf16x8*>(om[buf] + (16 * t + r16) * kS + 8 * g);
+    for (int t = 0; t < MT; ++t) {
+      const __bf16* orow = omb + (16 * t + r16) * kS + 4 * g;
+      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(orow);
+      const bf16x4 hi = *reinterpret_cast<const bf16x4*>(orow + 16);
+      oa[t] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
       float rem[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rem[e] = av[u][e];
+      for (int e = 0; e < 8; ++e) rem[e] = a[u][e];
       for (int h = 0; h < terms; ++h) {
         bf16x8 bt;
 #pragma unroll
@@ -312,27 +334,51 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
         for (int t = 0; t < MT; ++t) acc[t][u] = mfma_bf16(oa[t], bt, acc[t][u]);
       }
     }
-    __syncthreads();
-    if (more) {
+  };
+
+  const int64_t nfull = (it.r1 - it.r0) / kKC;
+  const int64_t klast = it.r0 + (nfull - 1) * kKC;
+  float a0[TN][8], a1[TN][8];
+  __syncthreads();
+  if (nfull > 0) {
+    load_full(it.r0, a0);
+    gen_omega_chunk<__bf16, kS, 64 * NW>(om[0], l, seed, bkey, it.r0, tid, to_bf);
+  }
+  lds_barrier();
+  auto step = [&](float (&cur)[TN][8], float (&nxt)[TN][8], int b, int64_t k0) {
+    const int64_t k1 = min(k0 + kKC, klast);
+    load_full(k1, nxt);
+    gen_omega_chunk<__bf16, kS, 64 * NW>(om[b ^ 1], l, seed, bkey, k1, tid, to_bf);
+    mfma_chunk(om[b], cur);
+    lds_barrier();
+  };
+  int64_t c = 0;
+  for (; c + 2 <= nfull; c += 2) {
+    step(a0, a1, 0, it.r0 + c * kKC);
+    step(a1, a0, 1, it.r0 + (c + 1) * kKC);
+  }
+  if (c < nfull) step(a0, a1, 0, it.r0 + c * kKC);
+  const int64_t kt = it.r0 + nfull * kKC;
+  if (kt < it.r1) {
+    const int b = (int)(nfull & 1);
+    gen_omega_chunk<__bf16, kS, 64 * NW>(om[b], l, seed, bkey, kt, tid, to_bf);
 #pragma unroll
-      for (int u = 0; u < TN; ++u)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[u][e] = an[u][e];
-    }
-    buf ^= 1;
+    for (int u = 0; u < TN; ++u)
+      load_pieces_tail<TA, 2, 4, 16>(ln.cb[u], kt + 4 * g, it.r1, ln.ok[u], a0[u]);
+    lds_barrier();
+    mfma_chunk(om[b], a0);
   }
   float* dst = (bi.nsplit == 1) ? (Y + bi.y_off)
-                                : (part + bi.part_off + (int64_t)it.split * ncols * l);
+                                : (part + bi.part_off + (int64_t)it.split * bi.n * l);
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
-    const int col = cwave + 16 * u + r16;
-    if (col < clo || col >= chi) continue;
+    if (!ln.ok[u]) continue;
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * t + 4 * g + v;
-        if (row < l) dst[(int64_t)col * l + row] = acc[t][u][v];
+        if (row < l) dst[(int64_t)ln.col[u] * l + row] = acc[t][u][v];
       }
   }
 }
@@ -358,44 +404,21 @@ __device__ __forceinline__ void gen_omega_chunk_e4m3(uint8_t* __restrict__ om, i
   for (int e = tid; e < npairs * kKC8; e += NTHR) {
     const int q = e / kKC8, kk = e - q * kKC8;
     const double2 z = omega_pair(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q);
-    om[(2 * q) * kOm8Stride + kk] = (uint8_t)to_e4m3_byte((float)rne_e4m3(z.x));
-    if (2 * q + 1 < l) om[(2 * q + 1) * kOm8Stride + kk] = (uint8_t)to_e4m3_byte((float)rne_e4m3(z.y));
+    // chunk row kk = 64 h + 16 w + 4 g + x sits at k = 64 h + 16 g + 4 w + x
+    const int kpos = (kk & ~63) | (((kk >> 2) & 3) << 4) | (((kk >> 4) & 3) << 2) | (kk & 3);
+    om[(2 * q) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte((float)rne_e4m3(z.x));
+    if (2 * q + 1 < l)
+      om[(2 * q + 1) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte((float)rne_e4m3(z.y));
   }
 }
 
 // The f8f6f4 16x16x128 operand layout (checked on the device): lane group g
 // = lane/16 holds k = 16g..16g+15 in bytes 0..15 and k = 64+16g..64+16g+15 in
 // bytes 16..31; the E8M0 scale of K block kb (k = 32kb..32kb+31) for row or
-// column c is taken from lane c + 16 kb.  Chunk row r of the sketch is k = r.
-// Load the lane's two 16-row runs of one column as floats (rows at or past
-// `rend` read as zero).
-template <typename TA>
-__device__ __forceinline__ void load32f(const TA* __restrict__ base, int64_t lda, int64_t col,
-                                        int64_t k0, int g, int64_t rend, bool vec,
-                                        float out[32]) {
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int64_t row = k0 + 64 * h + 16 * g;
-    const TA* p = base + col * lda + row;
-    bool done = false;
-    if constexpr (sizeof(TA) == 4) {
-      if (vec && row + 16 <= rend) {
-        const f32x4* q = reinterpret_cast<const f32x4*>(p);
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const f32x4 v = __builtin_nontemporal_load(q + w);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) out[16 * h + 4 * w + e] = v[e];
-        }
-        done = true;
-      }
-    }
-    if (!done) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) out[16 * h + e] = (row + e < rend) ? (float)p[e] : 0.0f;
-    }
-  }
-}
+// column c is taken from lane c + 16 kb.  Chunk row r = 64h + 16w + 4g + x
+// is placed at k = 64h + 16g + 4w + x, so lane g's sixteen k-values of a half
+// are rows 4g..4g+3 of each 16-row group (64 contiguous bytes per column and
+// load instruction); Omega is stored in LDS at the same k positions.
 
 // Power-of-two exponent E with amax * 2^-E < 256 (<= 448, the e4m3 maximum);
 // -127 for an all-zero block.
@@ -452,7 +475,7 @@ __device__ __forceinline__ i32x8 fp8_term(float res[32], int g, int& scale_byte)
   return out;
 }
 
-template <typename TA, int MT, int TN, int NW>
+template <typename TA, int MT, int TN, int NW, bool VEC>
 __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
     int omega_per_block, int j0, int j1, int terms, float* __restrict__ Y,
@@ -463,13 +486,10 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r16 = lane & 15;
-  const int ncols = bi.n;
   const int cwave = it.c0 + wave * 16 * TN;
-  const int clo = max(j0, 0), chi = min(j1, ncols);
-  if (it.c0 >= chi || it.c0 + NW * 16 * TN <= clo) return;
+  SkLane<TA, TN> ln;
+  if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
-  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
-  const bool vec = bi.vec_ok != 0;
 
   for (int e = tid; e < 2 * MT * 16 * kOm8Stride; e += 64 * NW) (&om[0][0])[e] = 0;
 
@@ -479,33 +499,19 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  auto load_chunk = [&](int64_t k0, float (&av)[TN][32]) {
+  // the lane's two 16-row runs: k0 + 16g and k0 + 64 + 16g
+  auto load_full = [&](int64_t k0, float (&a)[TN][32]) {
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
-      const int col = cwave + 16 * u + r16;
-      if (col >= clo && col < chi && k0 < it.r1) {
-        load32f<TA>(A, bi.lda, col, k0, g, it.r1, vec, av[u]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 32; ++e) av[u][e] = 0.0f;
-      }
+      load_pieces_full<TA, 4, 4, 16, VEC>(ln.cb[u], k0 + 4 * g, ln.ok[u], a[u]);
+      load_pieces_full<TA, 4, 4, 16, VEC>(ln.cb[u], k0 + 64 + 4 * g, ln.ok[u], a[u] + 16);
     }
   };
-
-  float av[TN][32];
-  __syncthreads();
-  gen_omega_chunk_e4m3<64 * NW>(om[0], l, seed, bkey, it.r0, tid);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t k0 = it.r0; k0 < it.r1; k0 += kKC8) {
-    const int64_t k1 = k0 + kKC8;
-    const bool more = k1 < it.r1;
-    load_chunk(k0, av);
-    if (more) gen_omega_chunk_e4m3<64 * NW>(om[buf ^ 1], l, seed, bkey, k1, tid);
+  auto mfma_chunk = [&](const uint8_t* __restrict__ omb, float (&a)[TN][32]) {
     i32x8 oa[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      const uint8_t* orow = om[buf] + (16 * t + r16) * kOm8Stride;
+      const uint8_t* orow = omb + (16 * t + r16) * kOm8Stride;
       const i32x4 lo = *reinterpret_cast<const i32x4*>(orow + 16 * g);
       const i32x4 hi = *reinterpret_cast<const i32x4*>(orow + 64 + 16 * g);
       oa[t] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
@@ -514,26 +520,58 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
     for (int u = 0; u < TN; ++u) {
       for (int h = 0; h < terms; ++h) {
         int sb;
-        const i32x8 bt = fp8_term(av[u], g, sb);
+        const i32x8 bt = fp8_term(a[u], g, sb);
 #pragma unroll
         for (int t = 0; t < MT; ++t) acc[t][u] = mfma_fp8_scaled(oa[t], bt, acc[t][u], 127, sb);
       }
     }
-    __syncthreads();
-    buf ^= 1;
+  };
+
+  const int64_t nfull = (it.r1 - it.r0) / kKC8;
+  const int64_t klast = it.r0 + (nfull - 1) * kKC8;
+  float a0[TN][32], a1[TN][32];
+  __syncthreads();
+  if (nfull > 0) {
+    load_full(it.r0, a0);
+    gen_omega_chunk_e4m3<64 * NW>(om[0], l, seed, bkey, it.r0, tid);
+  }
+  lds_barrier();
+  auto step = [&](float (&cur)[TN][32], float (&nxt)[TN][32], int b, int64_t k0) {
+    const int64_t k1 = min(k0 + kKC8, klast);
+    load_full(k1, nxt);
+    gen_omega_chunk_e4m3<64 * NW>(om[b ^ 1], l, seed, bkey, k1, tid);
+    mfma_chunk(om[b], cur);
+    lds_barrier();
+  };
+  int64_t c = 0;
+  for (; c + 2 <= nfull; c += 2) {
+    step(a0, a1, 0, it.r0 + c * kKC8);
+    step(a1, a0, 1, it.r0 + (c + 1) * kKC8);
+  }
+  if (c < nfull) step(a0, a1, 0, it.r0 + c * kKC8);
+  const int64_t kt = it.r0 + nfull * kKC8;
+  if (kt < it.r1) {
+    const int b = (int)(nfull & 1);
+    gen_omega_chunk_e4m3<64 * NW>(om[b], l, seed, bkey, kt, tid);
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      load_pieces_tail<TA, 4, 4, 16>(ln.cb[u], kt + 4 * g, it.r1, ln.ok[u], a0[u]);
+      load_pieces_tail<TA, 4, 4, 16>(ln.cb[u], kt + 64 + 4 * g, it.r1, ln.ok[u], a0[u] + 16);
+    }
+    lds_barrier();
+    mfma_chunk(om[b], a0);
   }
   float* dst = (bi.nsplit == 1) ? (Y + bi.y_off)
-                                : (part + bi.part_off + (int64_t)it.split * ncols * l);
+                                : (part + bi.part_off + (int64_t)it.split * bi.n * l);
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
-    const int col = cwave + 16 * u + r16;
-    if (col < clo || col >= chi) continue;
+    if (!ln.ok[u]) continue;
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * t + 4 * g + v;
-        if (row < l) dst[(int64_t)col * l + row] = acc[t][u][v];
+        if (row < l) dst[(int64_t)ln.col[u] * l + row] = acc[t][u][v];
       }
   }
 }
@@ -1009,44 +1047,14 @@ __global__ __launch_bounds__(64) void coeffs_kernel(const BlkInfo* __restrict__ 
 }
 
 constexpr int kRcThreads = 256;
-constexpr int kRcCols = 64;
+constexpr int kRcCols = 256;   // non-skeleton columns whose coefficients are staged at once
 
-// ---------------------------------------------------------------------------
-// Reconstruction error on the matrix cores (double precision).
-// Ahat(rows, cols) = A(rows, S) P(:, cols) with v_mfma_f64_16x16x4: the
-// skeleton A(rows, S) is the A operand (16 rows x 4 selected columns per
-// k-step), P the B operand (4 x 16 columns), Ahat accumulates in D.  Rows
-// inside a 16-row tile are permuted so that lane (g, c) receives D rows
-// 4g..4g+3 (row = 4 (rho % 4) + rho / 4 for tile row rho): each lane then
-// loads 4 consecutive entries of column c for the residual (coalesced).
-// Work item = 64*MTR*... rows: a workgroup of 4 waves covers 4 * 16 * MTR
-// rows; every wave streams all non-skeleton columns 16 at a time, with the
-// coefficients of a 64-column chunk staged in LDS.  KS = k-steps (k_max / 4
-// rounded up) held in registers per 16-row tile.
-// ---------------------------------------------------------------------------
-template <typename TA, int KS, int MTR>
-__global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
-    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max,
-    const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
-    const double* __restrict__ P, TA* __restrict__ skel, double* __restrict__ part) {
-  extern __shared__ double p_lds[];   // [kRcCols][kp]
-  __shared__ double red[8];
-  __shared__ int cols[1024];
-  __shared__ unsigned char is_sel[1024];
-  __shared__ int wcount[4];
-  const RcItem it = items[blockIdx.x];
-  const BlkInfo bi = blks[it.blk];
-  const int n = bi.n;
-  const int k = k_ws[it.blk];
-  const int kp = 4 * KS;
-  const int32_t* S = S_ws + (int64_t)it.blk * k_max;
-  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
-  const double* __restrict__ Pb = P + bi.p_off;
+// Compact the non-skeleton columns of a block into `cols` (ascending j);
+// returns their number.  All threads of the workgroup call it.
+__device__ __forceinline__ int rc_compact_columns(int n, int k, const int32_t* __restrict__ S,
+                                                  unsigned char* is_sel, int* cols,
+                                                  int* wcount) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, c16 = lane & 15;
-  // 16-byte loads need aligned column starts and a 4-row aligned tile start
-  const bool vec = bi.vec_ok != 0 && (it.i0 % 4) == 0;
-
   for (int j = tid; j < n; j += kRcThreads) is_sel[j] = 0;
   __syncthreads();
   if (tid < k) is_sel[S[tid]] = 1;
@@ -1067,12 +1075,109 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
     ncols += tot;
     __syncthreads();
   }
+  return ncols;
+}
 
-  // rows of this wave: tile mt covers rbase + 16 mt + [0,16)
+// Four consecutive rows i0..i0+3 (i0 a multiple of 4) of one column for the
+// residual, rows at or past m read as zero.  VEC (16-byte aligned columns and
+// m a multiple of 4): a group is entirely inside or entirely outside the
+// block, so one vector load from a clamped address plus a selection covers
+// both; otherwise four clamped scalar loads.  Branch-free either way.
+template <typename TA, bool VEC>
+__device__ __forceinline__ void rc_load4(const TA* __restrict__ colp, int64_t i0, int64_t m,
+                                         bool ok, double out[4]) {
+  if constexpr (VEC) {
+    const bool in = ok && i0 < m;
+    const TA* src = colp + (in ? i0 : 0);
+    if constexpr (sizeof(TA) == 8) {
+      const f64x2 x0 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src));
+      const f64x2 x1 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src) + 1);
+      out[0] = in ? x0[0] : 0.0;
+      out[1] = in ? x0[1] : 0.0;
+      out[2] = in ? x1[0] : 0.0;
+      out[3] = in ? x1[1] : 0.0;
+    } else {
+      const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[v] = in ? (double)x[v] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = min(i0 + v, m - 1);
+      const double x = (double)colp[i];
+      out[v] = (ok && i0 + v < m) ? x : 0.0;
+    }
+  }
+}
+
+// Rows i0, i0+1, i0+8, i0+9 (i0 even) of one column for the FP64 residual,
+// rows at or past m read as zero.  VEC (16-byte aligned columns, m a multiple
+// of 4): each pair is entirely inside or outside the block, one vector load
+// from a clamped address plus a selection; otherwise clamped scalar loads.
+template <typename TA, bool VEC>
+__device__ __forceinline__ void rc_load_pairs(const TA* __restrict__ colp, int64_t i0, int64_t m,
+                                              bool ok, double out[4]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t r = i0 + 8 * h;
+    if constexpr (VEC && sizeof(TA) == 8) {
+      const bool in = ok && r < m;
+      const f64x2 x = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(colp + (in ? r : 0)));
+      out[2 * h] = in ? x[0] : 0.0;
+      out[2 * h + 1] = in ? x[1] : 0.0;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int64_t i = min(r + e, m - 1);
+        const double x = (double)colp[i];
+        out[2 * h + e] = (ok && r + e < m) ? x : 0.0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction error on the matrix cores (double precision).
+// Ahat(rows, cols) = A(rows, S) P(:, cols) with v_mfma_f64_16x16x4: the
+// skeleton A(rows, S) is the A operand (16 rows x 4 selected columns per
+// k-step), P the B operand (4 x 16 columns), Ahat accumulates in D.  Rows
+// inside a 16-row tile are permuted (tile row rho -> 2 (rho % 4) +
+// (rho / 4) % 2 + 8 (rho / 8)) so that lane (g, c) receives D rows 2g, 2g+1,
+// 8+2g, 9+2g of column c: the residual loads are two pairs per lane, and the
+// four lanes of a column read 64 contiguous bytes per load instruction.
+// A workgroup of 4 waves covers 4 * 16 * MTR rows; each wave streams all
+// non-skeleton columns 16 at a time, the next 16 columns' loads in flight
+// while the current ones are reduced; the coefficients of up to kRcCols
+// columns are staged in LDS.  KS = k-steps (k_max / 4 rounded up).
+// Dynamic LDS: kRcCols * 4 * KS doubles.
+// ---------------------------------------------------------------------------
+template <typename TA, int KS, int MTR, bool VEC>
+__global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
+    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max,
+    const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
+    const double* __restrict__ P, TA* __restrict__ skel, double* __restrict__ part) {
+  extern __shared__ double p_lds[];   // [kRcCols][kp]
+  __shared__ double red[8];
+  __shared__ int cols[1024];
+  __shared__ unsigned char is_sel[1024];
+  __shared__ int wcount[4];
+  const RcItem it = items[blockIdx.x];
+  const BlkInfo bi = blks[it.blk];
+  const int n = bi.n;
+  const int k = k_ws[it.blk];
+  constexpr int kp = 4 * KS;
+  const int32_t* S = S_ws + (int64_t)it.blk * k_max;
+  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
+  const double* __restrict__ Pb = P + bi.p_off;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int ncols = rc_compact_columns(n, k, S, is_sel, cols, wcount);
+
   const int64_t rbase = it.i0 + (int64_t)wave * 16 * MTR;
-  // A operand: lane supplies tile row rho = c16 -> actual row 4 (rho % 4) + rho / 4,
-  // k-slot g of step s -> selected column 4 s + g
-  const int arow = 4 * (c16 & 3) + (c16 >> 2);
+  // A operand: lane supplies tile row rho = c16 -> actual row
+  // 2 (rho % 4) + (rho / 4) % 2 + 8 (rho / 8); k-slot g of step s -> selected column 4 s + g
+  const int arow = 2 * (c16 & 3) + ((c16 >> 2) & 1) + 8 * (c16 >> 3);
   double as[MTR][KS];
   double a2 = 0.0, e2 = 0.0;
 #pragma unroll
@@ -1091,63 +1196,59 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
     }
   }
 
-  for (int c0 = 0; c0 < ncols; c0 += kRcCols) {
-    const int cc = min(kRcCols, ncols - c0);
-    for (int e = tid; e < kRcCols * kp; e += kRcThreads) {
-      const int q = e / kp, t = e - q * kp;
-      p_lds[e] = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
-    }
-    __syncthreads();
-    for (int q0 = 0; q0 < cc; q0 += 16) {
-      const int q = q0 + c16;
-      const bool cok = q < cc;
-      const int64_t j = cok ? cols[c0 + q] : 0;
-      // residual operands: rows rbase + 16 mt + 4 g + v of column j
-      double av[MTR][4];
+  {
+    constexpr bool FAST = VEC;
+    for (int c0 = 0; c0 < ncols; c0 += kRcCols) {
+      const int cc = min(kRcCols, ncols - c0);
+      for (int e = tid; e < kRcCols * kp; e += kRcThreads) {
+        const int q = e / kp, t = e - q * kp;
+        p_lds[e] = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
+      }
+      __syncthreads();
+      const int ntile = (cc + 15) / 16;
+      auto load_tile = [&](int q0, double (&av)[MTR][4]) {
+        const int q = q0 + c16;
+        const bool cok = q < cc;
+        const TA* colp = A + (int64_t)cols[c0 + (cok ? q : cc - 1)] * bi.lda;
 #pragma unroll
-      for (int mt = 0; mt < MTR; ++mt) {
-        const int64_t i0 = rbase + 16 * mt + 4 * g;
-        const TA* src = A + j * bi.lda + i0;
-        if (cok && vec && i0 + 4 <= bi.m) {
-          if constexpr (sizeof(TA) == 8) {
-            const f64x2 x0 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src));
-            const f64x2 x1 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src) + 1);
-            av[mt][0] = x0[0];
-            av[mt][1] = x0[1];
-            av[mt][2] = x1[0];
-            av[mt][3] = x1[1];
-          } else {
-            const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
+        for (int mt = 0; mt < MTR; ++mt)
+          rc_load_pairs<TA, FAST>(colp, rbase + 16 * mt + 2 * g, bi.m, cok, av[mt]);
+      };
+      auto do_tile = [&](int q0, double (&av)[MTR][4]) {
+        f64x4 acc[MTR];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) av[mt][v] = (double)x[v];
+        for (int mt = 0; mt < MTR; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
+        const double* pc = p_lds + (q0 + c16) * kp + g;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const double pv = pc[4 * s];
+#pragma unroll
+          for (int mt = 0; mt < MTR; ++mt) acc[mt] = mfma_f64(as[mt][s], pv, acc[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double r = av[mt][v] - acc[mt][v];
+            e2 += r * r;
+            a2 += av[mt][v] * av[mt][v];
           }
-        } else {
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            av[mt][v] = (cok && i0 + v < bi.m) ? (double)src[v] : 0.0;
-        }
+      };
+      double b0[MTR][4], b1[MTR][4];
+      load_tile(0, b0);
+      int tq = 0;
+      // prefetch of the next tile (clamped: redundant on the last one)
+      for (; tq + 2 <= ntile; tq += 2) {
+        load_tile(min(16 * (tq + 1), 16 * (ntile - 1)), b1);
+        do_tile(16 * tq, b0);
+        load_tile(min(16 * (tq + 2), 16 * (ntile - 1)), b0);
+        do_tile(16 * (tq + 1), b1);
       }
-      f64x4 acc[MTR];
-#pragma unroll
-      for (int mt = 0; mt < MTR; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
-      const double* pc = p_lds + (q0 + c16) * kp + g;
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const double pv = pc[4 * s];
-#pragma unroll
-        for (int mt = 0; mt < MTR; ++mt) acc[mt] = mfma_f64(as[mt][s], pv, acc[mt]);
-      }
-#pragma unroll
-      for (int mt = 0; mt < MTR; ++mt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double r = av[mt][v] - acc[mt][v];
-          e2 += r * r;
-          a2 += av[mt][v] * av[mt][v];
-        }
+      if (tq < ntile) do_tile(16 * tq, b0);
+      lds_barrier();
     }
-    __syncthreads();
   }
+
   e2 = wave_sum(e2);
   a2 = wave_sum(a2);
   if (lane == 0) {
@@ -1171,15 +1272,17 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
 // square accumulated in FP64.  Lane (g, c) of the bf16 MFMA output holds rows
 // 4g..4g+3 of column c, so each lane loads 16 contiguous bytes per tile.
 // KS32 = k-steps of 32 selected columns; a workgroup of 4 waves covers
-// 4 * 16 * MTR rows.  The chunk's P terms are staged in LDS as bfloat16.
+// 4 * 16 * MTR rows.  The P terms of up to kRcCols columns are staged in LDS
+// as bfloat16; the next 16 columns' loads are in flight while the current
+// ones are reduced.  Dynamic LDS: 3 * kRcCols * 32 * KS32 bfloat16.
 // ---------------------------------------------------------------------------
-template <int KS32, int MTR>
+template <int KS32, int MTR, bool VEC>
 __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
     const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
     const double* __restrict__ P, float* __restrict__ skel, double* __restrict__ part) {
   constexpr int KP = 32 * KS32;
-  __shared__ __attribute__((aligned(16))) __bf16 pt[3][kRcCols][KP];
+  extern __shared__ __attribute__((aligned(16))) __bf16 pt_lds[];   // [3][kRcCols][KP]
   __shared__ double red[8];
   __shared__ int cols[1024];
   __shared__ unsigned char is_sel[1024];
@@ -1193,31 +1296,12 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
   const double* __restrict__ Pb = P + bi.p_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c16 = lane & 15;
-  const bool vec = bi.vec_ok != 0 && (it.i0 % 4) == 0;
-
-  for (int j = tid; j < n; j += kRcThreads) is_sel[j] = 0;
-  __syncthreads();
-  if (tid < k) is_sel[S[tid]] = 1;
-  __syncthreads();
-  int ncols = 0;
-  for (int base = 0; base < n; base += kRcThreads) {
-    const int j = base + tid;
-    const bool keep = j < n && !is_sel[j];
-    const uint64_t bal = __ballot(keep);
-    const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wcount[wave] = __popcll(bal);
-    __syncthreads();
-    int off = ncols;
-    for (int v = 0; v < wave; ++v) off += wcount[v];
-    if (keep) cols[off + before] = j;
-    int tot = 0;
-    for (int v = 0; v < 4; ++v) tot += wcount[v];
-    ncols += tot;
-    __syncthreads();
-  }
+  const int ncols = rc_compact_columns(n, k, S, is_sel, cols, wcount);
+  auto pt = [&](int term, int q, int t) -> __bf16* {
+    return pt_lds + ((size_t)term * kRcCols + q) * KP + t;
+  };
 
   const int64_t rbase = it.i0 + (int64_t)wave * 16 * MTR;
-  // A operand: tile row c16, selected columns 32 ks + 8 g + v, three terms
   bf16x8 at[MTR][KS32][3];
   double a2 = 0.0, e2 = 0.0;
 #pragma unroll
@@ -1245,68 +1329,74 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
     }
   }
 
-  for (int c0 = 0; c0 < ncols; c0 += kRcCols) {
-    const int cc = min(kRcCols, ncols - c0);
-    for (int e = tid; e < kRcCols * KP; e += kRcThreads) {
-      const int q = e / KP, t = e - q * KP;
-      const double pv = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
-      const __bf16 h = to_bf16((float)pv);
-      const double r1 = pv - (double)(float)h;
-      const __bf16 md = to_bf16((float)r1);
-      const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
-      pt[0][q][t] = h;
-      pt[1][q][t] = md;
-      pt[2][q][t] = lo;
-    }
-    __syncthreads();
-    for (int q0 = 0; q0 < cc; q0 += 16) {
-      const int q = q0 + c16;
-      const bool cok = q < cc;
-      const int64_t j = cok ? cols[c0 + q] : 0;
-      float av[MTR][4];
-#pragma unroll
-      for (int mt = 0; mt < MTR; ++mt) {
-        const int64_t i0 = rbase + 16 * mt + 4 * g;
-        const float* src = A + j * bi.lda + i0;
-        if (cok && vec && i0 + 4 <= bi.m) {
-          const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
-#pragma unroll
-          for (int v = 0; v < 4; ++v) av[mt][v] = x[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) av[mt][v] = (cok && i0 + v < bi.m) ? src[v] : 0.0f;
-        }
+  {
+    constexpr bool FAST = VEC;
+    for (int c0 = 0; c0 < ncols; c0 += kRcCols) {
+      const int cc = min(kRcCols, ncols - c0);
+      for (int e = tid; e < kRcCols * KP; e += kRcThreads) {
+        const int q = e / KP, t = e - q * KP;
+        const double pv = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
+        const __bf16 h = to_bf16((float)pv);
+        const double r1 = pv - (double)(float)h;
+        const __bf16 md = to_bf16((float)r1);
+        const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
+        *pt(0, q, t) = h;
+        *pt(1, q, t) = md;
+        *pt(2, q, t) = lo;
       }
-      f32x4 acc[MTR];
+      __syncthreads();
+      const int ntile = (cc + 15) / 16;
+      auto load_tile = [&](int q0, double (&av)[MTR][4]) {
+        const int q = q0 + c16;
+        const bool cok = q < cc;
+        const float* colp = A + (int64_t)cols[c0 + (cok ? q : cc - 1)] * bi.lda;
 #pragma unroll
-      for (int mt = 0; mt < MTR; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < MTR; ++mt)
+          rc_load4<float, FAST>(colp, rbase + 16 * mt + 4 * g, bi.m, cok, av[mt]);
+      };
+      auto do_tile = [&](int q0, double (&av)[MTR][4]) {
+        f32x4 acc[MTR];
 #pragma unroll
-      for (int ks = 0; ks < KS32; ++ks) {
-        const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(&pt[0][q0 + c16][32 * ks + 8 * g]);
-        const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(&pt[1][q0 + c16][32 * ks + 8 * g]);
-        const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(&pt[2][q0 + c16][32 * ks + 8 * g]);
+        for (int mt = 0; mt < MTR; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int mt = 0; mt < MTR; ++mt) {
-          // smallest terms first
-          acc[mt] = mfma_bf16(at[mt][ks][2], p0, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][1], p1, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][0], p2, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][1], p0, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][0], p1, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][0], p0, acc[mt]);
+        for (int ks = 0; ks < KS32; ++ks) {
+          const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(pt(0, q0 + c16, 32 * ks + 8 * g));
+          const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(pt(1, q0 + c16, 32 * ks + 8 * g));
+          const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(pt(2, q0 + c16, 32 * ks + 8 * g));
+#pragma unroll
+          for (int mt = 0; mt < MTR; ++mt) {
+            // smallest terms first
+            acc[mt] = mfma_bf16(at[mt][ks][2], p0, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][1], p1, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][0], p2, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][1], p0, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][0], p1, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][0], p0, acc[mt]);
+          }
         }
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float r = (float)av[mt][v] - acc[mt][v];
+            e2 += (double)r * (double)r;
+            a2 += av[mt][v] * av[mt][v];
+          }
+      };
+      double b0[MTR][4], b1[MTR][4];
+      load_tile(0, b0);
+      int tq = 0;
+      for (; tq + 2 <= ntile; tq += 2) {
+        load_tile(min(16 * (tq + 1), 16 * (ntile - 1)), b1);
+        do_tile(16 * tq, b0);
+        load_tile(min(16 * (tq + 2), 16 * (ntile - 1)), b0);
+        do_tile(16 * (tq + 1), b1);
       }
-#pragma unroll
-      for (int mt = 0; mt < MTR; ++mt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float r = av[mt][v] - acc[mt][v];
-          e2 += (double)r * (double)r;
-          a2 += (double)av[mt][v] * (double)av[mt][v];
-        }
+      if (tq < ntile) do_tile(16 * tq, b0);
+      lds_barrier();
     }
-    __syncthreads();
   }
+
   e2 = wave_sum(e2);
   a2 = wave_sum(a2);
   if (lane == 0) {
