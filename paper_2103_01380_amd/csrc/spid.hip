@@ -52,7 +52,10 @@ struct Shape {
   size_t sel_lds;  // dynamic LDS of the hybrid selection kernel
   int KMAX;      // register skeleton width in the error pass
   int KS;        // k-steps of 4 selected columns in the matrix-core error pass
-  int RC_ROWS;   // rows per error-pass work item
+  int MTR;       // 16-row MFMA tiles per wave in the error pass
+  int RC_SUB;    // rows of an error-pass sub-tile (4 waves x 16 * MTR)
+  int RPI;       // sub-tiles per error-pass work item
+  int PCAP;      // non-skeleton columns whose coefficients are staged in LDS at once
   int rc_bf16;   // 1: split-bfloat16 error pass (FP32 data, low-precision sketch)
   int KS32;      // k-steps of 32 selected columns in the split-bfloat16 error pass
 };
@@ -183,11 +186,25 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
         sh.KS = o;
         break;
       }
-    const int mtr = sh.KS <= 2 ? 4 : (sh.KS <= 16 ? 2 : 1);
-    sh.RC_ROWS = 4 * 16 * mtr;   // 4 waves x MTR 16-row tiles
     sh.rc_bf16 = (d->a_dtype == SPID_A_F32 && d->prec != SPID_SK_F64) ? 1 : 0;
     sh.KS32 = (d->k_max + 31) / 32;
-    if (sh.rc_bf16) sh.RC_ROWS = 4 * 16 * 2;
+    sh.MTR = sh.rc_bf16 ? 2 : (sh.KS <= 8 ? 4 : 2);
+    sh.RC_SUB = 4 * 16 * sh.MTR;
+    if (sh.rc_bf16) {
+      // one sub-tile per item, coefficients staged 64 columns at a time (static LDS)
+      sh.PCAP = kRcBfCols;
+      sh.RPI = 1;
+    } else {
+      // coefficient staging: as many columns as the LDS budget holds (multiple of 16)
+      const size_t per_col = 8 * 4 * (size_t)sh.KS;
+      const int cap = (int)(kRcLdsBytes / per_col) / 16 * 16;
+      const int need = (p.max_n + 15) / 16 * 16;
+      sh.PCAP = std::max(16, std::min(cap, need));
+      // sub-tiles per item: enough items to keep every CU busy (~8 per CU), at most 16
+      int64_t subs = 0;
+      for (int b = 0; b < nb; ++b) subs += (d->h_m[b] + sh.RC_SUB - 1) / sh.RC_SUB;
+      sh.RPI = (int)std::max<int64_t>(1, std::min<int64_t>(16, subs / 2048));
+    }
   }
 
   // sketch work items: column tiles x K splits
@@ -245,10 +262,12 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
         p.items.push_back(it);
       }
     p.rc_first.push_back((int64_t)p.rc.size());
-    for (int64_t i0 = 0; i0 < m; i0 += sh.RC_ROWS) {
+    const int64_t item_rows = (int64_t)sh.RC_SUB * sh.RPI;
+    for (int64_t i0 = 0; i0 < m; i0 += item_rows) {
       RcItem r{};
       r.blk = b;
       r.i0 = i0;
+      r.nsub = (int32_t)std::min<int64_t>(sh.RPI, (m - i0 + sh.RC_SUB - 1) / sh.RC_SUB);
       p.rc.push_back(r);
     }
   }
@@ -427,66 +446,61 @@ void launch_select_y(spid_ctx* c, hipStream_t s) {
 
 // ---- reconstruction dispatch (matrix-core kernels)
 // one attribute call per kernel instantiation for dynamic LDS above 64 KiB
-template <typename K>
-bool allow_lds(K kernel, size_t bytes) {
-  static bool done = false;
-  if (done || bytes <= 65536) return true;
-  done = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bytes) == hipSuccess;
-  return done;
+// Kernels whose dynamic LDS exceeds 64 KiB must opt in before every launch
+// (cheap host call, no stream work, safe under graph capture).
+bool allow_lds(const void* kernel, size_t bytes) {
+  if (bytes <= 65536) return true;
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+         hipSuccess;
 }
 
 template <typename TA, int KS, int MTR>
-void launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
+bool launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   const Plan& p = c->plan;
-  const size_t lds = sizeof(double) * kRcCols * 4 * KS;
+  const size_t lds = sizeof(double) * p.sh.PCAP * 4 * KS;
   auto launch = [&](auto kern) {
-    if (!allow_lds(kern, lds)) return;
+    if (!allow_lds((const void*)kern, lds)) return false;
     hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), lds, s,
                        c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.k_max,
-                       c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
+                       p.sh.PCAP, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
                        static_cast<TA*>(skel), c->at<double>(p.off_rcpart));
+    return true;
   };
-  if (c->all_vec4) launch(recon_mfma_kernel<TA, KS, MTR, true>);
-  else launch(recon_mfma_kernel<TA, KS, MTR, false>);
+  if (c->all_vec4) return launch(recon_mfma_kernel<TA, KS, MTR, true>);
+  return launch(recon_mfma_kernel<TA, KS, MTR, false>);
 }
 
 // single-precision data on the mixed path: split-bfloat16 error pass
 template <int KS32, int MTR>
-void launch_recon_bf16_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
+bool launch_recon_bf16_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   const Plan& p = c->plan;
-  const size_t lds = sizeof(__bf16) * 3 * kRcCols * 32 * KS32;
-  auto launch = [&](auto kern) {
-    if (!allow_lds(kern, lds)) return;
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), lds, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.k_max,
-                       c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
-                       static_cast<float*>(skel), c->at<double>(p.off_rcpart));
-  };
-  if (c->all_vec4) launch(recon_bf16x3_kernel<KS32, MTR, true>);
-  else launch(recon_bf16x3_kernel<KS32, MTR, false>);
+  hipLaunchKernelGGL((recon_bf16x3_kernel<KS32, MTR>), dim3((unsigned)p.rc.size()),
+                     dim3(kRcThreads), 0, s, c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc),
+                     c->desc.k_max, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
+                     static_cast<float*>(skel), c->at<double>(p.off_rcpart));
+  return true;
 }
 
 template <typename TA>
-void launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
+bool launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
+  const Shape& sh = c->plan.sh;
   if constexpr (sizeof(TA) == 4) {
-    if (c->plan.sh.rc_bf16) {
-      switch (c->plan.sh.KS32) {
-        case 1: launch_recon_bf16_t<1, 2>(c, P, skel, s); break;
-        case 2: launch_recon_bf16_t<2, 2>(c, P, skel, s); break;
-        default: launch_recon_bf16_t<3, 2>(c, P, skel, s); break;
+    if (sh.rc_bf16) {
+      switch (sh.KS32) {
+        case 1: return launch_recon_bf16_t<1, 2>(c, P, skel, s);
+        case 2: return launch_recon_bf16_t<2, 2>(c, P, skel, s);
+        default: return launch_recon_bf16_t<3, 2>(c, P, skel, s);
       }
-      return;
     }
   }
-  switch (c->plan.sh.KS) {
-    case 1: launch_recon_t<TA, 1, 4>(c, P, skel, s); break;
-    case 2: launch_recon_t<TA, 2, 4>(c, P, skel, s); break;
-    case 4: launch_recon_t<TA, 4, 2>(c, P, skel, s); break;
-    case 8: launch_recon_t<TA, 8, 2>(c, P, skel, s); break;
-    case 12: launch_recon_t<TA, 12, 2>(c, P, skel, s); break;
-    case 16: launch_recon_t<TA, 16, 2>(c, P, skel, s); break;
-    default: launch_recon_t<TA, 24, 1>(c, P, skel, s); break;
+  switch (sh.KS) {
+    case 1: return launch_recon_t<TA, 1, 4>(c, P, skel, s);
+    case 2: return launch_recon_t<TA, 2, 4>(c, P, skel, s);
+    case 4: return launch_recon_t<TA, 4, 4>(c, P, skel, s);
+    case 8: return launch_recon_t<TA, 8, 4>(c, P, skel, s);
+    case 12: return launch_recon_t<TA, 12, 2>(c, P, skel, s);
+    case 16: return launch_recon_t<TA, 16, 2>(c, P, skel, s);
+    default: return launch_recon_t<TA, 24, 2>(c, P, skel, s);
   }
 }
 
@@ -665,10 +679,9 @@ extern "C" spid_status spid_reconstruct(spid_ctx* c, const double* d_P, double* 
   if (!c->selected) return fail(SPID_ESTATE, "spid_reconstruct before spid_select");
   const Plan& p = c->plan;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (c->desc.a_dtype == SPID_A_F64)
-    launch_recon_a<double>(c, d_P, d_skeleton, s);
-  else
-    launch_recon_a<float>(c, d_P, d_skeleton, s);
+  const bool ok = c->desc.a_dtype == SPID_A_F64 ? launch_recon_a<double>(c, d_P, d_skeleton, s)
+                                                 : launch_recon_a<float>(c, d_P, d_skeleton, s);
+  if (!ok) return fail(SPID_EHIP, "reconstruct: cannot reserve the coefficient LDS");
   spid_status st = hip_check("reconstruct kernel launch");
   if (st != SPID_OK) return st;
   hipLaunchKernelGGL(recon_reduce_kernel, dim3((c->desc.nblocks + 255) / 256), dim3(256), 0, s,

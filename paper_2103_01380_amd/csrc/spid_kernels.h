@@ -46,8 +46,8 @@ struct SkItem {
 // One reconstruction work item: block, rows [i0, i0 + 256).
 struct RcItem {
   int32_t blk;
-  int32_t pad;
-  int64_t i0;
+  int32_t nsub;       // row sub-tiles of this item
+  int64_t i0;         // first row
 };
 
 constexpr int kSkThreads = 256;   // 4 waves
@@ -1047,7 +1047,7 @@ __global__ __launch_bounds__(64) void coeffs_kernel(const BlkInfo* __restrict__ 
 }
 
 constexpr int kRcThreads = 256;
-constexpr int kRcCols = 256;   // non-skeleton columns whose coefficients are staged at once
+constexpr int kRcLdsBytes = 65536;   // coefficient staging budget of one error-pass workgroup
 
 // Compact the non-skeleton columns of a block into `cols` (ascending j);
 // returns their number.  All threads of the workgroup call it.
@@ -1111,114 +1111,92 @@ __device__ __forceinline__ void rc_load4(const TA* __restrict__ colp, int64_t i0
   }
 }
 
-// Rows i0, i0+1, i0+8, i0+9 (i0 even) of one column for the FP64 residual,
-// rows at or past m read as zero.  VEC (16-byte aligned columns, m a multiple
-// of 4): each pair is entirely inside or outside the block, one vector load
-// from a clamped address plus a selection; otherwise clamped scalar loads.
-template <typename TA, bool VEC>
-__device__ __forceinline__ void rc_load_pairs(const TA* __restrict__ colp, int64_t i0, int64_t m,
-                                              bool ok, double out[4]) {
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int64_t r = i0 + 8 * h;
-    if constexpr (VEC && sizeof(TA) == 8) {
-      const bool in = ok && r < m;
-      const f64x2 x = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(colp + (in ? r : 0)));
-      out[2 * h] = in ? x[0] : 0.0;
-      out[2 * h + 1] = in ? x[1] : 0.0;
-    } else {
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int64_t i = min(r + e, m - 1);
-        const double x = (double)colp[i];
-        out[2 * h + e] = (ok && r + e < m) ? x : 0.0;
-      }
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Reconstruction error on the matrix cores (double precision).
 // Ahat(rows, cols) = A(rows, S) P(:, cols) with v_mfma_f64_16x16x4: the
 // skeleton A(rows, S) is the A operand (16 rows x 4 selected columns per
 // k-step), P the B operand (4 x 16 columns), Ahat accumulates in D.  Rows
-// inside a 16-row tile are permuted (tile row rho -> 2 (rho % 4) +
-// (rho / 4) % 2 + 8 (rho / 8)) so that lane (g, c) receives D rows 2g, 2g+1,
-// 8+2g, 9+2g of column c: the residual loads are two pairs per lane, and the
-// four lanes of a column read 64 contiguous bytes per load instruction.
-// A workgroup of 4 waves covers 4 * 16 * MTR rows; each wave streams all
-// non-skeleton columns 16 at a time, the next 16 columns' loads in flight
-// while the current ones are reduced; the coefficients of up to kRcCols
-// columns are staged in LDS.  KS = k-steps (k_max / 4 rounded up).
-// Dynamic LDS: kRcCols * 4 * KS doubles.
+// inside a 16-row tile are permuted (tile row rho -> 4 (rho % 4) + rho / 4)
+// so that lane (g, c) receives D rows 4g..4g+3 of column c: the residual
+// operands are four consecutive entries of one column per lane.
+//
+// Work item = (block, it.nsub sub-tiles of 4 * 16 * MTR rows starting at
+// it.i0).  The non-skeleton columns are compacted once per item and their
+// coefficients staged in LDS (pcap columns at a time, normally all of them),
+// so the staging is amortised over every sub-tile of the item.  Each wave
+// holds its 16 * MTR skeleton rows in registers and streams the staged
+// columns 16 at a time.  KS = k-steps (k_max / 4 rounded up).
+// Dynamic LDS: pcap * 4 * KS doubles.
 // ---------------------------------------------------------------------------
 template <typename TA, int KS, int MTR, bool VEC>
 __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
-    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max,
+    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max, int pcap,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
     const double* __restrict__ P, TA* __restrict__ skel, double* __restrict__ part) {
-  extern __shared__ double p_lds[];   // [kRcCols][kp]
+  extern __shared__ __attribute__((aligned(16))) double p_lds[];   // [pcap][kp]
   __shared__ double red[8];
   __shared__ int cols[1024];
   __shared__ unsigned char is_sel[1024];
   __shared__ int wcount[4];
+  constexpr int kp = 4 * KS;
+  constexpr int kSub = 4 * 16 * MTR;
   const RcItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
   const int n = bi.n;
   const int k = k_ws[it.blk];
-  constexpr int kp = 4 * KS;
   const int32_t* S = S_ws + (int64_t)it.blk * k_max;
   const TA* __restrict__ A = static_cast<const TA*>(bi.A);
   const double* __restrict__ Pb = P + bi.p_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const int ncols = rc_compact_columns(n, k, S, is_sel, cols, wcount);
-
-  const int64_t rbase = it.i0 + (int64_t)wave * 16 * MTR;
-  // A operand: lane supplies tile row rho = c16 -> actual row
-  // 2 (rho % 4) + (rho / 4) % 2 + 8 (rho / 8); k-slot g of step s -> selected column 4 s + g
-  const int arow = 2 * (c16 & 3) + ((c16 >> 2) & 1) + 8 * (c16 >> 3);
-  double as[MTR][KS];
+  // A operand: lane supplies tile row rho = c16 -> actual row 4 (rho % 4) + rho / 4,
+  // k-slot g of step s -> selected column 4 s + g
+  const int arow = 4 * (c16 & 3) + (c16 >> 2);
   double a2 = 0.0, e2 = 0.0;
-#pragma unroll
-  for (int mt = 0; mt < MTR; ++mt) {
-    const int64_t i = rbase + 16 * mt + arow;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int t = 4 * s + g;
-      double v = 0.0;
-      if (t < k && i < bi.m) {
-        v = (double)A[(int64_t)S[t] * bi.lda + i];
-        if (skel) skel[bi.sk_off + (int64_t)t * bi.m + i] = (TA)v;
-      }
-      as[mt][s] = v;
-      a2 += v * v;
-    }
-  }
 
-  {
-    constexpr bool FAST = VEC;
-    for (int c0 = 0; c0 < ncols; c0 += kRcCols) {
-      const int cc = min(kRcCols, ncols - c0);
-      for (int e = tid; e < kRcCols * kp; e += kRcThreads) {
-        const int q = e / kp, t = e - q * kp;
-        p_lds[e] = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
+  // one pass per coefficient chunk (a single one unless ncols > pcap)
+  for (int c0 = 0; c0 == 0 || c0 < ncols; c0 += pcap) {
+    const int cc = max(0, min(pcap, ncols - c0));
+    const int ntile = (cc + 15) / 16;
+    for (int e = tid; e < ntile * 16 * kp; e += kRcThreads) {
+      const int q = e / kp, t = e - q * kp;
+      const bool ok = q < cc && t < k_max;
+      const double x = cc > 0 ? Pb[(int64_t)cols[c0 + min(q, cc - 1)] * k_max + min(t, k_max - 1)]
+                              : 0.0;
+      p_lds[e] = ok ? x : 0.0;   // P rows k..k_max-1 are zero
+    }
+    __syncthreads();
+    for (int rs = 0; rs < it.nsub; ++rs) {
+      const int64_t rbase = it.i0 + (int64_t)rs * kSub + (int64_t)wave * 16 * MTR;
+      double as[MTR][KS];
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt) {
+        const int64_t i = rbase + 16 * mt + arow;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int t = 4 * s + g;
+          double v = 0.0;
+          if (t < k && i < bi.m) {
+            v = (double)A[(int64_t)S[t] * bi.lda + i];
+            if (skel && c0 == 0) skel[bi.sk_off + (int64_t)t * bi.m + i] = (TA)v;
+          }
+          as[mt][s] = v;
+          if (c0 == 0) a2 += v * v;
+        }
       }
-      __syncthreads();
-      const int ntile = (cc + 15) / 16;
-      auto load_tile = [&](int q0, double (&av)[MTR][4]) {
-        const int q = q0 + c16;
+      for (int tq = 0; tq < ntile; ++tq) {
+        const int q = 16 * tq + c16;
         const bool cok = q < cc;
         const TA* colp = A + (int64_t)cols[c0 + (cok ? q : cc - 1)] * bi.lda;
+        double av[MTR][4];
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt)
-          rc_load_pairs<TA, FAST>(colp, rbase + 16 * mt + 2 * g, bi.m, cok, av[mt]);
-      };
-      auto do_tile = [&](int q0, double (&av)[MTR][4]) {
+          rc_load4<TA, VEC>(colp, rbase + 16 * mt + 4 * g, bi.m, cok, av[mt]);
+        const double* pc = p_lds + q * kp + g;
         f64x4 acc[MTR];
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
-        const double* pc = p_lds + (q0 + c16) * kp + g;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
           const double pv = pc[4 * s];
@@ -1233,20 +1211,9 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
             e2 += r * r;
             a2 += av[mt][v] * av[mt][v];
           }
-      };
-      double b0[MTR][4], b1[MTR][4];
-      load_tile(0, b0);
-      int tq = 0;
-      // prefetch of the next tile (clamped: redundant on the last one)
-      for (; tq + 2 <= ntile; tq += 2) {
-        load_tile(min(16 * (tq + 1), 16 * (ntile - 1)), b1);
-        do_tile(16 * tq, b0);
-        load_tile(min(16 * (tq + 2), 16 * (ntile - 1)), b0);
-        do_tile(16 * (tq + 1), b1);
       }
-      if (tq < ntile) do_tile(16 * tq, b0);
-      lds_barrier();
     }
+    __syncthreads();
   }
 
   e2 = wave_sum(e2);
@@ -1271,37 +1238,39 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
 // with v_mfma_f32_16x16x32_bf16.  The residual is formed in FP32 and its
 // square accumulated in FP64.  Lane (g, c) of the bf16 MFMA output holds rows
 // 4g..4g+3 of column c, so each lane loads 16 contiguous bytes per tile.
-// KS32 = k-steps of 32 selected columns; a workgroup of 4 waves covers
-// 4 * 16 * MTR rows.  The P terms of up to kRcCols columns are staged in LDS
-// as bfloat16; the next 16 columns' loads are in flight while the current
-// ones are reduced.  Dynamic LDS: 3 * kRcCols * 32 * KS32 bfloat16.
+// KS32 = k-steps of 32 selected columns; a workgroup of 4 waves covers one
+// sub-tile of 4 * 16 * MTR rows (items carry nsub = 1).  The P terms of
+// kRcBfCols columns at a time are staged in 12-36 KiB of static LDS: this
+// kernel is bound by VALU latency, and the small footprint keeps six waves
+// per SIMD resident.
 // ---------------------------------------------------------------------------
-template <int KS32, int MTR, bool VEC>
+constexpr int kRcBfCols = 64;
+
+template <int KS32, int MTR>
 __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
     const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
     const double* __restrict__ P, float* __restrict__ skel, double* __restrict__ part) {
   constexpr int KP = 32 * KS32;
-  extern __shared__ __attribute__((aligned(16))) __bf16 pt_lds[];   // [3][kRcCols][KP]
+  __shared__ __attribute__((aligned(16))) __bf16 pt[3][kRcBfCols][KP];
   __shared__ double red[8];
   __shared__ int cols[1024];
   __shared__ unsigned char is_sel[1024];
   __shared__ int wcount[4];
   const RcItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
-  const int n = bi.n;
   const int k = k_ws[it.blk];
   const int32_t* S = S_ws + (int64_t)it.blk * k_max;
   const float* __restrict__ A = static_cast<const float*>(bi.A);
   const double* __restrict__ Pb = P + bi.p_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c16 = lane & 15;
-  const int ncols = rc_compact_columns(n, k, S, is_sel, cols, wcount);
-  auto pt = [&](int term, int q, int t) -> __bf16* {
-    return pt_lds + ((size_t)term * kRcCols + q) * KP + t;
-  };
+  // 16-byte loads need aligned column starts and a 4-row aligned tile start
+  const bool vec = bi.vec_ok != 0 && (it.i0 % 4) == 0;
+  const int ncols = rc_compact_columns(bi.n, k, S, is_sel, cols, wcount);
 
   const int64_t rbase = it.i0 + (int64_t)wave * 16 * MTR;
+  // A operand: tile row c16, selected columns 32 ks + 8 g + v, three terms
   bf16x8 at[MTR][KS32][3];
   double a2 = 0.0, e2 = 0.0;
 #pragma unroll
@@ -1329,72 +1298,67 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
     }
   }
 
-  {
-    constexpr bool FAST = VEC;
-    for (int c0 = 0; c0 < ncols; c0 += kRcCols) {
-      const int cc = min(kRcCols, ncols - c0);
-      for (int e = tid; e < kRcCols * KP; e += kRcThreads) {
-        const int q = e / KP, t = e - q * KP;
-        const double pv = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
-        const __bf16 h = to_bf16((float)pv);
-        const double r1 = pv - (double)(float)h;
-        const __bf16 md = to_bf16((float)r1);
-        const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
-        *pt(0, q, t) = h;
-        *pt(1, q, t) = md;
-        *pt(2, q, t) = lo;
-      }
-      __syncthreads();
-      const int ntile = (cc + 15) / 16;
-      auto load_tile = [&](int q0, double (&av)[MTR][4]) {
-        const int q = q0 + c16;
-        const bool cok = q < cc;
-        const float* colp = A + (int64_t)cols[c0 + (cok ? q : cc - 1)] * bi.lda;
-#pragma unroll
-        for (int mt = 0; mt < MTR; ++mt)
-          rc_load4<float, FAST>(colp, rbase + 16 * mt + 4 * g, bi.m, cok, av[mt]);
-      };
-      auto do_tile = [&](int q0, double (&av)[MTR][4]) {
-        f32x4 acc[MTR];
-#pragma unroll
-        for (int mt = 0; mt < MTR; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < KS32; ++ks) {
-          const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(pt(0, q0 + c16, 32 * ks + 8 * g));
-          const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(pt(1, q0 + c16, 32 * ks + 8 * g));
-          const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(pt(2, q0 + c16, 32 * ks + 8 * g));
-#pragma unroll
-          for (int mt = 0; mt < MTR; ++mt) {
-            // smallest terms first
-            acc[mt] = mfma_bf16(at[mt][ks][2], p0, acc[mt]);
-            acc[mt] = mfma_bf16(at[mt][ks][1], p1, acc[mt]);
-            acc[mt] = mfma_bf16(at[mt][ks][0], p2, acc[mt]);
-            acc[mt] = mfma_bf16(at[mt][ks][1], p0, acc[mt]);
-            acc[mt] = mfma_bf16(at[mt][ks][0], p1, acc[mt]);
-            acc[mt] = mfma_bf16(at[mt][ks][0], p0, acc[mt]);
-          }
-        }
-#pragma unroll
-        for (int mt = 0; mt < MTR; ++mt)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const float r = (float)av[mt][v] - acc[mt][v];
-            e2 += (double)r * (double)r;
-            a2 += av[mt][v] * av[mt][v];
-          }
-      };
-      double b0[MTR][4], b1[MTR][4];
-      load_tile(0, b0);
-      int tq = 0;
-      for (; tq + 2 <= ntile; tq += 2) {
-        load_tile(min(16 * (tq + 1), 16 * (ntile - 1)), b1);
-        do_tile(16 * tq, b0);
-        load_tile(min(16 * (tq + 2), 16 * (ntile - 1)), b0);
-        do_tile(16 * (tq + 1), b1);
-      }
-      if (tq < ntile) do_tile(16 * tq, b0);
-      lds_barrier();
+  for (int c0 = 0; c0 < ncols; c0 += kRcBfCols) {
+    const int cc = min(kRcBfCols, ncols - c0);
+    for (int e = tid; e < kRcBfCols * KP; e += kRcThreads) {
+      const int q = e / KP, t = e - q * KP;
+      const double pv = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
+      const __bf16 h = to_bf16((float)pv);
+      const double r1 = pv - (double)(float)h;
+      const __bf16 md = to_bf16((float)r1);
+      const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
+      pt[0][q][t] = h;
+      pt[1][q][t] = md;
+      pt[2][q][t] = lo;
     }
+    __syncthreads();
+    for (int q0 = 0; q0 < cc; q0 += 16) {
+      const int q = q0 + c16;
+      const bool cok = q < cc;
+      const int64_t j = cok ? cols[c0 + q] : 0;
+      float av[MTR][4];
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt) {
+        const int64_t i0 = rbase + 16 * mt + 4 * g;
+        const float* src = A + j * bi.lda + i0;
+        if (cok && vec && i0 + 4 <= bi.m) {
+          const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
+#pragma unroll
+          for (int v = 0; v < 4; ++v) av[mt][v] = x[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) av[mt][v] = (cok && i0 + v < bi.m) ? src[v] : 0.0f;
+        }
+      }
+      f32x4 acc[MTR];
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS32; ++ks) {
+        const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(&pt[0][q0 + c16][32 * ks + 8 * g]);
+        const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(&pt[1][q0 + c16][32 * ks + 8 * g]);
+        const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(&pt[2][q0 + c16][32 * ks + 8 * g]);
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt) {
+          // smallest terms first
+          acc[mt] = mfma_bf16(at[mt][ks][2], p0, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][1], p1, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][0], p2, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][1], p0, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][0], p1, acc[mt]);
+          acc[mt] = mfma_bf16(at[mt][ks][0], p0, acc[mt]);
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float r = av[mt][v] - acc[mt][v];
+          e2 += (double)r * (double)r;
+          a2 += (double)av[mt][v] * (double)av[mt][v];
+        }
+    }
+    __syncthreads();
   }
 
   e2 = wave_sum(e2);
