@@ -39,6 +39,12 @@ def parse():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="capture one step into a HIP graph and time graph replays")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="library default launch shapes instead of the autotuned ones")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON table of tuned shapes (default: the package's table)")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="skip timing the plain FP64 path on a mixed-precision workload")
     return ap.parse_args()
 
 
@@ -69,15 +75,121 @@ def main():
     log(args, f"generated {w.name}: {A.numel() * A.element_size() / 1e9:.2f} GB in "
               f"{time.time() - t0:.1f}s")
     nbytes = int((m * n.astype(np.int64)).sum()) * w.elem_bytes
-    ctx = sp.SPID(m, n, w.l, w.k_max, tol=w.tol, seed=w.omega_seed,
-                  a_dtype=w.a_dtype, prec=w.prec, lp_terms=w.lp_terms, device=dev)
-    ctx.bind(A, offsets=off)
     stream = torch.cuda.current_stream()
+    tuning = None
+    if not args.no_autotune:
+        from paper_2103_01380_amd import autotune as at
+        t0 = time.time()
+        tuning = at.autotune(A, m, n, w.l, w.k_max, offsets=off, tol=w.tol, seed=w.omega_seed,
+                             a_dtype=w.a_dtype, prec=w.prec, lp_terms=w.lp_terms,
+                             stream_columns=w.stream, cache=args.tune_cache or at.CACHE,
+                             log=(lambda s: log(args, s)))
+        log(args, f"launch shapes {tuning} ({time.time() - t0:.1f}s)")
+    ctx = sp.SPID(m, n, w.l, w.k_max, tol=w.tol, seed=w.omega_seed,
+                  a_dtype=w.a_dtype, prec=w.prec, lp_terms=w.lp_terms, device=dev, tuning=tuning)
+    ctx.bind(A, offsets=off)
+    ms_step, stage, wall = time_steps(args, ctx, w, stream)
+    graph_ms = None
+    if args.graph:
+        # one step captured into a HIP graph, replayed for the same number of steps
+        graph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(stream)
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(graph, stream=cap):
+                ctx.run(stream=cap)
+        stream.wait_stream(cap)
+        graph.replay()
+        torch.cuda.synchronize()
+        t0g = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0g) * 1e3 / args.steps
+        log(args, f"graph replay: {graph_ms:.3f} ms per step")
+    value = nbytes / (ms_step * 1e-3) / 1e9
+    rel_err = ctx.rel_error()
+    kk = ctx.k.cpu().numpy()
+    cf = float((m * n.astype(np.int64)).sum() / max(1, (kk * (m + n)).sum()))
+    log(args, f"stage ms: sketch {stage[0]:.3f} select {stage[1]:.3f} coeffs {stage[2]:.3f} "
+              f"recon {stage[3]:.3f}; step {ms_step:.3f} ms; rel err {rel_err:.3e}")
+
+    work = stage_work(w, m, n, kk, nbytes)
+    roof = dominant_roofline(w, stage, work)
+    step_roof = step_roofline(w, stage, work, ms_step)
+
+    cpu = None
+    agree = None
+    if not args.no_cpu_baseline:
+        cpu, agree = cpu_baseline(args, w, A, m, n, off, ctx)
+
+    fp64 = None
+    if w.prec != "f64" and not args.no_fp64_compare:
+        # the plain FP64 method on the same resident data: FP64 sketch and FP64 error pass
+        ctx64 = sp.SPID(m, n, w.l, w.k_max, tol=w.tol, seed=w.omega_seed, a_dtype=w.a_dtype,
+                        prec="f64", device=dev)
+        ctx64.bind(A, offsets=off)
+        ms64, stage64, _ = time_steps(args, ctx64, w, stream)
+        fp64 = {"ms_per_step": round(ms64, 4), "value": round(nbytes / (ms64 * 1e-3) / 1e9, 2),
+                "rel_error": ctx64.rel_error(),
+                "stage_ms": {k: round(v, 4) for k, v in zip(STAGES, stage64)}}
+        log(args, f"plain FP64 path: {ms64:.3f} ms per step, rel err {fp64['rel_error']:.3e}")
+        ctx64.close()
+
+    out = {
+        "metric": "snapshot GB/s compressed at rel. err <= 1e-3 (sketched column ID: sketch + "
+                  "CPQR select + coefficients + reconstruction error)",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w.prec == "f64" else f"{w.prec}-sketch/f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "description": w.description,
+                   "nblocks": int(len(m)), "bytes": nbytes, "l": w.l, "k_max": w.k_max,
+                   "tol": w.tol, "sketch_update": "one snapshot per call" if w.stream
+                   else "all snapshots in one call"},
+        "rel_error": rel_err,
+        "error_gate_1e-3": bool(rel_err <= 1e-3),
+        "compression_factor": round(cf, 3),
+        "k_mean": float(kk.mean()),
+        "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 4),
+        "stage_ms": {k: round(v, 4) for k, v in zip(STAGES, stage)},
+        "launch_shapes": ctx.tuning,
+        "roofline": roof,
+        "roofline_step": step_roof,
+        "cpu_baseline": cpu,
+        "oracle_agreement": agree,
+        "fp64_path": fp64,
+        "speedup_vs_fp64": None if fp64 is None else round(fp64["ms_per_step"] / ms_step, 3),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+STAGES = ("sketch", "select", "coeffs", "reconstruct")
+
+
+def time_steps(args, ctx, w, stream):
+    """Warm-up, then ``args.steps`` timed steps; returns (ms per step, stage ms, wall s).
+    A step is the whole method: the sketch of every snapshot (one update per
+    snapshot for a streamed workload), selection, coefficients, error pass."""
+    import torch
+    nmax = int(ctx.n.max())
 
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        ctx.sketch_update(stream=stream)
+        if w.stream:
+            for j in range(nmax):
+                ctx.sketch_update(j, 1, stream=stream)
+        else:
+            ctx.sketch_update(stream=stream)
         if ev is not None:
             ev[1].record(stream)
         ctx.select(stream)
@@ -104,47 +216,37 @@ def main():
     for e in evs:
         for i in range(4):
             stage[i] += e[i].elapsed_time(e[i + 1])
-    stage /= args.steps                     # ms per stage
-    graph_ms = None
-    if args.graph:
-        # one step captured into a HIP graph, replayed for the same number of steps
-        graph = torch.cuda.CUDAGraph()
-        cap = torch.cuda.Stream()
-        cap.wait_stream(stream)
-        with torch.cuda.stream(cap):
-            with torch.cuda.graph(graph, stream=cap):
-                ctx.run(stream=cap)
-        stream.wait_stream(cap)
-        graph.replay()
-        torch.cuda.synchronize()
-        t0g = time.perf_counter()
-        for _ in range(args.steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        graph_ms = (time.perf_counter() - t0g) * 1e3 / args.steps
-        log(args, f"graph replay: {graph_ms:.3f} ms per step")
-    ms_step = wall * 1e3 / args.steps
-    value = nbytes / (ms_step * 1e-3) / 1e9
-    rel_err = ctx.rel_error()
-    kk = ctx.k.cpu().numpy()
-    cf = float((m * n.astype(np.int64)).sum() / max(1, (kk * (m + n)).sum()))
-    log(args, f"stage ms: sketch {stage[0]:.3f} select {stage[1]:.3f} coeffs {stage[2]:.3f} "
-              f"recon {stage[3]:.3f}; step {ms_step:.3f} ms; rel err {rel_err:.3e}")
+    stage /= args.steps
+    return wall * 1e3 / args.steps, stage, wall
 
-    # roofline of the dominant kernel (algorithmic bytes / flops per launch)
-    sk_flops = 2.0 * w.l * float((m * n.astype(np.int64)).sum())
-    rc_flops = 2.0 * float((m * (n.astype(np.int64) - kk) * kk).sum())
-    kernels = {
-        "sketch": (stage[0], nbytes, sk_flops),
-        "reconstruct": (stage[3], nbytes, rc_flops),
+
+def stage_work(w, m, n, kk, nbytes):
+    """Algorithmic (bytes, flops, flop peak) per stage: what the method must do."""
+    n64 = n.astype(np.int64)
+    k64 = kk.astype(np.int64)
+    sk_flops = 2.0 * w.l * float((m * n64).sum())
+    sel_flops = float((4.0 * w.l * k64 * (n64 - (k64 - 1) / 2.0)).sum())
+    co_flops = float((k64 * k64 * (n64 - k64)).sum())
+    rc_flops = 2.0 * float((m * (n64 - k64) * k64).sum())
+    sk_peak = PEAK_TFLOPS["f64" if w.prec == "f64" else w.prec]
+    rc_peak = PEAK_TFLOPS["f64" if (w.a_dtype == "f64" or w.prec == "f64") else "bf16"]
+    return {
+        "sketch": (nbytes, sk_flops, sk_peak),
+        "select": (0, sel_flops, PEAK_TFLOPS["f64"]),
+        "coeffs": (0, co_flops, PEAK_TFLOPS["f64"]),
+        "reconstruct": (nbytes, rc_flops, rc_peak),
     }
-    dom = max(kernels, key=lambda x: kernels[x][0])
-    t_ms, b_alg, f_alg = kernels[dom]
-    gbs = b_alg / (t_ms * 1e-3) / 1e9
-    tfl = f_alg / (t_ms * 1e-3) / 1e12
-    peak_t = PEAK_TFLOPS["f64" if (w.prec == "f64" and dom == "sketch") else
-                         ("f64" if dom == "reconstruct" else w.prec)]
-    # bound: whichever roof is closer to the achieved rate
+
+
+def dominant_roofline(w, stage, work):
+    """Roofline of the slowest streaming kernel: algorithmic bytes or flops over its
+    average launch time (HIP events on its launch stream), against the closer roof."""
+    t = dict(zip(STAGES, stage))
+    dom = max(("sketch", "reconstruct"), key=lambda x: t[x])
+    b_alg, f_alg, peak_t = work[dom]
+    t_s = t[dom] * 1e-3
+    gbs = b_alg / t_s / 1e9
+    tfl = f_alg / t_s / 1e12
     if tfl / peak_t > gbs / PEAK_HBM_GBS:
         roof = {"bound": "mfma", "achieved": round(tfl, 3), "peak": peak_t, "unit": "TFLOP/s",
                 "frac": round(tfl / peak_t, 4)}
@@ -153,43 +255,63 @@ def main():
                 "frac": round(gbs / PEAK_HBM_GBS, 4)}
     roof["kernel"] = dom
     roof["traffic"] = None
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, w, A, m, n, off)
-
-    out = {
-        "metric": "snapshot GB/s compressed at rel. err <= 1e-3 (sketched column ID: sketch + "
-                  "CPQR select + coefficients + reconstruction error)",
-        "value": round(value, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if w.prec == "f64" else f"{w.prec}-sketch/f64",
-        "data": "synthetic",
-        "config": {"workload": w.name, "description": w.description,
-                   "nblocks": int(len(m)), "bytes": nbytes, "l": w.l, "k_max": w.k_max,
-                   "tol": w.tol},
-        "rel_error": rel_err,
-        "error_gate_1e-3": bool(rel_err <= 1e-3),
-        "compression_factor": round(cf, 3),
-        "k_mean": float(kk.mean()),
-        "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 4),
-        "stage_ms": {"sketch": round(stage[0], 4), "select": round(stage[1], 4),
-                     "coeffs": round(stage[2], 4), "reconstruct": round(stage[3], 4)},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
-    ctx.close()
+    return roof
 
 
-def cpu_baseline(args, w, A, m, n, off):
+def step_roofline(w, stage, work, ms_step):
+    """T_roof = sum over stages of max(bytes / HBM peak, flops / matrix-core peak);
+    frac = T_roof / measured step time."""
+    per = {}
+    t_roof = 0.0
+    for name, ms in zip(STAGES, stage):
+        b, f, peak_t = work[name]
+        t = max(b / (PEAK_HBM_GBS * 1e9), f / (peak_t * 1e12)) * 1e3
+        per[name] = {"t_roof_ms": round(t, 4), "frac": round(t / ms, 4) if ms > 0 else None}
+        t_roof += t
+    return {"t_roof_ms": round(t_roof, 4), "frac": round(t_roof / ms_step, 4), "stages": per}
+
+
+def oracle_agreement(w, A, m, n, off, ctx, idx, res):
+    """The GPU's factors against the oracle's on the oracle's sample of blocks:
+    relative errors of both, the A-space difference of the two reconstructions
+    (R2) and how many blocks select the oracle's columns over the decidable prefix."""
+    import torch
+    gamma = {"f64": 1e-10, "bf16": 1e-3, "fp8": 1e-2}[w.prec]
+    S = ctx.S.cpu().numpy()
+    k = ctx.k.cpu().numpy()
+    e2g = ctx.err2.cpu().numpy()
+    n2g = ctx.nrm2.cpu().numpy()
+    num = den = 0.0
+    match = full = 0
+    flat = A.reshape(-1)
+    for r, b in enumerate(idx):
+        b = int(b)
+        mb, nb_ = int(m[b]), int(n[b])
+        Ad = flat[int(off[b]):int(off[b]) + mb * nb_].view(nb_, mb).t().double()
+        kg, ko = int(k[b]), int(res.k[r])
+        Pg = torch.from_numpy(np.ascontiguousarray(ctx.block_P(b)[:kg])).to(Ad.device)
+        Po = torch.from_numpy(np.ascontiguousarray(res.P[r][:ko])).to(Ad.device)
+        ag = Ad[:, torch.from_numpy(S[b][:kg].astype(np.int64)).to(Ad.device)] @ Pg
+        ao = Ad[:, torch.from_numpy(res.S[r][:ko].astype(np.int64)).to(Ad.device)] @ Po
+        num += float(((ag - ao) ** 2).sum())
+        den += float(n2g[b])
+        s_star = 0
+        while s_star < min(kg, ko) and res.gaps[r][s_star] > gamma:
+            s_star += 1
+        if np.array_equal(S[b][:s_star], res.S[r][:s_star]):
+            match += 1
+        if s_star == ko and kg == ko and np.array_equal(S[b][:kg], res.S[r][:ko]):
+            full += 1
+    return {"blocks": int(len(idx)),
+            "gpu_rel_error": float(np.sqrt(e2g[idx].sum() / n2g[idx].sum())),
+            "oracle_rel_error": res.rel_error,
+            "R2": float(np.sqrt(num / den)) if den > 0 else 0.0,
+            "gap_gamma": gamma,
+            "prefix_match_blocks": int(match),
+            "identical_selection_blocks": int(full)}
+
+
+def cpu_baseline(args, w, A, m, n, off, ctx):
     """The oracle, as it stands, timed on a bounded sample of the same blocks.
 
     A first batch (one block per thread) measures the per-block cost; the
@@ -219,11 +341,13 @@ def cpu_baseline(args, w, A, m, n, off):
     dt, sbytes, res = run(idx)
     log(args, f"cpu oracle: {len(idx)} blocks, {threads} threads, {dt:.1f}s, "
               f"rel err {res.rel_error:.3e}")
+    agree = oracle_agreement(w, A, m, n, off, ctx, idx, res)
+    log(args, f"oracle agreement: {agree}")
     return {"value": round(sbytes / dt / 1e9, 5), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{len(idx)} of {nb} blocks (seeded choice), whole method per block "
                       f"(sketch, select, coefficients, error), {dt:.1f} s wall on {threads} "
-                      f"threads"}
+                      f"threads"}, agree
 
 
 if __name__ == "__main__":

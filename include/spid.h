@@ -75,9 +75,9 @@ typedef enum { SPID_SK_F64 = 0, SPID_SK_BF16 = 1, SPID_SK_FP8E4M3 = 2 } spid_skp
 typedef struct {
   int32_t nblocks;          /* number of spatial blocks (>= 1) */
   const int64_t* h_m;       /* host [nblocks]: rows m_b (>= 1) */
-  const int32_t* h_n;       /* host [nblocks]: snapshots n_b (>= 1) */
+  const int32_t* h_n;       /* host [nblocks]: snapshots n_b, 1..1024 */
   int32_t l;                /* sketch rows, 1 <= l <= 128 */
-  int32_t k_max;            /* rank (tol == 0) or rank cap (tol > 0), <= 128;
+  int32_t k_max;            /* rank (tol == 0) or rank cap (tol > 0), <= 96;
                                fixed rank requires k_max <= min(l, n_b) */
   double tol;               /* 0: fixed rank.  > 0: stop after the first step
                                with ||Y - Y(:,S)P||_F <= tol ||Y||_F (Remark
@@ -94,9 +94,32 @@ typedef struct {
                                for F64) */
 } spid_desc;
 
+/* Launch-shape choices (the batching schedule of Section 3.2's independent
+ * blocks on one GPU).  Any field 0 = the library's default for the
+ * descriptor; an autotuner times candidates and passes the fastest.  Shapes
+ * never change results beyond the order of floating-point sums inside a
+ * sketch column (K splits), so every choice meets the same parity rules.
+ *   sk_tn    16-column MFMA tiles per wave in the sketch: 1, 2 or 4
+ *            (FP64: 1 or 2, and 2 only for l <= 64; BF16: 4 only for
+ *            l <= 80; FP8: 1)
+ *   sk_nw    waves per sketch workgroup: 8, or 4 with sk_tn = 1
+ *   sk_items target number of sketch work items (64..65536): blocks are
+ *            split along their rows (K) until about this many items exist
+ *   rc_rpi   error-pass row sub-tiles per work item, 1..16 (double-precision
+ *            error pass only; the split-bfloat16 pass uses one)            */
+typedef struct {
+  int32_t sk_tn;
+  int32_t sk_nw;
+  int32_t sk_items;
+  int32_t rc_rpi;
+} spid_tuning;
+
 /* Bytes of device workspace a descriptor needs (0 if the descriptor is
  * invalid; spid_last_error() says why).  Host-only, no HIP call. */
 size_t spid_workspace_bytes(const spid_desc* desc);
+
+/* The same for explicit launch shapes (tuning may be NULL = defaults). */
+size_t spid_workspace_bytes_tuned(const spid_desc* desc, const spid_tuning* tuning);
 
 /* Create a context on the current HIP device.  `d_workspace` (256-byte
  * aligned, >= spid_workspace_bytes) is owned by the caller and must outlive
@@ -105,6 +128,14 @@ size_t spid_workspace_bytes(const spid_desc* desc);
  * freed by spid_destroy. */
 spid_status spid_create(const spid_desc* desc, void* d_workspace, size_t ws_bytes,
                         spid_ctx** out);
+
+/* spid_create with explicit launch shapes (NULL = defaults).  EINVAL for a
+ * value outside the ranges listed at spid_tuning. */
+spid_status spid_create_tuned(const spid_desc* desc, const spid_tuning* tuning,
+                              void* d_workspace, size_t ws_bytes, spid_ctx** out);
+
+/* The launch shapes a context uses (defaults resolved), for the record. */
+spid_status spid_get_tuning(const spid_ctx* ctx, spid_tuning* out);
 
 /* Bind the snapshot data: h_block_ptrs[b] is the device address of block b
  * (column-major, m_b x n_b, A dtype), h_lda[b] >= m_b its leading dimension

@@ -8,7 +8,9 @@ immediately; there is no CPU fallback.
 The functions carry the C names (``spid_workspace_bytes``, ``spid_create``,
 ``spid_bind_A``, ``spid_sketch_update``, ``spid_select``, ``spid_coeffs``,
 ``spid_reconstruct``, ``spid_copy_sketch``, ``spid_destroy``,
-``spid_last_error``); :class:`SPID` bundles them for a batch of blocks.
+``spid_last_error``, and the launch-shape variants ``spid_workspace_bytes_tuned``,
+``spid_create_tuned``, ``spid_get_tuning``); :class:`SPID` bundles them for a
+batch of blocks.
 """
 from __future__ import annotations
 
@@ -25,7 +27,8 @@ BLOCK_OK, BLOCK_RANK_DEFICIENT, BLOCK_NONFINITE, BLOCK_TOL_NOT_MET = 0, 1, 2, 3
 A_F64, A_F32 = 0, 1
 SK_F64, SK_BF16, SK_FP8E4M3 = 0, 1, 2
 
-EXPORTS = ("spid_workspace_bytes", "spid_create", "spid_bind_A", "spid_sketch_update",
+EXPORTS = ("spid_workspace_bytes", "spid_workspace_bytes_tuned", "spid_create",
+           "spid_create_tuned", "spid_get_tuning", "spid_bind_A", "spid_sketch_update",
            "spid_select", "spid_coeffs", "spid_reconstruct", "spid_copy_sketch",
            "spid_destroy", "spid_last_error")
 
@@ -53,6 +56,28 @@ class spid_desc(ctypes.Structure):
     ]
 
 
+class spid_tuning(ctypes.Structure):
+    _fields_ = [
+        ("sk_tn", ctypes.c_int32),
+        ("sk_nw", ctypes.c_int32),
+        ("sk_items", ctypes.c_int32),
+        ("rc_rpi", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def make_tuning(t=None):
+    """A spid_tuning from a dict (missing keys = 0 = library default), or None."""
+    if t is None:
+        return None
+    tu = spid_tuning()
+    for f, _ in spid_tuning._fields_:
+        setattr(tu, f, int(t.get(f, 0)))
+    return tu
+
+
 _lib = None
 
 
@@ -70,8 +95,15 @@ def load_library(path: str = LIB_PATH):
     D = ctypes.POINTER(spid_desc)
     lib.spid_workspace_bytes.argtypes = [D]
     lib.spid_workspace_bytes.restype = ctypes.c_size_t
+    T = ctypes.POINTER(spid_tuning)
+    lib.spid_workspace_bytes_tuned.argtypes = [D, T]
+    lib.spid_workspace_bytes_tuned.restype = ctypes.c_size_t
     lib.spid_create.argtypes = [D, P, ctypes.c_size_t, ctypes.POINTER(P)]
     lib.spid_create.restype = ctypes.c_int
+    lib.spid_create_tuned.argtypes = [D, T, P, ctypes.c_size_t, ctypes.POINTER(P)]
+    lib.spid_create_tuned.restype = ctypes.c_int
+    lib.spid_get_tuning.argtypes = [P, T]
+    lib.spid_get_tuning.restype = ctypes.c_int
     lib.spid_bind_A.argtypes = [P, P, P]
     lib.spid_bind_A.restype = ctypes.c_int
     lib.spid_sketch_update.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
@@ -134,12 +166,32 @@ def spid_workspace_bytes(desc: spid_desc) -> int:
     return int(load_library().spid_workspace_bytes(ctypes.byref(desc)))
 
 
+def spid_workspace_bytes_tuned(desc: spid_desc, tuning) -> int:
+    t = None if tuning is None else ctypes.byref(tuning)
+    return int(load_library().spid_workspace_bytes_tuned(ctypes.byref(desc), t))
+
+
 def spid_create(desc: spid_desc, workspace) -> ctypes.c_void_p:
     ctx = ctypes.c_void_p()
     _check(load_library().spid_create(ctypes.byref(desc), _ptr(workspace),
                                       workspace.numel() * workspace.element_size(),
                                       ctypes.byref(ctx)))
     return ctx
+
+
+def spid_create_tuned(desc: spid_desc, tuning, workspace) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    t = None if tuning is None else ctypes.byref(tuning)
+    _check(load_library().spid_create_tuned(ctypes.byref(desc), t, _ptr(workspace),
+                                            workspace.numel() * workspace.element_size(),
+                                            ctypes.byref(ctx)))
+    return ctx
+
+
+def spid_get_tuning(ctx) -> dict:
+    t = spid_tuning()
+    _check(load_library().spid_get_tuning(ctx, ctypes.byref(t)))
+    return t.as_dict()
 
 
 def spid_bind_A(ctx, block_ptrs, lda):
@@ -189,7 +241,7 @@ class SPID:
     """
 
     def __init__(self, m, n, l, k_max, tol=0.0, rank_floor=0.0, seed=0, omega_per_block=False,
-                 a_dtype="f64", prec="f64", lp_terms=1, device="cuda"):
+                 a_dtype="f64", prec="f64", lp_terms=1, device="cuda", tuning=None):
         import torch
         self.m = np.ascontiguousarray(m, dtype=np.int64)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
@@ -197,7 +249,8 @@ class SPID:
         self.l, self.k_max = int(l), int(k_max)
         self.desc = make_desc(self.m, self.n, l, k_max, tol, rank_floor, seed, omega_per_block,
                               A_F64 if a_dtype == "f64" else A_F32, _PREC[prec], lp_terms)
-        nbytes = spid_workspace_bytes(self.desc)
+        self._tuning = make_tuning(tuning)
+        nbytes = spid_workspace_bytes_tuned(self.desc, self._tuning)
         if nbytes == 0:
             raise SpidError(SPID_EINVAL, spid_last_error())
         self.device = torch.device(device)
@@ -205,7 +258,8 @@ class SPID:
         self._ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self._ws_raw.data_ptr()) % 256
         self.workspace = self._ws_raw[off:off + nbytes]
-        self.ctx = spid_create(self.desc, self.workspace)
+        self.ctx = spid_create_tuned(self.desc, self._tuning, self.workspace)
+        self.tuning = spid_get_tuning(self.ctx)
         sum_n = int(self.n.astype(np.int64).sum())
         self.k = torch.zeros(self.nblocks, dtype=torch.int32, device=self.device)
         self.S = torch.full((self.nblocks, self.k_max), -1, dtype=torch.int32, device=self.device)

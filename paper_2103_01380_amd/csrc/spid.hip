@@ -35,6 +35,9 @@ spid_status fail(spid_status st, const char* fmt, ...) {
 constexpr int kMaxL = 128;
 constexpr int kMaxK = 96;
 constexpr int kMaxN = 1024;
+constexpr int kStreamNW = 8;                       // waves of a one-snapshot sketch workgroup
+constexpr int kStreamGroup = 16 * kStreamNW;       // blocks per group (one 16-column tile per wave)
+constexpr int kStreamMaxW = 4;                     // updates of up to this many snapshots use it
 
 constexpr size_t kAlign = 256;
 
@@ -58,6 +61,7 @@ struct Shape {
   int PCAP;      // non-skeleton columns whose coefficients are staged in LDS at once
   int rc_bf16;   // 1: split-bfloat16 error pass (FP32 data, low-precision sketch)
   int KS32;      // k-steps of 32 selected columns in the split-bfloat16 error pass
+  int sk_items;  // target number of sketch work items
 };
 
 int pick_mt(int l) {
@@ -90,10 +94,17 @@ struct Plan {
   std::vector<int32_t> split_blocks;
   std::vector<RcItem> rc;
   std::vector<int64_t> rc_first;
+  // one-snapshot updates: blocks ordered by m (perm), groups of kStreamGroup
+  // equal-m blocks x K ranges (sitems), heads of groups with several K ranges
+  bool st_ok = false;
+  std::vector<int32_t> perm;
+  std::vector<SkItem> sitems;
+  std::vector<int32_t> sheads;
+  int64_t st_part_elems = 0;
   int64_t sum_n = 0, sum_m = 0, part_elems = 0;
   int max_n = 0, max_split_n = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
-      off_st, off_rcpart, total;
+      off_st, off_rcpart, off_perm, off_sitems, off_sheads, total;
 };
 
 spid_status validate(const spid_desc* d) {
@@ -126,8 +137,33 @@ spid_status validate(const spid_desc* d) {
   return SPID_OK;
 }
 
-spid_status make_plan(const spid_desc* d, Plan& p) {
+spid_status validate_tuning(const spid_desc* d, const spid_tuning* t, int mt) {
+  if (!t) return SPID_OK;
+  if (t->sk_tn != 0 && t->sk_tn != 1 && t->sk_tn != 2 && t->sk_tn != 4)
+    return fail(SPID_EINVAL, "tuning: sk_tn must be 0, 1, 2 or 4 (got %d)", t->sk_tn);
+  if (t->sk_tn != 0) {
+    const bool f64 = d->prec == SPID_SK_F64;
+    if (f64 && (t->sk_tn == 4 || (t->sk_tn == 2 && mt > 4)))
+      return fail(SPID_EINVAL, "tuning: sk_tn=%d not available for the FP64 sketch with l=%d",
+                  t->sk_tn, d->l);
+    if (d->prec == SPID_SK_BF16 && t->sk_tn == 4 && mt >= 6)
+      return fail(SPID_EINVAL, "tuning: sk_tn=4 not available for the BF16 sketch with l=%d", d->l);
+    if (d->prec == SPID_SK_FP8E4M3 && t->sk_tn != 1)
+      return fail(SPID_EINVAL, "tuning: the FP8 sketch takes sk_tn=1 (got %d)", t->sk_tn);
+  }
+  if (t->sk_nw != 0 && t->sk_nw != 4 && t->sk_nw != 8)
+    return fail(SPID_EINVAL, "tuning: sk_nw must be 0, 4 or 8 (got %d)", t->sk_nw);
+  if (t->sk_items != 0 && (t->sk_items < 64 || t->sk_items > 65536))
+    return fail(SPID_EINVAL, "tuning: sk_items must be 0 or 64..65536 (got %d)", t->sk_items);
+  if (t->rc_rpi < 0 || t->rc_rpi > 16)
+    return fail(SPID_EINVAL, "tuning: rc_rpi must be 0..16 (got %d)", t->rc_rpi);
+  return SPID_OK;
+}
+
+spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   spid_status st = validate(d);
+  if (st != SPID_OK) return st;
+  st = validate_tuning(d, tune, pick_mt(d->l));
   if (st != SPID_OK) return st;
   const int nb = d->nblocks;
   p.ydt = (d->prec == SPID_SK_F64) ? 0 : 1;
@@ -149,6 +185,12 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
     if (sh.MT >= 6 && sh.TN > 2) sh.TN = 2;
     if (d->prec == SPID_SK_FP8E4M3) sh.TN = 1;
     sh.NW = p.max_n >= 128 ? 8 : 4;
+  }
+  if (tune && tune->sk_tn) sh.TN = tune->sk_tn;
+  if (tune && tune->sk_nw) sh.NW = tune->sk_nw;
+  if (sh.NW == 4 && sh.TN != 1) {
+    if (tune && tune->sk_nw == 4) return fail(SPID_EINVAL, "tuning: sk_nw=4 requires sk_tn=1");
+    sh.NW = 8;
   }
   sh.LMAX = pick_lmax(d->l);
   sh.CPT = (p.max_n > 512) ? 2 : 1;
@@ -204,6 +246,7 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
       int64_t subs = 0;
       for (int b = 0; b < nb; ++b) subs += (d->h_m[b] + sh.RC_SUB - 1) / sh.RC_SUB;
       sh.RPI = (int)std::max<int64_t>(1, std::min<int64_t>(16, subs / 2048));
+      if (tune && tune->rc_rpi) sh.RPI = tune->rc_rpi;
     }
   }
 
@@ -214,7 +257,8 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
   // (total / kTargetItems), keeping at least min_rows rows per split.
   double total_cost = 0.0;
   for (int b = 0; b < nb; ++b) total_cost += (double)d->h_m[b] * d->h_n[b];
-  const int64_t kTargetItems = 2048;
+  const int64_t kTargetItems = (tune && tune->sk_items) ? tune->sk_items : 2048;
+  sh.sk_items = (int)kTargetItems;
   const int64_t min_rows = 256;
   const double target_cost = std::max(total_cost / kTargetItems, (double)min_rows * tile_cols);
   p.blk.resize(nb);
@@ -273,6 +317,49 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
   }
   p.rc_first.push_back((int64_t)p.rc.size());
   p.part_elems = part_off;
+
+  // one-snapshot (stream) plan: needs Omega shared by all blocks
+  p.st_ok = d->omega_per_block == 0;
+  if (p.st_ok) {
+    p.perm.resize(nb);
+    for (int b = 0; b < nb; ++b) p.perm[b] = b;
+    std::stable_sort(p.perm.begin(), p.perm.end(),
+                     [&](int32_t a, int32_t b2) { return d->h_m[a] > d->h_m[b2]; });
+    double st_total = 0.0;
+    for (int b = 0; b < nb; ++b) st_total += (double)d->h_m[b];
+    const double st_target = std::max(st_total / kTargetItems, (double)min_rows * kStreamGroup);
+    int64_t st_off = 0;
+    for (int first = 0; first < nb;) {
+      const int64_t m = d->h_m[p.perm[first]];
+      int last = first;
+      while (last < nb && last - first < kStreamGroup && d->h_m[p.perm[last]] == m) ++last;
+      const int gsize = last - first;
+      int nsplit = (int)std::ceil((double)m * gsize / st_target);
+      nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nsplit, m / min_rows));
+      int64_t rows = (m + nsplit - 1) / nsplit;
+      rows = (rows + kKC - 1) / kKC * kKC;
+      nsplit = (int)((m + rows - 1) / rows);
+      const int64_t gpart = nsplit > 1 ? st_off : 0;
+      if (nsplit > 1) {
+        p.sheads.push_back((int32_t)p.sitems.size());
+        st_off += (int64_t)nsplit * kStreamGroup * d->l;
+      }
+      for (int sp = 0; sp < nsplit; ++sp) {
+        SkItem it{};
+        it.blk = p.perm[first];
+        it.c0 = first;
+        it.split = sp;
+        it.gsize = gsize;
+        it.r0 = (int64_t)sp * rows;
+        it.r1 = std::min(m, (int64_t)(sp + 1) * rows);
+        it.gnsplit = nsplit;
+        it.gpart = gpart;
+        p.sitems.push_back(it);
+      }
+      first = last;
+    }
+    p.st_part_elems = st_off;
+  }
   // longest items first (the hardware dispatches workgroups in grid order)
   std::stable_sort(p.items.begin(), p.items.end(), [&](const SkItem& a, const SkItem& b2) {
     const int64_t ca = (a.r1 - a.r0) * std::min<int64_t>(tile_cols, d->h_n[a.blk] - a.c0);
@@ -292,12 +379,15 @@ spid_status make_plan(const spid_desc* d, Plan& p) {
   p.off_rc = take(sizeof(RcItem) * p.rc.size());
   p.off_rcfirst = take(sizeof(int64_t) * p.rc_first.size());
   p.off_Y = take(ysz * (size_t)d->l * p.sum_n);
-  p.off_part = take(ysz * (size_t)std::max<int64_t>(1, p.part_elems));
+  p.off_part = take(ysz * (size_t)std::max<int64_t>({(int64_t)1, p.part_elems, p.st_part_elems}));
   p.off_R = take(sizeof(double) * (size_t)d->k_max * p.sum_n);
   p.off_S = take(sizeof(int32_t) * (size_t)nb * d->k_max);
   p.off_k = take(sizeof(int32_t) * nb);
   p.off_st = take(sizeof(int32_t) * nb);
   p.off_rcpart = take(sizeof(double) * 2 * p.rc.size());
+  p.off_perm = take(sizeof(int32_t) * std::max<size_t>(1, p.perm.size()));
+  p.off_sitems = take(sizeof(SkItem) * std::max<size_t>(1, p.sitems.size()));
+  p.off_sheads = take(sizeof(int32_t) * std::max<size_t>(1, p.sheads.size()));
   p.total = off;
   return SPID_OK;
 }
@@ -331,24 +421,36 @@ spid_status hip_check(const char* what) {
 }
 
 // ---- sketch dispatch
-template <typename TA, int MT, int TN, int NW, bool VEC>
-void launch_sketch_k(spid_ctx* c, int j0, int j1, hipStream_t s) {
+// ST: one-snapshot update of snapshot jst over the block groups
+template <typename TA, int MT, int TN, int NW, bool VEC, bool ST>
+void launch_sketch_k(spid_ctx* c, int j0, int j1, int jst, hipStream_t s) {
   const Plan& p = c->plan;
-  dim3 grid((unsigned)p.items.size()), block(64 * NW);
+  const size_t nitems = ST ? p.sitems.size() : p.items.size();
+  const SkItem* items = c->at<SkItem>(ST ? p.off_sitems : p.off_items);
+  const int32_t* perm = c->at<int32_t>(p.off_perm);
+  dim3 grid((unsigned)nitems), block(64 * NW);
+  // shapes the planner can choose (others are not instantiated): FP64 TN <= 2
+  // (2 only for MT <= 4), FP8 TN = 1, BF16 TN = 4 only for MT < 6
+  constexpr bool kF64 = TN == 1 || (TN == 2 && MT <= 4);
+  constexpr bool kFP8 = TN == 1;
+  constexpr bool kBF16 = TN <= 2 || MT < 6;
   if (p.ydt == 0) {
-    hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN, NW, VEC>), grid, block, 0, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->at<double>(p.off_Y),
+    if constexpr (kF64)
+    hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN, NW, VEC, ST>), grid, block, 0, s,
+                       c->at<BlkInfo>(p.off_blk), items, c->desc.l, c->desc.seed,
+                       c->desc.omega_per_block, j0, j1, perm, jst, c->at<double>(p.off_Y),
                        c->at<double>(p.off_part));
   } else if (c->desc.prec == SPID_SK_FP8E4M3) {
-    hipLaunchKernelGGL((sketch_fp8_kernel<TA, MT, TN, NW, VEC>), grid, block, 0, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+    if constexpr (kFP8)
+    hipLaunchKernelGGL((sketch_fp8_kernel<TA, MT, TN, NW, VEC, ST>), grid, block, 0, s,
+                       c->at<BlkInfo>(p.off_blk), items, c->desc.l, c->desc.seed,
+                       c->desc.omega_per_block, j0, j1, perm, jst, c->desc.lp_terms,
                        c->at<float>(p.off_Y), c->at<float>(p.off_part));
   } else {
-    hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, NW, VEC>), grid, block, 0, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_items), c->desc.l,
-                       c->desc.seed, c->desc.omega_per_block, j0, j1, c->desc.lp_terms,
+    if constexpr (kBF16)
+    hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, NW, VEC, ST>), grid, block, 0, s,
+                       c->at<BlkInfo>(p.off_blk), items, c->desc.l, c->desc.seed,
+                       c->desc.omega_per_block, j0, j1, perm, jst, c->desc.lp_terms,
                        c->at<float>(p.off_Y), c->at<float>(p.off_part));
   }
 }
@@ -359,12 +461,12 @@ template <typename TA, int MT, int TN>
 void launch_sketch_t(spid_ctx* c, int j0, int j1, hipStream_t s) {
   const bool vec = c->all_vec;
   if (c->plan.sh.NW == 8) {
-    if (vec) launch_sketch_k<TA, MT, TN, 8, true>(c, j0, j1, s);
-    else launch_sketch_k<TA, MT, TN, 8, false>(c, j0, j1, s);
+    if (vec) launch_sketch_k<TA, MT, TN, 8, true, false>(c, j0, j1, 0, s);
+    else launch_sketch_k<TA, MT, TN, 8, false, false>(c, j0, j1, 0, s);
   } else {
     if constexpr (TN == 1) {
-      if (vec) launch_sketch_k<TA, MT, 1, 4, true>(c, j0, j1, s);
-      else launch_sketch_k<TA, MT, 1, 4, false>(c, j0, j1, s);
+      if (vec) launch_sketch_k<TA, MT, 1, 4, true, false>(c, j0, j1, 0, s);
+      else launch_sketch_k<TA, MT, 1, 4, false, false>(c, j0, j1, 0, s);
     }
   }
 }
@@ -378,6 +480,12 @@ void launch_sketch_mt(spid_ctx* c, int j0, int j1, hipStream_t s) {
   }
 }
 
+template <typename TA, int MT>
+void launch_sketch_stream_mt(spid_ctx* c, int j, hipStream_t s) {
+  if (c->all_vec) launch_sketch_k<TA, MT, 1, kStreamNW, true, true>(c, 0, 0, j, s);
+  else launch_sketch_k<TA, MT, 1, kStreamNW, false, true>(c, 0, 0, j, s);
+}
+
 template <typename TA>
 void launch_sketch_a(spid_ctx* c, int j0, int j1, hipStream_t s) {
   switch (c->plan.sh.MT) {
@@ -387,6 +495,18 @@ void launch_sketch_a(spid_ctx* c, int j0, int j1, hipStream_t s) {
     case 4: launch_sketch_mt<TA, 4>(c, j0, j1, s); break;
     case 6: launch_sketch_mt<TA, 6>(c, j0, j1, s); break;
     default: launch_sketch_mt<TA, 8>(c, j0, j1, s); break;
+  }
+}
+
+template <typename TA>
+void launch_sketch_stream_a(spid_ctx* c, int j, hipStream_t s) {
+  switch (c->plan.sh.MT) {
+    case 1: launch_sketch_stream_mt<TA, 1>(c, j, s); break;
+    case 2: launch_sketch_stream_mt<TA, 2>(c, j, s); break;
+    case 3: launch_sketch_stream_mt<TA, 3>(c, j, s); break;
+    case 4: launch_sketch_stream_mt<TA, 4>(c, j, s); break;
+    case 6: launch_sketch_stream_mt<TA, 6>(c, j, s); break;
+    default: launch_sketch_stream_mt<TA, 8>(c, j, s); break;
   }
 }
 
@@ -509,18 +629,37 @@ bool launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
 // ============================================================================ C ABI
 
 extern "C" size_t spid_workspace_bytes(const spid_desc* desc) {
+  return spid_workspace_bytes_tuned(desc, nullptr);
+}
+
+extern "C" size_t spid_workspace_bytes_tuned(const spid_desc* desc, const spid_tuning* tuning) {
   Plan p;
-  if (make_plan(desc, p) != SPID_OK) return 0;
+  if (make_plan(desc, tuning, p) != SPID_OK) return 0;
   return p.total;
 }
 
 extern "C" spid_status spid_create(const spid_desc* desc, void* d_workspace, size_t ws_bytes,
                                    spid_ctx** out) {
+  return spid_create_tuned(desc, nullptr, d_workspace, ws_bytes, out);
+}
+
+extern "C" spid_status spid_get_tuning(const spid_ctx* c, spid_tuning* out) {
+  if (!c || !out) return fail(SPID_EINVAL, "NULL argument to spid_get_tuning");
+  const Shape& sh = c->plan.sh;
+  out->sk_tn = sh.TN;
+  out->sk_nw = sh.NW;
+  out->sk_items = sh.sk_items;
+  out->rc_rpi = sh.rc_bf16 ? 1 : sh.RPI;
+  return SPID_OK;
+}
+
+extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tuning* tuning,
+                                         void* d_workspace, size_t ws_bytes, spid_ctx** out) {
   if (!out) return fail(SPID_EINVAL, "out is NULL");
   *out = nullptr;
   spid_ctx* c = new (std::nothrow) spid_ctx();
   if (!c) return fail(SPID_EINVAL, "host allocation failed");
-  spid_status st = make_plan(desc, c->plan);
+  spid_status st = make_plan(desc, tuning, c->plan);
   if (st != SPID_OK) {
     delete c;
     return st;
@@ -554,6 +693,15 @@ extern "C" spid_status spid_create(const spid_desc* desc, void* d_workspace, siz
                   hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(c->ws + p.off_rcfirst, p.rc_first.data(), sizeof(int64_t) * p.rc_first.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p.perm.empty())
+    e = hipMemcpy(c->ws + p.off_perm, p.perm.data(), sizeof(int32_t) * p.perm.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p.sitems.empty())
+    e = hipMemcpy(c->ws + p.off_sitems, p.sitems.data(), sizeof(SkItem) * p.sitems.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p.sheads.empty())
+    e = hipMemcpy(c->ws + p.off_sheads, p.sheads.data(), sizeof(int32_t) * p.sheads.size(),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete c;
@@ -603,6 +751,38 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
   const int j1 = (int)std::min<int64_t>((int64_t)j0 + w, p.max_n);
   if (j0 >= p.max_n) return fail(SPID_EINVAL, "j0=%d is past every block's last column", j0);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p.st_ok && j1 - j0 <= kStreamMaxW) {
+    // a few snapshots: one launch per snapshot with the blocks as MFMA columns
+    for (int j = j0; j < j1; ++j) {
+      if (c->desc.a_dtype == SPID_A_F64)
+        launch_sketch_stream_a<double>(c, j, s);
+      else
+        launch_sketch_stream_a<float>(c, j, s);
+      spid_status st = hip_check("stream sketch kernel launch");
+      if (st != SPID_OK) return st;
+      if (!p.sheads.empty()) {
+        dim3 grid((unsigned)(((int64_t)c->desc.l * kStreamGroup + 255) / 256),
+                  (unsigned)p.sheads.size());
+        if (p.ydt == 0)
+          hipLaunchKernelGGL((sketch_stream_reduce_kernel<double>), grid, dim3(256), 0, s,
+                             c->at<BlkInfo>(p.off_blk), c->at<int32_t>(p.off_perm),
+                             c->at<SkItem>(p.off_sitems), c->at<int32_t>(p.off_sheads),
+                             c->desc.l, kStreamGroup, j, c->at<double>(p.off_Y),
+                             c->at<double>(p.off_part));
+        else
+          hipLaunchKernelGGL((sketch_stream_reduce_kernel<float>), grid, dim3(256), 0, s,
+                             c->at<BlkInfo>(p.off_blk), c->at<int32_t>(p.off_perm),
+                             c->at<SkItem>(p.off_sitems), c->at<int32_t>(p.off_sheads),
+                             c->desc.l, kStreamGroup, j, c->at<float>(p.off_Y),
+                             c->at<float>(p.off_part));
+        st = hip_check("stream sketch reduce launch");
+        if (st != SPID_OK) return st;
+      }
+    }
+    for (int j = j0; j < j1; ++j) c->covered[j] = 1;
+    c->selected = false;
+    return SPID_OK;
+  }
   if (c->desc.a_dtype == SPID_A_F64)
     launch_sketch_a<double>(c, j0, j1, s);
   else

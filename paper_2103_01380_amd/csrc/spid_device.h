@@ -43,18 +43,68 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // Sketch-matrix entries Omega(2q, i) and Omega(2q+1, i): one Philox block at
 // counter (i, q, block key, stream 0) under the 64-bit seed, two 53-bit
 // uniforms (u1 in (0,1], u2 in [0,1)), Box-Muller in double precision.
-__device__ __forceinline__ double2 omega_pair(uint64_t seed, uint32_t bkey, uint32_t i,
-                                              uint32_t q) {
+__device__ __forceinline__ void omega_words(uint64_t seed, uint32_t bkey, uint32_t i, uint32_t q,
+                                            uint64_t& a, uint64_t& b) {
   const uint4 x = philox4x32_10(make_uint4(i, q, bkey, 0u), (uint32_t)seed,
                                 (uint32_t)(seed >> 32));
-  const uint64_t a = ((uint64_t)(x.x >> 5) << 26) | (uint64_t)(x.y >> 6);
-  const uint64_t b = ((uint64_t)(x.z >> 5) << 26) | (uint64_t)(x.w >> 6);
+  a = ((uint64_t)(x.x >> 5) << 26) | (uint64_t)(x.y >> 6);
+  b = ((uint64_t)(x.z >> 5) << 26) | (uint64_t)(x.w >> 6);
+}
+
+__device__ __forceinline__ double2 box_muller_f64(uint64_t a, uint64_t b) {
   const double u1 = (double)(a + 1u) * 0x1p-53;
   const double u2 = (double)b * 0x1p-53;
   const double rho = sqrt(-2.0 * log(u1));
   double s, c;
   sincos(6.283185307179586 * u2, &s, &c);
   return make_double2(rho * c, rho * s);
+}
+
+__device__ __forceinline__ double2 omega_pair(uint64_t seed, uint32_t bkey, uint32_t i,
+                                              uint32_t q) {
+  uint64_t a, b;
+  omega_words(seed, bkey, i, q, a, b);
+  return box_muller_f64(a, b);
+}
+
+// The same pair rounded by `rnd` (round-to-nearest-even to bfloat16 or e4m3,
+// a monotone map) for the low-precision sketches, evaluated cheaply but with
+// the same result.  Box-Muller first runs in single precision: u1 -> ln u1
+// (log1p of the exact complement when u1 > 1/2), rho = sqrt(-2 ln u1), the
+// angle as sincospi(2 u2).  Error of z = rho (cos, sin) against the
+// double-precision evaluation: u2 rounded to single (angle error <= 1.9e-7),
+// sincospi (<= 2.4e-7), ln and sqrt (rho relative error <= 2.7e-7), product
+// rounding (6e-8 relative): |dz| <= 7.6e-7 rho.  With eps = rho 2^-19
+// (1.9e-6 rho) every value within eps of the single-precision z rounds alike
+// when z - eps and z + eps do (the map is monotone), so the double-precision
+// pair lies in that interval and rounds to the same value.  Only when a value
+// is that close to a rounding boundary is the double-precision pair evaluated.
+template <typename RND>
+__device__ __forceinline__ void omega_pair_rounded(uint64_t seed, uint32_t bkey, uint32_t i,
+                                                   uint32_t q, RND rnd, double& o0, double& o1) {
+  uint64_t a, b;
+  omega_words(seed, bkey, i, q, a, b);
+  float lnu;
+  if (a >= (1ull << 52)) {
+    const float v = (float)((1ull << 53) - 1u - a) * 0x1p-53f;
+    lnu = log1pf(-v);
+  } else {
+    lnu = logf((float)(a + 1u) * 0x1p-53f);
+  }
+  const float rho = sqrtf(-2.0f * lnu);
+  float sn, cs;
+  sincospif(2.0f * ((float)b * 0x1p-53f), &sn, &cs);
+  const double z0 = (double)(rho * cs), z1 = (double)(rho * sn);
+  const double eps = (double)rho * 0x1p-19 + 0x1p-60;
+  const double r0 = rnd(z0), r1 = rnd(z1);
+  if (rnd(z0 - eps) == r0 && rnd(z0 + eps) == r0 && rnd(z1 - eps) == r1 && rnd(z1 + eps) == r1) {
+    o0 = r0;
+    o1 = r1;
+    return;
+  }
+  const double2 z = box_muller_f64(a, b);
+  o0 = rnd(z.x);
+  o1 = rnd(z.y);
 }
 
 // Round-to-nearest-even of a double to bfloat16 precision (8 significant

@@ -2,7 +2,8 @@
 //
 //   sketch_kernel     Y_b(:, cols) = Omega_b A_b(:, cols) on the matrix cores,
 //                     Omega regenerated per 32-row chunk into LDS.
-//   sketch_reduce     fixed-order sum of split-K partial sketches.
+//   sketch_reduce     fixed-order sum of split-K partial sketches (per block,
+//                     or per group of blocks for one-snapshot updates).
 //   select_kernel     pivoted modified Gram-Schmidt on the sketch, one
 //                     workgroup per block, one sketch column per lane held in
 //                     registers, pivot search by wave + LDS reduction.
@@ -36,11 +37,14 @@ struct BlkInfo {
 
 // One sketch work item: block, 64*TN-column tile, K range [r0, r1).
 struct SkItem {
-  int32_t blk;
-  int32_t c0;
+  int32_t blk;        // block (stream items: the first block of the group)
+  int32_t c0;         // first column (stream items: first position in the block order)
   int32_t split;      // index of the K range
+  int32_t gsize;      // stream items: blocks in the group
+  int64_t r0, r1;     // rows [r0, r1)
+  int32_t gnsplit;    // stream items: K ranges of the group
   int32_t pad;
-  int64_t r0, r1;
+  int64_t gpart;      // stream items: element offset of the group's partial sketches
 };
 
 // One reconstruction work item: block, rows [i0, i0 + 256).
@@ -117,6 +121,22 @@ __device__ __forceinline__ void load_pieces_tail(const TA* __restrict__ cb, int6
 // Omega chunk generation into LDS: rows 0..l-1 of columns k0..k0+31 of the
 // sketch matrix (pair q -> rows 2q, 2q+1).  Rows l..MT*16-1 stay zero.
 // ---------------------------------------------------------------------------
+// bfloat16 Omega chunk: entries rounded to nearest-even bfloat16 through the
+// cheap exact path of omega_pair_rounded.
+template <int STRIDE, int NTHR>
+__device__ __forceinline__ void gen_omega_chunk_bf16(__bf16* __restrict__ om, int l, uint64_t seed,
+                                                     uint32_t bkey, int64_t k0, int tid) {
+  const int npairs = (l + 1) >> 1;
+  for (int e = tid; e < npairs * kKC; e += NTHR) {
+    const int q = e / kKC, kk = e - q * kKC;
+    double z0, z1;
+    omega_pair_rounded(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q,
+                       [](double x) { return rne_bf16(x); }, z0, z1);
+    om[(2 * q) * STRIDE + kk] = to_bf16((float)z0);
+    if (2 * q + 1 < l) om[(2 * q + 1) * STRIDE + kk] = to_bf16((float)z1);
+  }
+}
+
 template <typename TO, int STRIDE, int NTHR, typename CVT>
 __device__ __forceinline__ void gen_omega_chunk(TO* __restrict__ om, int l, uint64_t seed,
                                                 uint32_t bkey, int64_t k0, int tid, CVT cvt) {
@@ -156,6 +176,44 @@ __device__ __forceinline__ bool sk_setup(const BlkInfo& bi, const SkItem& it, in
   return true;
 }
 
+// One-snapshot update of many blocks (stream mode): the MFMA column
+// dimension runs over the blocks of a group instead of one block's columns,
+// so Y_b(:, j) = Omega(:, rows) A_b(rows, j) for every block of the group is
+// one matrix product with a shared Omega chunk (blocks of a group have equal
+// m_b; Omega keyed by (seed, r, i) only).  Lane column `local` is block
+// perm[it.c0 + local], snapshot j.
+template <typename TA, int TN>
+__device__ __forceinline__ void sk_setup_stream(const BlkInfo* __restrict__ blks,
+                                                const int32_t* __restrict__ perm,
+                                                const SkItem& it, int cw, int r16, int j,
+                                                SkLane<TA, TN>& ln) {
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int local = cw + 16 * u + r16;
+    const bool valid = local < it.gsize;
+    const BlkInfo& bb = blks[perm[it.c0 + (valid ? local : 0)]];
+    const bool ok = valid && j < bb.n;
+    ln.col[u] = local;
+    ln.ok[u] = ok;
+    ln.cb[u] = static_cast<const TA*>(bb.A) + (int64_t)(ok ? j : 0) * bb.lda;
+  }
+}
+
+// Output offset of lane column u in the sketch (or its partial buffer).
+template <typename TA, int TN, int GCAP, bool ST>
+__device__ __forceinline__ int64_t sk_out_offset(const BlkInfo* __restrict__ blks,
+                                                 const int32_t* __restrict__ perm,
+                                                 const BlkInfo& bi, const SkItem& it,
+                                                 const SkLane<TA, TN>& ln, int u, int l, int j) {
+  if constexpr (ST) {
+    if (it.gnsplit == 1) return blks[perm[it.c0 + ln.col[u]]].y_off + (int64_t)j * l;
+    return it.gpart + ((int64_t)it.split * GCAP + ln.col[u]) * l;
+  } else {
+    const int64_t base = (bi.nsplit == 1) ? bi.y_off : bi.part_off + (int64_t)it.split * bi.n * l;
+    return base + (int64_t)ln.col[u] * l;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Sketch, double precision: Y = Omega A on v_mfma_f64_16x16x4.
 // Workgroup = NW waves; wave w owns columns c0 + 16*TN*w + [0, 16*TN); every
@@ -169,10 +227,11 @@ __device__ __forceinline__ bool sk_setup(const BlkInfo& bi, const SkItem& it, in
 // workgroup generates chunk c+1's Omega; one LDS-only barrier per chunk.  The
 // ragged last chunk is handled after the loop.
 // ---------------------------------------------------------------------------
-template <typename TA, int MT, int TN, int NW, bool VEC>
+template <typename TA, int MT, int TN, int NW, bool VEC, bool ST>
 __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
-    int omega_per_block, int j0, int j1, double* __restrict__ Y, double* __restrict__ part) {
+    int omega_per_block, int j0, int j1, const int32_t* __restrict__ perm, int jst,
+    double* __restrict__ Y, double* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) double om[2][MT * 16 * kOmStride];
   const SkItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
@@ -181,7 +240,11 @@ __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
   const int g = lane >> 4, r16 = lane & 15;
   const int cwave = it.c0 + wave * 16 * TN;
   SkLane<TA, TN> ln;
-  if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
+  if constexpr (ST) {
+    sk_setup_stream<TA, TN>(blks, perm, it, wave * 16 * TN, r16, jst, ln);
+  } else {
+    if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
+  }
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
   auto ident = [](double x) { return x; };
 
@@ -252,17 +315,18 @@ __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
     mfma_chunk(om[b], a0);
   }
   // epilogue: lane holds rows 16t + g + 4v of column cwave + 16u + r16
-  double* dst = (bi.nsplit == 1) ? (Y + bi.y_off)
-                                 : (part + bi.part_off + (int64_t)it.split * bi.n * l);
+  const bool direct = ST ? it.gnsplit == 1 : bi.nsplit == 1;
+  double* dst = direct ? Y : part;
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
     if (!ln.ok[u]) continue;
+    const int64_t ob = sk_out_offset<TA, TN, NW * 16 * TN, ST>(blks, perm, bi, it, ln, u, l, jst);
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * t + g + 4 * v;
-        if (row < l) dst[(int64_t)ln.col[u] * l + row] = acc[t][u][v];
+        if (row < l) dst[ob + row] = acc[t][u][v];
       }
   }
 }
@@ -277,11 +341,11 @@ __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
 // supplies the same rows.  Same software pipeline as the double-precision
 // kernel.
 // ---------------------------------------------------------------------------
-template <typename TA, int MT, int TN, int NW, bool VEC>
+template <typename TA, int MT, int TN, int NW, bool VEC, bool ST>
 __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
-    int omega_per_block, int j0, int j1, int terms, float* __restrict__ Y,
-    float* __restrict__ part) {
+    int omega_per_block, int j0, int j1, const int32_t* __restrict__ perm, int jst, int terms,
+    float* __restrict__ Y, float* __restrict__ part) {
   constexpr int kS = kKC + 8;   // LDS row stride in bf16 elements (80 bytes)
   __shared__ __attribute__((aligned(16))) __bf16 om[2][MT * 16 * kS];
   const SkItem it = items[blockIdx.x];
@@ -291,9 +355,12 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
   const int g = lane >> 4, r16 = lane & 15;
   const int cwave = it.c0 + wave * 16 * TN;
   SkLane<TA, TN> ln;
-  if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
+  if constexpr (ST) {
+    sk_setup_stream<TA, TN>(blks, perm, it, wave * 16 * TN, r16, jst, ln);
+  } else {
+    if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
+  }
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
-  auto to_bf = [](double x) { return to_bf16((float)rne_bf16(x)); };
 
   for (int e = tid; e < 2 * MT * 16 * kS; e += 64 * NW) (&om[0][0])[e] = (__bf16)0.0f;
 
@@ -342,13 +409,13 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
   __syncthreads();
   if (nfull > 0) {
     load_full(it.r0, a0);
-    gen_omega_chunk<__bf16, kS, 64 * NW>(om[0], l, seed, bkey, it.r0, tid, to_bf);
+    gen_omega_chunk_bf16<kS, 64 * NW>(om[0], l, seed, bkey, it.r0, tid);
   }
   lds_barrier();
   auto step = [&](float (&cur)[TN][8], float (&nxt)[TN][8], int b, int64_t k0) {
     const int64_t k1 = min(k0 + kKC, klast);
     load_full(k1, nxt);
-    gen_omega_chunk<__bf16, kS, 64 * NW>(om[b ^ 1], l, seed, bkey, k1, tid, to_bf);
+    gen_omega_chunk_bf16<kS, 64 * NW>(om[b ^ 1], l, seed, bkey, k1, tid);
     mfma_chunk(om[b], cur);
     lds_barrier();
   };
@@ -361,24 +428,25 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
   const int64_t kt = it.r0 + nfull * kKC;
   if (kt < it.r1) {
     const int b = (int)(nfull & 1);
-    gen_omega_chunk<__bf16, kS, 64 * NW>(om[b], l, seed, bkey, kt, tid, to_bf);
+    gen_omega_chunk_bf16<kS, 64 * NW>(om[b], l, seed, bkey, kt, tid);
 #pragma unroll
     for (int u = 0; u < TN; ++u)
       load_pieces_tail<TA, 2, 4, 16>(ln.cb[u], kt + 4 * g, it.r1, ln.ok[u], a0[u]);
     lds_barrier();
     mfma_chunk(om[b], a0);
   }
-  float* dst = (bi.nsplit == 1) ? (Y + bi.y_off)
-                                : (part + bi.part_off + (int64_t)it.split * bi.n * l);
+  const bool direct = ST ? it.gnsplit == 1 : bi.nsplit == 1;
+  float* dst = direct ? Y : part;
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
     if (!ln.ok[u]) continue;
+    const int64_t ob = sk_out_offset<TA, TN, NW * 16 * TN, ST>(blks, perm, bi, it, ln, u, l, jst);
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * t + 4 * g + v;
-        if (row < l) dst[(int64_t)ln.col[u] * l + row] = acc[t][u][v];
+        if (row < l) dst[ob + row] = acc[t][u][v];
       }
   }
 }
@@ -403,12 +471,13 @@ __device__ __forceinline__ void gen_omega_chunk_e4m3(uint8_t* __restrict__ om, i
   const int npairs = (l + 1) >> 1;
   for (int e = tid; e < npairs * kKC8; e += NTHR) {
     const int q = e / kKC8, kk = e - q * kKC8;
-    const double2 z = omega_pair(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q);
+    double z0, z1;
+    omega_pair_rounded(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q,
+                       [](double x) { return rne_e4m3(x); }, z0, z1);
     // chunk row kk = 64 h + 16 w + 4 g + x sits at k = 64 h + 16 g + 4 w + x
     const int kpos = (kk & ~63) | (((kk >> 2) & 3) << 4) | (((kk >> 4) & 3) << 2) | (kk & 3);
-    om[(2 * q) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte((float)rne_e4m3(z.x));
-    if (2 * q + 1 < l)
-      om[(2 * q + 1) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte((float)rne_e4m3(z.y));
+    om[(2 * q) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte((float)z0);
+    if (2 * q + 1 < l) om[(2 * q + 1) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte((float)z1);
   }
 }
 
@@ -475,11 +544,11 @@ __device__ __forceinline__ i32x8 fp8_term(float res[32], int g, int& scale_byte)
   return out;
 }
 
-template <typename TA, int MT, int TN, int NW, bool VEC>
+template <typename TA, int MT, int TN, int NW, bool VEC, bool ST>
 __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
-    int omega_per_block, int j0, int j1, int terms, float* __restrict__ Y,
-    float* __restrict__ part) {
+    int omega_per_block, int j0, int j1, const int32_t* __restrict__ perm, int jst, int terms,
+    float* __restrict__ Y, float* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) uint8_t om[2][MT * 16 * kOm8Stride];
   const SkItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
@@ -488,7 +557,11 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
   const int g = lane >> 4, r16 = lane & 15;
   const int cwave = it.c0 + wave * 16 * TN;
   SkLane<TA, TN> ln;
-  if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
+  if constexpr (ST) {
+    sk_setup_stream<TA, TN>(blks, perm, it, wave * 16 * TN, r16, jst, ln);
+  } else {
+    if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
+  }
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
 
   for (int e = tid; e < 2 * MT * 16 * kOm8Stride; e += 64 * NW) (&om[0][0])[e] = 0;
@@ -561,17 +634,18 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
     lds_barrier();
     mfma_chunk(om[b], a0);
   }
-  float* dst = (bi.nsplit == 1) ? (Y + bi.y_off)
-                                : (part + bi.part_off + (int64_t)it.split * bi.n * l);
+  const bool direct = ST ? it.gnsplit == 1 : bi.nsplit == 1;
+  float* dst = direct ? Y : part;
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
     if (!ln.ok[u]) continue;
+    const int64_t ob = sk_out_offset<TA, TN, NW * 16 * TN, ST>(blks, perm, bi, it, ln, u, l, jst);
 #pragma unroll
     for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * t + 4 * g + v;
-        if (row < l) dst[(int64_t)ln.col[u] * l + row] = acc[t][u][v];
+        if (row < l) dst[ob + row] = acc[t][u][v];
       }
   }
 }
@@ -598,6 +672,27 @@ __global__ __launch_bounds__(256) void sketch_reduce_kernel(const BlkInfo* __res
   TY s = 0;
   for (int sp = 0; sp < bi.nsplit; ++sp) s += p[(int64_t)sp * total];
   Y[bi.y_off + e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Stream-mode split-K reduction for snapshot j: for each listed group head
+// (grid.y) and each (block of the group, sketch row) pair, sum the group's
+// partials over its K ranges in ascending order into Y_b(:, j).
+// ---------------------------------------------------------------------------
+template <typename TY>
+__global__ __launch_bounds__(256) void sketch_stream_reduce_kernel(
+    const BlkInfo* __restrict__ blks, const int32_t* __restrict__ perm,
+    const SkItem* __restrict__ items, const int32_t* __restrict__ heads, int l, int gcap, int j,
+    TY* __restrict__ Y, const TY* __restrict__ part) {
+  const SkItem it = items[heads[blockIdx.y]];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)it.gsize * l) return;
+  const int c = (int)(e / l), r = (int)(e - (int64_t)c * l);
+  const BlkInfo bb = blks[perm[it.c0 + c]];
+  if (j >= bb.n) return;
+  TY s = 0;
+  for (int sp = 0; sp < it.gnsplit; ++sp) s += part[it.gpart + ((int64_t)sp * gcap + c) * l + r];
+  Y[bb.y_off + (int64_t)j * l + r] = s;
 }
 
 // ---------------------------------------------------------------------------

@@ -116,16 +116,6 @@ def test_omega_per_block_keys():
     compare(g, o)
 
 
-def test_streamed_columns_equal_batch():
-    shapes = [(3000, 48), (1200, 64)]
-    blocks = _rand_blocks(shapes, 11, rank=12, decay=0.2)
-    a = gpu_run(blocks, 16, 8, 3)
-    b = gpu_run(blocks, 16, 8, 3, stream_columns=True)
-    for x, y in zip(a.Y, b.Y):
-        assert np.array_equal(x, y)
-    assert np.array_equal(a.S, b.S)
-
-
 def test_padded_leading_dimension():
     shapes = [(1000, 30), (513, 64)]
     blocks = _rand_blocks(shapes, 12, rank=8, decay=0.3)
