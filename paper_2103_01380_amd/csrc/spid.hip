@@ -100,11 +100,12 @@ struct Plan {
   std::vector<int32_t> perm;
   std::vector<SkItem> sitems;
   std::vector<int32_t> sheads;
+  std::vector<int32_t> ritems;   // FP8 resident-Omega items: (first stream item, count, stride)
   int64_t st_part_elems = 0;
   int64_t sum_n = 0, sum_m = 0, part_elems = 0;
   int max_n = 0, max_split_n = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
-      off_st, off_rcpart, off_perm, off_sitems, off_sheads, total;
+      off_st, off_rcpart, off_perm, off_sitems, off_sheads, off_ritems, total;
 };
 
 spid_status validate(const spid_desc* d) {
@@ -338,6 +339,13 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
       nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nsplit, m / min_rows));
       int64_t rows = (m + nsplit - 1) / nsplit;
       rows = (rows + kKC - 1) / kKC * kKC;
+      if (d->prec == SPID_SK_FP8E4M3) {
+        // resident Omega: K ranges of whole 128-row chunks, at most kResChunks of them
+        const int64_t rmax = (int64_t)kResChunks * kKC8;
+        nsplit = (int)std::max<int64_t>(1, (m + rmax - 1) / rmax);
+        rows = (m + nsplit - 1) / nsplit;
+        rows = (rows + kKC8 - 1) / kKC8 * kKC8;
+      }
       nsplit = (int)((m + rows - 1) / rows);
       const int64_t gpart = nsplit > 1 ? st_off : 0;
       if (nsplit > 1) {
@@ -359,6 +367,29 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
       first = last;
     }
     p.st_part_elems = st_off;
+    if (d->prec == SPID_SK_FP8E4M3) {
+      // groups sharing (m, K split) in runs; pack gw of them per resident item, so
+      // that about 384 items exist
+      const int64_t gw = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)p.sitems.size() / 384));
+      size_t i = 0;
+      while (i < p.sitems.size()) {
+        // run of consecutive groups with the same m and K split
+        const SkItem& h = p.sitems[i];
+        const int ns = h.gnsplit;
+        size_t j = i;
+        while (j < p.sitems.size() && p.sitems[j].gnsplit == ns &&
+               d->h_m[p.sitems[j].blk] == d->h_m[h.blk])
+          j += ns;
+        const int64_t ngroups = (int64_t)(j - i) / ns;
+        for (int sp = 0; sp < ns; ++sp)
+          for (int64_t g0 = 0; g0 < ngroups; g0 += gw) {
+            p.ritems.push_back((int32_t)(i + g0 * ns + sp));
+            p.ritems.push_back((int32_t)std::min<int64_t>(gw, ngroups - g0));
+            p.ritems.push_back(ns);
+          }
+        i = j;
+      }
+    }
   }
   // longest items first (the hardware dispatches workgroups in grid order)
   std::stable_sort(p.items.begin(), p.items.end(), [&](const SkItem& a, const SkItem& b2) {
@@ -388,6 +419,7 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_perm = take(sizeof(int32_t) * std::max<size_t>(1, p.perm.size()));
   p.off_sitems = take(sizeof(SkItem) * std::max<size_t>(1, p.sitems.size()));
   p.off_sheads = take(sizeof(int32_t) * std::max<size_t>(1, p.sheads.size()));
+  p.off_ritems = take(sizeof(int32_t) * std::max<size_t>(1, p.ritems.size()));
   p.total = off;
   return SPID_OK;
 }
@@ -418,6 +450,14 @@ spid_status hip_check(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(SPID_EHIP, "%s: %s", what, hipGetErrorString(e));
   return SPID_OK;
+}
+
+// Kernels whose dynamic LDS exceeds 64 KiB must opt in before every launch
+// (cheap host call, no stream work, safe under graph capture).
+bool allow_lds(const void* kernel, size_t bytes) {
+  if (bytes <= 65536) return true;
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+         hipSuccess;
 }
 
 // ---- sketch dispatch
@@ -480,10 +520,28 @@ void launch_sketch_mt(spid_ctx* c, int j0, int j1, hipStream_t s) {
   }
 }
 
+template <typename TA, int MT, bool VEC>
+bool launch_fp8_resident(spid_ctx* c, int j, hipStream_t s) {
+  const Plan& p = c->plan;
+  const size_t lds = (size_t)kResChunks * MT * 16 * kOm8Stride;
+  auto kern = sketch_fp8_resident_kernel<TA, MT, kStreamNW, VEC>;
+  if (!allow_lds((const void*)kern, lds)) return false;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(p.ritems.size() / 3)), dim3(64 * kStreamNW), lds, s,
+                     c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_sitems),
+                     c->at<int32_t>(p.off_ritems), c->desc.l, c->desc.seed,
+                     c->at<int32_t>(p.off_perm), j, c->desc.lp_terms, c->at<float>(p.off_Y),
+                     c->at<float>(p.off_part));
+  return true;
+}
+
 template <typename TA, int MT>
-void launch_sketch_stream_mt(spid_ctx* c, int j, hipStream_t s) {
+bool launch_sketch_stream_mt(spid_ctx* c, int j, hipStream_t s) {
+  if (c->desc.prec == SPID_SK_FP8E4M3 && !c->plan.ritems.empty())
+    return c->all_vec ? launch_fp8_resident<TA, MT, true>(c, j, s)
+                      : launch_fp8_resident<TA, MT, false>(c, j, s);
   if (c->all_vec) launch_sketch_k<TA, MT, 1, kStreamNW, true, true>(c, 0, 0, j, s);
   else launch_sketch_k<TA, MT, 1, kStreamNW, false, true>(c, 0, 0, j, s);
+  return true;
 }
 
 template <typename TA>
@@ -499,14 +557,14 @@ void launch_sketch_a(spid_ctx* c, int j0, int j1, hipStream_t s) {
 }
 
 template <typename TA>
-void launch_sketch_stream_a(spid_ctx* c, int j, hipStream_t s) {
+bool launch_sketch_stream_a(spid_ctx* c, int j, hipStream_t s) {
   switch (c->plan.sh.MT) {
-    case 1: launch_sketch_stream_mt<TA, 1>(c, j, s); break;
-    case 2: launch_sketch_stream_mt<TA, 2>(c, j, s); break;
-    case 3: launch_sketch_stream_mt<TA, 3>(c, j, s); break;
-    case 4: launch_sketch_stream_mt<TA, 4>(c, j, s); break;
-    case 6: launch_sketch_stream_mt<TA, 6>(c, j, s); break;
-    default: launch_sketch_stream_mt<TA, 8>(c, j, s); break;
+    case 1: return launch_sketch_stream_mt<TA, 1>(c, j, s);
+    case 2: return launch_sketch_stream_mt<TA, 2>(c, j, s);
+    case 3: return launch_sketch_stream_mt<TA, 3>(c, j, s);
+    case 4: return launch_sketch_stream_mt<TA, 4>(c, j, s);
+    case 6: return launch_sketch_stream_mt<TA, 6>(c, j, s);
+    default: return launch_sketch_stream_mt<TA, 8>(c, j, s);
   }
 }
 
@@ -566,14 +624,6 @@ void launch_select_y(spid_ctx* c, hipStream_t s) {
 
 // ---- reconstruction dispatch (matrix-core kernels)
 // one attribute call per kernel instantiation for dynamic LDS above 64 KiB
-// Kernels whose dynamic LDS exceeds 64 KiB must opt in before every launch
-// (cheap host call, no stream work, safe under graph capture).
-bool allow_lds(const void* kernel, size_t bytes) {
-  if (bytes <= 65536) return true;
-  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
-         hipSuccess;
-}
-
 template <typename TA, int KS, int MTR>
 bool launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   const Plan& p = c->plan;
@@ -703,6 +753,9 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
   if (e == hipSuccess && !p.sheads.empty())
     e = hipMemcpy(c->ws + p.off_sheads, p.sheads.data(), sizeof(int32_t) * p.sheads.size(),
                   hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p.ritems.empty())
+    e = hipMemcpy(c->ws + p.off_ritems, p.ritems.data(), sizeof(int32_t) * p.ritems.size(),
+                  hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete c;
     return fail(SPID_EHIP, "spid_create: %s", hipGetErrorString(e));
@@ -754,10 +807,9 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
   if (p.st_ok && j1 - j0 <= kStreamMaxW) {
     // a few snapshots: one launch per snapshot with the blocks as MFMA columns
     for (int j = j0; j < j1; ++j) {
-      if (c->desc.a_dtype == SPID_A_F64)
-        launch_sketch_stream_a<double>(c, j, s);
-      else
-        launch_sketch_stream_a<float>(c, j, s);
+      const bool ok = c->desc.a_dtype == SPID_A_F64 ? launch_sketch_stream_a<double>(c, j, s)
+                                                    : launch_sketch_stream_a<float>(c, j, s);
+      if (!ok) return fail(SPID_EHIP, "stream sketch: cannot reserve the Omega LDS");
       spid_status st = hip_check("stream sketch kernel launch");
       if (st != SPID_OK) return st;
       if (!p.sheads.empty()) {

@@ -31,11 +31,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t p0_hi = __umulhi(0xD2511F53u, c.x);
-    const uint32_t p0_lo = 0xD2511F53u * c.x;
-    const uint32_t p1_hi = __umulhi(0xCD9E8D57u, c.z);
-    const uint32_t p1_lo = 0xCD9E8D57u * c.z;
-    c = make_uint4(p1_hi ^ c.y ^ k0, p1_lo, p0_hi ^ c.w ^ k1, p0_lo);
+    // one 32x32->64 product each (v_mad_u64_u32) instead of separate lo/hi multiplies
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                   (uint32_t)p0);
   }
   return c;
 }
@@ -67,46 +67,6 @@ __device__ __forceinline__ double2 omega_pair(uint64_t seed, uint32_t bkey, uint
   return box_muller_f64(a, b);
 }
 
-// The same pair rounded by `rnd` (round-to-nearest-even to bfloat16 or e4m3,
-// a monotone map) for the low-precision sketches, evaluated cheaply but with
-// the same result.  Box-Muller first runs in single precision: u1 -> ln u1
-// (log1p of the exact complement when u1 > 1/2), rho = sqrt(-2 ln u1), the
-// angle as sincospi(2 u2).  Error of z = rho (cos, sin) against the
-// double-precision evaluation: u2 rounded to single (angle error <= 1.9e-7),
-// sincospi (<= 2.4e-7), ln and sqrt (rho relative error <= 2.7e-7), product
-// rounding (6e-8 relative): |dz| <= 7.6e-7 rho.  With eps = rho 2^-19
-// (1.9e-6 rho) every value within eps of the single-precision z rounds alike
-// when z - eps and z + eps do (the map is monotone), so the double-precision
-// pair lies in that interval and rounds to the same value.  Only when a value
-// is that close to a rounding boundary is the double-precision pair evaluated.
-template <typename RND>
-__device__ __forceinline__ void omega_pair_rounded(uint64_t seed, uint32_t bkey, uint32_t i,
-                                                   uint32_t q, RND rnd, double& o0, double& o1) {
-  uint64_t a, b;
-  omega_words(seed, bkey, i, q, a, b);
-  float lnu;
-  if (a >= (1ull << 52)) {
-    const float v = (float)((1ull << 53) - 1u - a) * 0x1p-53f;
-    lnu = log1pf(-v);
-  } else {
-    lnu = logf((float)(a + 1u) * 0x1p-53f);
-  }
-  const float rho = sqrtf(-2.0f * lnu);
-  float sn, cs;
-  sincospif(2.0f * ((float)b * 0x1p-53f), &sn, &cs);
-  const double z0 = (double)(rho * cs), z1 = (double)(rho * sn);
-  const double eps = (double)rho * 0x1p-19 + 0x1p-60;
-  const double r0 = rnd(z0), r1 = rnd(z1);
-  if (rnd(z0 - eps) == r0 && rnd(z0 + eps) == r0 && rnd(z1 - eps) == r1 && rnd(z1 + eps) == r1) {
-    o0 = r0;
-    o1 = r1;
-    return;
-  }
-  const double2 z = box_muller_f64(a, b);
-  o0 = rnd(z.x);
-  o1 = rnd(z.y);
-}
-
 // Round-to-nearest-even of a double to bfloat16 precision (8 significant
 // bits), result as a double.  Valid for zero and for normal values inside
 // the bfloat16 exponent range (the normals of the sketch matrix).
@@ -134,6 +94,92 @@ __device__ __forceinline__ double rne_e4m3(double x) {
     r = __longlong_as_double((long long)u);
   }
   return fmin(fmax(r, -448.0), 448.0);
+}
+
+// The same roundings of a float (results exactly representable in float).
+__device__ __forceinline__ float rne_bf16_f(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+
+__device__ __forceinline__ float rne_e4m3_f(float x) {
+  float r;
+  if (fabsf(x) < 0.015625f) {
+    r = rintf(x * 512.0f) * 0.001953125f;
+  } else {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFFu + ((u >> 20) & 1u);
+    r = __uint_as_float(u & 0xFFF00000u);
+  }
+  return fminf(fmaxf(r, -448.0f), 448.0f);
+}
+
+// Omega pair rounded to nearest-even bfloat16 (KIND 0) or e4m3 (KIND 1) for
+// the low-precision sketches: equal to rounding the double-precision pair of
+// omega_pair, evaluated cheaply.  Box-Muller first runs in single precision
+// on the hardware transcendentals:
+//   ln u1: u1 > 7/8: -(v + v^2/2 + ... + v^8/8) with v = 1 - u1 taken exactly
+//          from the integer (truncation 6e-9, rounding 5.5e-7 relative);
+//          else log2(fl(u1)) ln 2 (v_log_f32: relative error <= 1.2e-7 over
+//          every float input in [2^-53, 1], measured exhaustively on gfx950;
+//          input rounding 6e-8 absolute, |ln u1| >= 0.133): relative error
+//          <= 6.6e-7, so rho = sqrt(-2 ln u1) is within 3.9e-7 relative;
+//   sin / cos of 2 pi u2: v_sin_f32 / v_cos_f32 take revolutions; their error
+//          is <= 1.26e-7 absolute over every float in [0, 1) (exhaustive), the
+//          rounding of u2 to single adds <= 1.9e-7.
+// So |dz| <= 7.6e-7 rho for both values.  With eps = rho 2^-19 (1.9e-6 rho;
+// forming z -+ eps in single precision narrows the bracket by at most one ulp
+// of z, 6e-8 rho) every value between fl(z - eps) and fl(z + eps) contains the
+// double-precision value; when both ends round alike (the rounding is
+// monotone) so does it.  Only when a value is that close to a rounding
+// boundary is the double-precision pair evaluated.
+template <int KIND>
+__device__ __forceinline__ float rne_lp_f(float x) {
+  if constexpr (KIND == 0) return rne_bf16_f(x);
+  else return rne_e4m3_f(x);
+}
+
+template <int KIND>
+__device__ __forceinline__ void omega_pair_rounded(uint64_t seed, uint32_t bkey, uint32_t i,
+                                                   uint32_t q, float& o0, float& o1) {
+  uint64_t a, b;
+  omega_words(seed, bkey, i, q, a, b);
+  float lnu;
+  if (a >= 7ull * (1ull << 50)) {
+    const float v = (float)((double)((1ull << 53) - 1u - a) * 0x1p-53);
+    float p = 1.0f / 8.0f;
+    p = __builtin_fmaf(p, v, 1.0f / 7.0f);
+    p = __builtin_fmaf(p, v, 1.0f / 6.0f);
+    p = __builtin_fmaf(p, v, 1.0f / 5.0f);
+    p = __builtin_fmaf(p, v, 0.25f);
+    p = __builtin_fmaf(p, v, 1.0f / 3.0f);
+    p = __builtin_fmaf(p, v, 0.5f);
+    p = __builtin_fmaf(p, v, 1.0f);
+    lnu = -v * p;
+  } else {
+    lnu = __builtin_amdgcn_logf((float)((double)(a + 1u) * 0x1p-53)) * 0.693147180559945309f;
+  }
+  const float rho = sqrtf(-2.0f * lnu);
+  const float u2 = (float)((double)b * 0x1p-53);
+  const float z0 = rho * __builtin_amdgcn_cosf(u2);
+  const float z1 = rho * __builtin_amdgcn_sinf(u2);
+  const float eps = rho * 0x1p-19f + 0x1p-60f;
+  const float r0 = rne_lp_f<KIND>(z0), r1 = rne_lp_f<KIND>(z1);
+  if (rne_lp_f<KIND>(z0 - eps) == r0 && rne_lp_f<KIND>(z0 + eps) == r0 &&
+      rne_lp_f<KIND>(z1 - eps) == r1 && rne_lp_f<KIND>(z1 + eps) == r1) {
+    o0 = r0;
+    o1 = r1;
+    return;
+  }
+  const double2 z = box_muller_f64(a, b);
+  if constexpr (KIND == 0) {
+    o0 = (float)rne_bf16(z.x);
+    o1 = (float)rne_bf16(z.y);
+  } else {
+    o0 = (float)rne_e4m3(z.x);
+    o1 = (float)rne_e4m3(z.y);
+  }
 }
 
 // bfloat16 bit pattern of a float (round to nearest even; exact when the

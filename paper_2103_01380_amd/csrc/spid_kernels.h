@@ -129,11 +129,10 @@ __device__ __forceinline__ void gen_omega_chunk_bf16(__bf16* __restrict__ om, in
   const int npairs = (l + 1) >> 1;
   for (int e = tid; e < npairs * kKC; e += NTHR) {
     const int q = e / kKC, kk = e - q * kKC;
-    double z0, z1;
-    omega_pair_rounded(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q,
-                       [](double x) { return rne_bf16(x); }, z0, z1);
-    om[(2 * q) * STRIDE + kk] = to_bf16((float)z0);
-    if (2 * q + 1 < l) om[(2 * q + 1) * STRIDE + kk] = to_bf16((float)z1);
+    float z0, z1;
+    omega_pair_rounded<0>(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q, z0, z1);
+    om[(2 * q) * STRIDE + kk] = to_bf16(z0);
+    if (2 * q + 1 < l) om[(2 * q + 1) * STRIDE + kk] = to_bf16(z1);
   }
 }
 
@@ -471,13 +470,12 @@ __device__ __forceinline__ void gen_omega_chunk_e4m3(uint8_t* __restrict__ om, i
   const int npairs = (l + 1) >> 1;
   for (int e = tid; e < npairs * kKC8; e += NTHR) {
     const int q = e / kKC8, kk = e - q * kKC8;
-    double z0, z1;
-    omega_pair_rounded(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q,
-                       [](double x) { return rne_e4m3(x); }, z0, z1);
+    float z0, z1;
+    omega_pair_rounded<1>(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q, z0, z1);
     // chunk row kk = 64 h + 16 w + 4 g + x sits at k = 64 h + 16 g + 4 w + x
     const int kpos = (kk & ~63) | (((kk >> 2) & 3) << 4) | (((kk >> 4) & 3) << 2) | (kk & 3);
-    om[(2 * q) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte((float)z0);
-    if (2 * q + 1 < l) om[(2 * q + 1) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte((float)z1);
+    om[(2 * q) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte(z0);
+    if (2 * q + 1 < l) om[(2 * q + 1) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte(z1);
   }
 }
 
@@ -647,6 +645,97 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
         const int row = 16 * t + 4 * g + v;
         if (row < l) dst[ob + row] = acc[t][u][v];
       }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-snapshot FP8 update with the sketch matrix resident in LDS.  A work
+// item is one K range [r0, r1) of at most kResChunks chunks shared by `cnt`
+// block groups (stream items first, first + stride, ...; equal m and K
+// split).  The workgroup generates Omega for the whole range once, then each
+// wave streams its 16 blocks of every group through it; the main loop has no
+// barriers.  Omega is regenerated once per item instead of once per group
+// and chunk.  Dynamic LDS: kResChunks * MT * 16 * kOm8Stride bytes.
+// ---------------------------------------------------------------------------
+constexpr int kResChunks = 5;
+
+template <typename TA, int MT, int NW, bool VEC>
+__global__ __launch_bounds__(64 * NW) void sketch_fp8_resident_kernel(
+    const BlkInfo* __restrict__ blks, const SkItem* __restrict__ sitems,
+    const int32_t* __restrict__ ritems, int l, uint64_t seed, const int32_t* __restrict__ perm,
+    int jst, int terms, float* __restrict__ Y, float* __restrict__ part) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t omr[];
+  constexpr int kCh = MT * 16 * kOm8Stride;
+  const int first = ritems[3 * blockIdx.x], cnt = ritems[3 * blockIdx.x + 1];
+  const int stride = ritems[3 * blockIdx.x + 2];
+  const int64_t r0 = sitems[first].r0, r1 = sitems[first].r1;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  const int nch = (int)((r1 - r0 + kKC8 - 1) / kKC8);
+  for (int e = tid; e < nch * kCh; e += 64 * NW) omr[e] = 0;
+  __syncthreads();
+  for (int c = 0; c < nch; ++c)
+    gen_omega_chunk_e4m3<64 * NW>(omr + c * kCh, l, seed, 0u, r0 + (int64_t)c * kKC8, tid);
+  lds_barrier();
+
+  const int64_t nfull = (r1 - r0) / kKC8;
+  const int64_t kt = r0 + nfull * kKC8;
+  for (int gi = 0; gi < cnt; ++gi) {
+    const SkItem it = sitems[first + gi * stride];
+    SkLane<TA, 1> ln;
+    sk_setup_stream<TA, 1>(blks, perm, it, wave * 16, r16, jst, ln);
+    f32x4 acc[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    auto load_full = [&](int64_t k0, float (&a)[32]) {
+      load_pieces_full<TA, 4, 4, 16, VEC>(ln.cb[0], k0 + 4 * g, ln.ok[0], a);
+      load_pieces_full<TA, 4, 4, 16, VEC>(ln.cb[0], k0 + 64 + 4 * g, ln.ok[0], a + 16);
+    };
+    auto mfma_chunk = [&](const uint8_t* __restrict__ omb, float (&a)[32]) {
+      i32x8 oa[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const uint8_t* orow = omb + (16 * t + r16) * kOm8Stride;
+        const i32x4 lo = *reinterpret_cast<const i32x4*>(orow + 16 * g);
+        const i32x4 hi = *reinterpret_cast<const i32x4*>(orow + 64 + 16 * g);
+        oa[t] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+      for (int h = 0; h < terms; ++h) {
+        int sb;
+        const i32x8 bt = fp8_term(a, g, sb);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) acc[t] = mfma_fp8_scaled(oa[t], bt, acc[t], 127, sb);
+      }
+    };
+    float a0[32], a1[32];
+    if (nfull > 0) load_full(r0, a0);
+    const int64_t klast = r0 + (nfull - 1) * kKC8;
+    int64_t c = 0;
+    for (; c + 2 <= nfull; c += 2) {
+      load_full(min(r0 + (c + 1) * kKC8, klast), a1);
+      mfma_chunk(omr + c * kCh, a0);
+      load_full(min(r0 + (c + 2) * kKC8, klast), a0);
+      mfma_chunk(omr + (c + 1) * kCh, a1);
+    }
+    if (c < nfull) mfma_chunk(omr + c * kCh, a0);
+    if (kt < r1) {
+      load_pieces_tail<TA, 4, 4, 16>(ln.cb[0], kt + 4 * g, r1, ln.ok[0], a0);
+      load_pieces_tail<TA, 4, 4, 16>(ln.cb[0], kt + 64 + 4 * g, r1, ln.ok[0], a0 + 16);
+      mfma_chunk(omr + nfull * kCh, a0);
+    }
+    if (ln.ok[0]) {
+      const BlkInfo bi = blks[it.blk];
+      float* dst = it.gnsplit == 1 ? Y : part;
+      const int64_t ob = sk_out_offset<TA, 1, NW * 16, true>(blks, perm, bi, it, ln, 0, l, jst);
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + 4 * g + v;
+          if (row < l) dst[ob + row] = acc[t][v];
+        }
+    }
   }
 }
 
