@@ -254,8 +254,37 @@ def dominant_roofline(w, stage, work):
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs / PEAK_HBM_GBS, 4)}
     roof["kernel"] = dom
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(w.name, dom)
     return roof
+
+
+def kernel_source_digest() -> str:
+    """Digest of the kernel sources; counter records are valid only for this digest."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("spid_kernels.h", "spid_device.h"):
+        with open(os.path.join(ROOT, "paper_2103_01380_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the recorded rocprofv3 counters
+    (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what the counter
+    reads for a plain copy of known size); None when no record exists or the kernels
+    changed since it was taken."""
+    path = os.path.join(ROOT, "paper_2103_01380_amd", "measured_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(workload)
+    if not rec or rec.get("kernel_source_sha1") != kernel_source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    kib = rec["fetch_factor"] * k["fetch_kib"] + rec["write_factor"] * (k.get("write_kib") or 0.0)
+    return round(kib * 1024.0)
 
 
 def step_roofline(w, stage, work, ms_step):
