@@ -171,10 +171,13 @@ spid_status spid_coeffs(spid_ctx* ctx, double* d_P, void* stream);
 /* Reconstruction error (Section 5.1) against the stored A:
  *   d_err2[b] = ||A_b - A_b(:,S_b) P_b||_F^2 (FP64 sum of squares),
  *   d_nrm2[b] = ||A_b||_F^2.
- * d_P as written by spid_coeffs.  d_skeleton (nullable) receives A_b(:,S_b),
+ * d_P as written by spid_coeffs (ESTATE unless spid_coeffs ran after the last
+ * spid_select).  With FP32 data and a BF16/FP8 sketch the error pass reads
+ * the split-bfloat16 copy of the same P that spid_coeffs keeps in the
+ * workspace.  d_skeleton (nullable) receives A_b(:,S_b),
  * m_b x k_max column-major in the A dtype at element offset
  * k_max * sum_{c<b} m_c (columns >= k_b untouched).  Sums are deterministic
- * (fixed reduction order).  ESTATE before spid_select. */
+ * (fixed reduction order).  ESTATE before spid_coeffs. */
 spid_status spid_reconstruct(spid_ctx* ctx, const double* d_P, double* d_err2, double* d_nrm2,
                              void* d_skeleton, void* stream);
 

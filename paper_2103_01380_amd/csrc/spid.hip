@@ -105,7 +105,8 @@ struct Plan {
   int64_t sum_n = 0, sum_m = 0, part_elems = 0;
   int max_n = 0, max_split_n = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
-      off_st, off_rcpart, off_perm, off_sitems, off_sheads, off_ritems, total;
+      off_st, off_rcpart, off_perm, off_sitems, off_sheads, off_ritems, off_pt, off_cols, off_ncols,
+      total;
 };
 
 spid_status validate(const spid_desc* d) {
@@ -234,9 +235,9 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     sh.MTR = sh.rc_bf16 ? 2 : (sh.KS <= 8 ? 4 : 2);
     sh.RC_SUB = 4 * 16 * sh.MTR;
     if (sh.rc_bf16) {
-      // one sub-tile per item, coefficients staged 64 columns at a time (static LDS)
+      // kRcBfSubs sub-tiles per item, split coefficients staged 64 columns at a time
       sh.PCAP = kRcBfCols;
-      sh.RPI = 1;
+      sh.RPI = kRcBfSubs;
     } else {
       // coefficient staging: as many columns as the LDS budget holds (multiple of 16)
       const size_t per_col = 8 * 4 * (size_t)sh.KS;
@@ -420,6 +421,11 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_sitems = take(sizeof(SkItem) * std::max<size_t>(1, p.sitems.size()));
   p.off_sheads = take(sizeof(int32_t) * std::max<size_t>(1, p.sheads.size()));
   p.off_ritems = take(sizeof(int32_t) * std::max<size_t>(1, p.ritems.size()));
+  // mixed error pass: split-bfloat16 coefficients and compact column lists
+  const size_t kp_bf = 32 * (size_t)sh.KS32;
+  p.off_pt = take(sh.rc_bf16 ? sizeof(uint16_t) * 3 * kp_bf * (size_t)p.sum_n : 256);
+  p.off_cols = take(sh.rc_bf16 ? sizeof(int32_t) * (size_t)p.sum_n : 256);
+  p.off_ncols = take(sizeof(int32_t) * nb);
   p.total = off;
   return SPID_OK;
 }
@@ -434,7 +440,7 @@ struct spid_ctx {
   char* ws = nullptr;
   bool bound = false;
   bool selected = false;
-  bool coeffs_lds_set = false;
+  bool coeffs_done = false;        // spid_coeffs ran after the last selection
   bool all_vec = false;            // every block's column starts are 16-byte aligned
   bool all_vec4 = false;           // ... and every m is a multiple of 4
   std::vector<uint8_t> covered;   // per column index: sketched since bind
@@ -643,11 +649,18 @@ bool launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
 // single-precision data on the mixed path: split-bfloat16 error pass
 template <int KS32, int MTR>
 bool launch_recon_bf16_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
+  (void)P;   // the split coefficients written by spid_coeffs are used
   const Plan& p = c->plan;
-  hipLaunchKernelGGL((recon_bf16x3_kernel<KS32, MTR>), dim3((unsigned)p.rc.size()),
-                     dim3(kRcThreads), 0, s, c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc),
-                     c->desc.k_max, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
-                     static_cast<float*>(skel), c->at<double>(p.off_rcpart));
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), 0, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.l,
+                       c->desc.k_max, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
+                       c->at<__bf16>(p.off_pt), c->at<int32_t>(p.off_cols),
+                       c->at<int32_t>(p.off_ncols), static_cast<float*>(skel),
+                       c->at<double>(p.off_rcpart));
+  };
+  if (c->all_vec4) launch(recon_bf16x3_kernel<KS32, MTR, true>);
+  else launch(recon_bf16x3_kernel<KS32, MTR, false>);
   return true;
 }
 
@@ -672,6 +685,21 @@ bool launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
     case 16: return launch_recon_t<TA, 16, 2>(c, P, skel, s);
     default: return launch_recon_t<TA, 24, 2>(c, P, skel, s);
   }
+}
+
+template <int KMAX>
+bool launch_coeffs_t(spid_ctx* c, double* P, hipStream_t s) {
+  const Plan& p = c->plan;
+  const size_t lds = sizeof(double) * (size_t)c->desc.k_max * c->desc.k_max;
+  if (!allow_lds((const void*)coeffs_kernel<KMAX>, lds)) return false;
+  const bool bf = p.sh.rc_bf16 != 0;
+  hipLaunchKernelGGL((coeffs_kernel<KMAX>), dim3(c->desc.nblocks), dim3(kCoThreads), lds, s,
+                     c->at<BlkInfo>(p.off_blk), c->desc.l, c->desc.k_max, c->at<double>(p.off_R),
+                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
+                     bf ? c->at<__bf16>(p.off_pt) : nullptr, 32 * p.sh.KS32,
+                     bf ? c->at<int32_t>(p.off_cols) : nullptr,
+                     bf ? c->at<int32_t>(p.off_ncols) : nullptr);
+  return true;
 }
 
 }  // namespace
@@ -792,6 +820,7 @@ extern "C" spid_status spid_bind_A(spid_ctx* c, const void* const* h_block_ptrs,
   if (e != hipSuccess) return fail(SPID_EHIP, "spid_bind_A: %s", hipGetErrorString(e));
   c->bound = true;
   c->selected = false;
+  c->coeffs_done = false;
   std::fill(c->covered.begin(), c->covered.end(), 0);
   return SPID_OK;
 }
@@ -833,6 +862,7 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
     }
     for (int j = j0; j < j1; ++j) c->covered[j] = 1;
     c->selected = false;
+    c->coeffs_done = false;
     return SPID_OK;
   }
   if (c->desc.a_dtype == SPID_A_F64)
@@ -857,6 +887,7 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
   }
   for (int j = j0; j < j1; ++j) c->covered[j] = 1;
   c->selected = false;
+  c->coeffs_done = false;
   return SPID_OK;
 }
 
@@ -884,24 +915,25 @@ extern "C" spid_status spid_select(spid_ctx* c, int32_t* d_k, int32_t* d_S, int3
     if (st != SPID_OK) return st;
   }
   c->selected = true;
+  c->coeffs_done = false;
   return SPID_OK;
 }
 
 extern "C" spid_status spid_coeffs(spid_ctx* c, double* d_P, void* stream) {
   if (!c || !d_P) return fail(SPID_EINVAL, "NULL argument to spid_coeffs");
   if (!c->selected) return fail(SPID_ESTATE, "spid_coeffs before spid_select");
-  const Plan& p = c->plan;
-  const size_t lds = sizeof(double) * ((size_t)c->desc.k_max * c->desc.k_max + 64 * c->desc.k_max);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (lds > 65536 && !c->coeffs_lds_set) {
-    if (hipFuncSetAttribute((const void*)coeffs_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess)
-      return fail(SPID_EHIP, "coeffs: cannot reserve %zu bytes of LDS", lds);
-    c->coeffs_lds_set = true;
+  bool ok = false;
+  switch (c->plan.sh.KMAX) {
+    case 8: ok = launch_coeffs_t<8>(c, d_P, s); break;
+    case 16: ok = launch_coeffs_t<16>(c, d_P, s); break;
+    case 32: ok = launch_coeffs_t<32>(c, d_P, s); break;
+    case 48: ok = launch_coeffs_t<48>(c, d_P, s); break;
+    case 64: ok = launch_coeffs_t<64>(c, d_P, s); break;
+    default: ok = launch_coeffs_t<96>(c, d_P, s); break;
   }
-  hipLaunchKernelGGL(coeffs_kernel, dim3(c->desc.nblocks), dim3(64), lds, s,
-                     c->at<BlkInfo>(p.off_blk), c->desc.k_max, c->at<double>(p.off_R),
-                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), d_P);
+  if (!ok) return fail(SPID_EHIP, "coeffs: cannot reserve the R11 LDS");
+  c->coeffs_done = true;
   return hip_check("coeffs kernel launch");
 }
 
@@ -909,6 +941,7 @@ extern "C" spid_status spid_reconstruct(spid_ctx* c, const double* d_P, double* 
                                         double* d_nrm2, void* d_skeleton, void* stream) {
   if (!c || !d_P || !d_err2 || !d_nrm2) return fail(SPID_EINVAL, "NULL argument to spid_reconstruct");
   if (!c->selected) return fail(SPID_ESTATE, "spid_reconstruct before spid_select");
+  if (!c->coeffs_done) return fail(SPID_ESTATE, "spid_reconstruct before spid_coeffs");
   const Plan& p = c->plan;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool ok = c->desc.a_dtype == SPID_A_F64 ? launch_recon_a<double>(c, d_P, d_skeleton, s)

@@ -7,7 +7,8 @@
 //   select_kernel     pivoted modified Gram-Schmidt on the sketch, one
 //                     workgroup per block, one sketch column per lane held in
 //                     registers, pivot search by wave + LDS reduction.
-//   coeffs_kernel     back-substitution R11 x = R12(:, j), identity columns.
+//   coeffs_kernel     back-substitution R11 x = R12(:, j), identity columns
+//                     (and the split-bfloat16 coefficients of the mixed error pass).
 //   recon_mfma_kernel streaming residual ||A - A(:,S) P||^2 per row tile, the
 //                     product A(:,S) P on the FP64 matrix cores.
 //   recon_reduce      fixed-order per-block sums of the row-tile partials.
@@ -1175,56 +1176,108 @@ __global__ void select_export_kernel(int nblocks, int k_max, const int32_t* __re
 }
 
 // ---------------------------------------------------------------------------
-// Coefficients: one wave per block.  R11 (k x k, R11[s][t] = R(s, S[t])) in
-// LDS; lane handles columns j = lane + 64 c; back-substitution with the
-// partial solution x in LDS (x[t][lane]).  Identity columns are exact.
-// Dynamic LDS: (k_max*k_max + 64*k_max) doubles.
+// Coefficients: P_b(:, S[t]) = e_t, and for every other column j the
+// back-substitution R11 x = R12(:, j) (Section 2, Algorithm 1), FP64.
+// One workgroup of kCoThreads per block: the non-skeleton columns are listed
+// in ascending order in LDS (the order the error pass uses), R11 is staged in
+// LDS, and each thread solves whole columns with the solution x held in
+// registers (KMAX >= k_max, fully unrolled; R11 entries are LDS broadcasts).
+// When `pt` is given (mixed error pass on FP32 data) the thread also writes
+// its column's three bfloat16 terms (hi, mid, lo: 24 significant bits) and
+// the compact column list, so the error pass stages them by plain copies.
+// Layouts: cols[col_off + q], pt[(col_off + q) * 3 * KP + term * KP + t] with
+// col_off = y_off / l (the block's first column in the batch), KP = 32 KS32.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void coeffs_kernel(const BlkInfo* __restrict__ blks, int k_max,
-                                                    const double* __restrict__ R,
-                                                    const int32_t* __restrict__ S_ws,
-                                                    const int32_t* __restrict__ k_ws,
-                                                    double* __restrict__ P) {
-  extern __shared__ double sm[];
+constexpr int kCoThreads = 256;
+
+template <int KMAX>
+__global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
+    const BlkInfo* __restrict__ blks, int l, int k_max, const double* __restrict__ R,
+    const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws, double* __restrict__ P,
+    __bf16* __restrict__ pt, int KP, int32_t* __restrict__ cols_out, int32_t* __restrict__ ncols_out) {
+  extern __shared__ double r11[];               // [k][k] row-major, zero below the diagonal
+  __shared__ int cols[1024];
+  __shared__ unsigned char is_sel[1024];
+  __shared__ int wcount[kCoThreads / 64];
   const int b = blockIdx.x;
   const BlkInfo bi = blks[b];
   const int n = bi.n;
   const int k = k_ws[b];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int32_t* S = S_ws + (int64_t)b * k_max;
   const double* Rb = R + bi.r_off;
   double* Pb = P + bi.p_off;
-  double* r11 = sm;                    // [k][k]
-  double* x = sm + k_max * k_max;      // [k][64]
-  for (int e = lane; e < k * k; e += 64) {
-    const int s = e / k, t = e - s * k;
-    r11[e] = (t >= s) ? Rb[(int64_t)s * n + S[t]] : 0.0;
+  for (int e = tid; e < k * k; e += kCoThreads) {
+    const int s2 = e / k, t = e - s2 * k;
+    r11[s2 * k + t] = (t >= s2) ? Rb[(int64_t)s2 * n + S[t]] : 0.0;
   }
+  // compact list of the non-skeleton columns (ascending)
+  for (int j = tid; j < n; j += kCoThreads) is_sel[j] = 0;
   __syncthreads();
-  for (int j0 = 0; j0 < n; j0 += 64) {
-    const int j = j0 + lane;
-    bool sel = false;
-    int pos = -1;
-    if (j < n) {
-      for (int t = 0; t < k; ++t)
-        if (S[t] == j) {
-          sel = true;
-          pos = t;
-        }
-    }
-    if (j < n && !sel) {
-      for (int s = k - 1; s >= 0; --s) {
-        double acc = Rb[(int64_t)s * n + j];
-        for (int t = s + 1; t < k; ++t) acc -= r11[s * k + t] * x[t * 64 + lane];
-        x[s * 64 + lane] = acc / r11[s * k + s];
+  if (tid < k) is_sel[S[tid]] = 1;
+  __syncthreads();
+  int ncols = 0;
+  for (int base = 0; base < n; base += kCoThreads) {
+    const int j = base + tid;
+    const bool keep = j < n && !is_sel[j];
+    const uint64_t bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wave] = __popcll(bal);
+    __syncthreads();
+    int off = ncols;
+    for (int v = 0; v < wave; ++v) off += wcount[v];
+    if (keep) cols[off + before] = j;
+    int tot = 0;
+    for (int v = 0; v < kCoThreads / 64; ++v) tot += wcount[v];
+    ncols += tot;
+    __syncthreads();
+  }
+  const int64_t col_off = bi.y_off / l;
+  if (pt && tid == 0) ncols_out[b] = ncols;
+  // skeleton columns: exact unit vectors
+  for (int t = tid; t < k; t += kCoThreads) {
+    double* pc = Pb + (int64_t)S[t] * k_max;
+    for (int u = 0; u < k_max; ++u) pc[u] = (u == t) ? 1.0 : 0.0;
+  }
+  for (int q = tid; q < ncols; q += kCoThreads) {
+    const int j = cols[q];
+    double x[KMAX];
+#pragma unroll
+    for (int s2 = KMAX - 1; s2 >= 0; --s2) {
+      x[s2] = 0.0;
+      if (s2 < k) {
+        double acc = Rb[(int64_t)s2 * n + j];
+        const double* rr = r11 + s2 * k;
+#pragma unroll
+        for (int t = s2 + 1; t < KMAX; ++t)
+          if (t < k) acc -= rr[t] * x[t];
+        x[s2] = acc / rr[s2];
       }
     }
-    if (j < n) {
-      double* pc = Pb + (int64_t)j * k_max;
-      for (int t = 0; t < k_max; ++t) {
-        double v = 0.0;
-        if (t < k) v = sel ? (t == pos ? 1.0 : 0.0) : x[t * 64 + lane];
-        pc[t] = v;
+    double* pc = Pb + (int64_t)j * k_max;
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t)
+      if (t < k_max) pc[t] = (t < k) ? x[t] : 0.0;
+    if (pt) {
+      cols_out[col_off + q] = j;
+      __bf16* o = pt + (col_off + q) * 3 * KP;
+#pragma unroll
+      for (int t = 0; t < KMAX; ++t) {
+        if (t < KP) {
+          const double pv = (t < k) ? x[t] : 0.0;
+          const __bf16 h = to_bf16((float)pv);
+          const double r1 = pv - (double)(float)h;
+          const __bf16 md = to_bf16((float)r1);
+          const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
+          o[t] = h;
+          o[KP + t] = md;
+          o[2 * KP + t] = lo;
+        }
+      }
+      for (int t = KMAX; t < KP; ++t) {
+        o[t] = to_bf16(0.0f);
+        o[KP + t] = to_bf16(0.0f);
+        o[2 * KP + t] = to_bf16(0.0f);
       }
     }
   }
@@ -1422,125 +1475,129 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
 // with v_mfma_f32_16x16x32_bf16.  The residual is formed in FP32 and its
 // square accumulated in FP64.  Lane (g, c) of the bf16 MFMA output holds rows
 // 4g..4g+3 of column c, so each lane loads 16 contiguous bytes per tile.
-// KS32 = k-steps of 32 selected columns; a workgroup of 4 waves covers one
-// sub-tile of 4 * 16 * MTR rows (items carry nsub = 1).  The P terms of
-// kRcBfCols columns at a time are staged in 12-36 KiB of static LDS: this
-// kernel is bound by VALU latency, and the small footprint keeps six waves
-// per SIMD resident.
+// KS32 = k-steps of 32 selected columns.  A work item is SUBS sub-tiles of
+// 4 * 16 * MTR rows; their skeleton terms stay in registers while the P
+// terms (split once by the coefficients kernel, with the compact column
+// list) are staged kRcBfCols columns at a time by plain 16-byte copies into
+// 12-36 KiB of static LDS: the kernel is bound by VALU latency, and the small
+// footprint keeps five or more waves per SIMD resident.
 // ---------------------------------------------------------------------------
 constexpr int kRcBfCols = 64;
+constexpr int kRcBfSubs = 2;
 
-template <int KS32, int MTR>
+template <int KS32, int MTR, bool VEC>
 __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
-    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max,
+    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int l, int k_max,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
-    const double* __restrict__ P, float* __restrict__ skel, double* __restrict__ part) {
+    const __bf16* __restrict__ pt_g, const int32_t* __restrict__ cols_g,
+    const int32_t* __restrict__ ncols_g, float* __restrict__ skel, double* __restrict__ part) {
   constexpr int KP = 32 * KS32;
-  __shared__ __attribute__((aligned(16))) __bf16 pt[3][kRcBfCols][KP];
+  constexpr int kSub = 4 * 16 * MTR;
+  __shared__ __attribute__((aligned(16))) __bf16 pt[kRcBfCols][3][KP];
+  __shared__ int cols[kRcBfCols];
   __shared__ double red[8];
-  __shared__ int cols[1024];
-  __shared__ unsigned char is_sel[1024];
-  __shared__ int wcount[4];
   const RcItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
   const int k = k_ws[it.blk];
   const int32_t* S = S_ws + (int64_t)it.blk * k_max;
   const float* __restrict__ A = static_cast<const float*>(bi.A);
-  const double* __restrict__ Pb = P + bi.p_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c16 = lane & 15;
-  // 16-byte loads need aligned column starts and a 4-row aligned tile start
-  const bool vec = bi.vec_ok != 0 && (it.i0 % 4) == 0;
-  const int ncols = rc_compact_columns(bi.n, k, S, is_sel, cols, wcount);
+  const int64_t col_off = bi.y_off / l;
+  const int ncols = ncols_g[it.blk];
+  const __bf16* __restrict__ ptb = pt_g + col_off * 3 * KP;
+  const int32_t* __restrict__ colb = cols_g + col_off;
 
-  const int64_t rbase = it.i0 + (int64_t)wave * 16 * MTR;
   // A operand: tile row c16, selected columns 32 ks + 8 g + v, three terms
-  bf16x8 at[MTR][KS32][3];
+  bf16x8 at[kRcBfSubs][MTR][KS32][3];
   double a2 = 0.0, e2 = 0.0;
 #pragma unroll
-  for (int mt = 0; mt < MTR; ++mt) {
-    const int64_t i = rbase + 16 * mt + c16;
+  for (int sb = 0; sb < kRcBfSubs; ++sb)
 #pragma unroll
-    for (int ks = 0; ks < KS32; ++ks) {
+    for (int mt = 0; mt < MTR; ++mt) {
+      const int64_t i = it.i0 + (int64_t)sb * kSub + wave * 16 * MTR + 16 * mt + c16;
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int t = 32 * ks + 8 * g + v;
-        float x = 0.0f;
-        if (t < k && i < bi.m) {
-          x = A[(int64_t)S[t] * bi.lda + i];
-          if (skel) skel[bi.sk_off + (int64_t)t * bi.m + i] = x;
+      for (int ks = 0; ks < KS32; ++ks) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          const int t = 32 * ks + 8 * g + v;
+          float x = 0.0f;
+          if (t < k && i < bi.m) {
+            x = A[(int64_t)S[t] * bi.lda + i];
+            if (skel) skel[bi.sk_off + (int64_t)t * bi.m + i] = x;
+          }
+          a2 += (double)x * (double)x;
+          const __bf16 h = to_bf16(x);
+          const float r1 = x - (float)h;
+          const __bf16 md = to_bf16(r1);
+          const __bf16 lo = to_bf16(r1 - (float)md);
+          at[sb][mt][ks][0][v] = h;
+          at[sb][mt][ks][1][v] = md;
+          at[sb][mt][ks][2][v] = lo;
         }
-        a2 += (double)x * (double)x;
-        const __bf16 h = to_bf16(x);
-        const float r1 = x - (float)h;
-        const __bf16 md = to_bf16(r1);
-        const __bf16 lo = to_bf16(r1 - (float)md);
-        at[mt][ks][0][v] = h;
-        at[mt][ks][1][v] = md;
-        at[mt][ks][2][v] = lo;
       }
     }
-  }
 
   for (int c0 = 0; c0 < ncols; c0 += kRcBfCols) {
     const int cc = min(kRcBfCols, ncols - c0);
-    for (int e = tid; e < kRcBfCols * KP; e += kRcThreads) {
-      const int q = e / KP, t = e - q * KP;
-      const double pv = (q < cc && t < k) ? Pb[(int64_t)cols[c0 + q] * k_max + t] : 0.0;
-      const __bf16 h = to_bf16((float)pv);
-      const double r1 = pv - (double)(float)h;
-      const __bf16 md = to_bf16((float)r1);
-      const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
-      pt[0][q][t] = h;
-      pt[1][q][t] = md;
-      pt[2][q][t] = lo;
+    constexpr int kVec = kRcBfCols * 3 * KP / 8;   // 16-byte pieces of the chunk
+    for (int e = tid; e < kVec; e += kRcThreads) {
+      const int q = e / (3 * KP / 8);
+      bf16x8 v = bf16x8{};
+      if (q < cc) v = *reinterpret_cast<const bf16x8*>(ptb + (int64_t)c0 * 3 * KP + (int64_t)e * 8);
+      *reinterpret_cast<bf16x8*>(&pt[0][0][0] + (int64_t)e * 8) = v;
     }
+    if (tid < kRcBfCols) cols[tid] = (tid < cc) ? colb[c0 + tid] : 0;
     __syncthreads();
-    for (int q0 = 0; q0 < cc; q0 += 16) {
-      const int q = q0 + c16;
-      const bool cok = q < cc;
-      const int64_t j = cok ? cols[c0 + q] : 0;
-      float av[MTR][4];
 #pragma unroll
-      for (int mt = 0; mt < MTR; ++mt) {
-        const int64_t i0 = rbase + 16 * mt + 4 * g;
-        const float* src = A + j * bi.lda + i0;
-        if (cok && vec && i0 + 4 <= bi.m) {
-          const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
-#pragma unroll
-          for (int v = 0; v < 4; ++v) av[mt][v] = x[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) av[mt][v] = (cok && i0 + v < bi.m) ? src[v] : 0.0f;
-        }
-      }
-      f32x4 acc[MTR];
-#pragma unroll
-      for (int mt = 0; mt < MTR; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < KS32; ++ks) {
-        const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(&pt[0][q0 + c16][32 * ks + 8 * g]);
-        const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(&pt[1][q0 + c16][32 * ks + 8 * g]);
-        const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(&pt[2][q0 + c16][32 * ks + 8 * g]);
+    for (int sb = 0; sb < kRcBfSubs; ++sb) {
+      const int64_t rbase = it.i0 + (int64_t)sb * kSub + wave * 16 * MTR;
+      for (int q0 = 0; q0 < cc; q0 += 16) {
+        const int q = q0 + c16;
+        const bool cok = q < cc;
+        const int64_t j = cols[cok ? q : 0];
+        float av[MTR][4];
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt) {
-          // smallest terms first
-          acc[mt] = mfma_bf16(at[mt][ks][2], p0, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][1], p1, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][0], p2, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][1], p0, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][0], p1, acc[mt]);
-          acc[mt] = mfma_bf16(at[mt][ks][0], p0, acc[mt]);
+          const int64_t i0 = rbase + 16 * mt + 4 * g;
+          const float* src = A + j * bi.lda + i0;
+          if (VEC && cok && i0 + 4 <= bi.m) {
+            const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
+#pragma unroll
+            for (int v = 0; v < 4; ++v) av[mt][v] = x[v];
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) av[mt][v] = (cok && i0 + v < bi.m) ? src[v] : 0.0f;
+          }
         }
+        f32x4 acc[MTR];
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS32; ++ks) {
+          const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(&pt[q0 + c16][0][32 * ks + 8 * g]);
+          const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(&pt[q0 + c16][1][32 * ks + 8 * g]);
+          const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(&pt[q0 + c16][2][32 * ks + 8 * g]);
+#pragma unroll
+          for (int mt = 0; mt < MTR; ++mt) {
+            // smallest terms first
+            acc[mt] = mfma_bf16(at[sb][mt][ks][2], p0, acc[mt]);
+            acc[mt] = mfma_bf16(at[sb][mt][ks][1], p1, acc[mt]);
+            acc[mt] = mfma_bf16(at[sb][mt][ks][0], p2, acc[mt]);
+            acc[mt] = mfma_bf16(at[sb][mt][ks][1], p0, acc[mt]);
+            acc[mt] = mfma_bf16(at[sb][mt][ks][0], p1, acc[mt]);
+            acc[mt] = mfma_bf16(at[sb][mt][ks][0], p0, acc[mt]);
+          }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float r = av[mt][v] - acc[mt][v];
+            e2 += (double)r * (double)r;
+            a2 += (double)av[mt][v] * (double)av[mt][v];
+          }
       }
-#pragma unroll
-      for (int mt = 0; mt < MTR; ++mt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float r = av[mt][v] - acc[mt][v];
-          e2 += (double)r * (double)r;
-          a2 += (double)av[mt][v] * (double)av[mt][v];
-        }
     }
     __syncthreads();
   }
