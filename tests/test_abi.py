@@ -86,3 +86,66 @@ def test_workspace_scales_with_batch():
     nb = sp.spid_workspace_bytes(d)
     # sketch (FP64) + R (FP64) dominate: 512*256*(42+32)*8 bytes
     assert 512 * 256 * (42 + 32) * 8 <= nb < 4 * 512 * 256 * (42 + 32) * 8
+
+
+def _tuned_bytes(tuning, **kw):
+    import paper_2103_01380_amd as sp
+    args = dict(m=[4096, 3000], n=[256, 40], l=18, k_max=8)
+    args.update(kw)
+    d = sp.make_desc(**args)
+    return sp.spid_workspace_bytes_tuned(d, sp.make_tuning(tuning)), sp.spid_last_error()
+
+
+@pytest.mark.parametrize("tuning", [
+    None, {}, dict(sk_tn=1, sk_nw=4), dict(sk_tn=2, sk_nw=8, sk_items=1024),
+    dict(sk_items=64), dict(sk_items=65536), dict(rc_rpi=1), dict(rc_rpi=16),
+])
+def test_valid_launch_shapes_are_accepted(tuning):
+    nb, err = _tuned_bytes(tuning)
+    assert nb > 0 and nb % 256 == 0, err
+
+
+@pytest.mark.parametrize("tuning,kw,msg", [
+    (dict(sk_tn=3), {}, "sk_tn"),
+    (dict(sk_tn=4), {}, "FP64 sketch"),                       # FP64: at most 2 tiles
+    (dict(sk_tn=2), dict(l=70), "FP64 sketch"),               # FP64 2 tiles only for l <= 64
+    (dict(sk_tn=4), dict(l=100, prec=1, a_dtype=1, lp_terms=2), "BF16 sketch"),
+    (dict(sk_tn=2), dict(prec=2, a_dtype=1, lp_terms=3), "FP8 sketch"),
+    (dict(sk_nw=6), {}, "sk_nw"),
+    (dict(sk_nw=4, sk_tn=2), {}, "sk_nw=4 requires sk_tn=1"),
+    (dict(sk_items=10), {}, "sk_items"),
+    (dict(rc_rpi=17), {}, "rc_rpi"),
+    (dict(rc_rpi=-1), {}, "rc_rpi"),
+])
+def test_invalid_launch_shapes_are_rejected(tuning, kw, msg):
+    nb, err = _tuned_bytes(tuning, **kw)
+    assert nb == 0
+    assert msg in err
+
+
+def test_more_sketch_items_split_blocks_further():
+    """A larger work-item target splits blocks along their rows: more split partials."""
+    a, _ = _tuned_bytes(dict(sk_items=64), m=[1 << 16] * 4, n=[64] * 4)
+    b, _ = _tuned_bytes(dict(sk_items=4096), m=[1 << 16] * 4, n=[64] * 4)
+    assert b > a
+
+
+def test_autotune_candidates_respect_instantiated_shapes():
+    from paper_2103_01380_amd import autotune as at
+    for prec, l in (("f64", 42), ("f64", 96), ("bf16", 48), ("bf16", 96), ("fp8", 96)):
+        for c in at.sketch_candidates(prec, l, 384):
+            nb, err = _tuned_bytes(c, l=l, n=[384, 384], m=[4096, 4096],
+                                   prec={"f64": 0, "bf16": 1, "fp8": 2}[prec],
+                                   a_dtype=0 if prec == "f64" else 1,
+                                   lp_terms=1 if prec == "f64" else 2)
+            assert nb > 0, (prec, l, c, err)
+    assert at.recon_candidates("f32", "bf16") == [{}]
+    assert all("rc_rpi" in c for c in at.recon_candidates("f64", "f64"))
+
+
+def test_autotune_signature_separates_batches():
+    from paper_2103_01380_amd import autotune as at
+    s1 = at.signature([100, 200], [10, 20], 18, 8, 0.0, "f64", "f64", 1)
+    s2 = at.signature([100, 201], [10, 20], 18, 8, 0.0, "f64", "f64", 1)
+    s3 = at.signature([100, 200], [10, 20], 18, 8, 0.0, "f64", "f64", 1, stream_columns=True)
+    assert len({s1, s2, s3}) == 3
