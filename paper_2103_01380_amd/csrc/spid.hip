@@ -53,6 +53,7 @@ struct Shape {
   int sel_thr;   // selection workgroup size
   int sel_rr;    // 0: all-register selection; else register rows of the hybrid kernel
   size_t sel_lds;  // dynamic LDS of the hybrid selection kernel
+  int sel_pair;    // 0, or rows per lane of the two-lanes-per-column selection
   int KMAX;      // register skeleton width in the error pass
   int KS;        // k-steps of 4 selected columns in the matrix-core error pass
   int MTR;       // 16-row MFMA tiles per wave in the error pass
@@ -202,7 +203,12 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   }
   sh.sel_rr = 0;
   sh.sel_lds = 0;
-  if (sh.LMAX > 56 || p.max_n > 512) {
+  sh.sel_pair = 0;
+  if (sh.LMAX > 56 && p.max_n <= 384) {
+    // two lanes per column, every row in registers
+    sh.sel_pair = d->l <= 64 ? 32 : (d->l <= 96 ? 48 : 64);
+    sh.sel_thr = std::max(64, (2 * p.max_n + 63) / 64 * 64);
+  } else if (sh.LMAX > 56 || p.max_n > 512) {
     // hybrid: one column per thread, RR rows in registers, the rest in LDS
     sh.CPT = 1;
     sh.sel_thr = std::max(64, (p.max_n + 63) / 64 * 64);
@@ -606,9 +612,24 @@ void launch_select_hybrid_t(spid_ctx* c, hipStream_t s) {
                      c->at<int32_t>(p.off_st));
 }
 
+template <typename TY, int RPT>
+void launch_select_pair_t(spid_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
+  hipLaunchKernelGGL((select_pair_kernel<TY, RPT>), dim3(c->desc.nblocks), dim3(p.sh.sel_thr), 0,
+                     s, c->at<BlkInfo>(p.off_blk), c->desc.l, c->desc.k_max, c->desc.tol,
+                     c->desc.rank_floor, c->at<TY>(p.off_Y), c->at<double>(p.off_R),
+                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), c->at<int32_t>(p.off_st));
+}
+
 template <typename TY>
 void launch_select_y(spid_ctx* c, hipStream_t s) {
   const Shape& sh = c->plan.sh;
+  if (sh.sel_pair) {
+    if (sh.sel_pair == 32) launch_select_pair_t<TY, 32>(c, s);
+    else if (sh.sel_pair == 48) launch_select_pair_t<TY, 48>(c, s);
+    else launch_select_pair_t<TY, 64>(c, s);
+    return;
+  }
   if (sh.sel_rr) {
     if (sh.sel_thr > 512) {
       if (sh.sel_rr == 32) launch_select_hybrid_t<TY, 32, 1024>(c, s);

@@ -986,6 +986,174 @@ __global__ __launch_bounds__(512) void select_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Column selection for tall sketches (l up to 2 RPT) on narrow blocks
+// (n <= 384): two lanes per sketch column, each holding RPT consecutive rows
+// in registers (rows >= l are zero), so the whole sketch stays in registers.
+// Dot products and norms add the two halves with one lane exchange; the
+// pivot search, publication of q and the updates follow select_kernel.
+// ---------------------------------------------------------------------------
+template <typename TY, int RPT>
+__global__ __launch_bounds__(768) void select_pair_kernel(
+    const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor,
+    const TY* __restrict__ Y, double* __restrict__ R, int32_t* __restrict__ S_ws,
+    int32_t* __restrict__ k_ws, int32_t* __restrict__ st_ws) {
+  __shared__ double q_lds[2 * RPT];
+  __shared__ double red_v[16];
+  __shared__ int red_i[16];
+  __shared__ double bc_v;
+  __shared__ double bc_rss;
+  __shared__ int bc_i;
+  const int b = blockIdx.x;
+  const BlkInfo bi = blks[b];
+  const int n = bi.n;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+  const int h = tid & 1;            // row half
+  const int j = tid >> 1;           // sketch column
+  const int r0 = h * RPT;
+  const TY* __restrict__ Yb = Y + bi.y_off;
+  double* __restrict__ Rb = R + bi.r_off;
+
+  double w[RPT];
+  bool live = j < n;
+  int bad = 0;
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    double v = 0.0;
+    if (live && r0 + i < l) v = (double)Yb[(int64_t)j * l + r0 + i];
+    if (!isfinite(v)) bad = 1;
+    w[i] = v;
+    part += v * v;
+  }
+  double nu = part + __shfl_xor(part, 1, kWave);
+  nu = live ? nu : 0.0;
+  for (int e = tid; e < 2 * RPT; e += nthr) q_lds[e] = 0.0;
+  const int any_bad = __syncthreads_or(bad);
+
+  // Frobenius norm^2 and largest column norm^2 of the sketch (each column once)
+  double fs = h == 0 ? nu : 0.0, fm = nu;
+  fs = wave_sum(fs);
+  fm = wave_max(fm);
+  if (lane == 0) red_v[wave] = fs;
+  __syncthreads();
+  double F2 = 0.0;
+  for (int v = 0; v < nwaves; ++v) F2 += red_v[v];
+  __syncthreads();
+  if (lane == 0) red_v[wave] = fm;
+  __syncthreads();
+  double nu0max = 0.0;
+  for (int v = 0; v < nwaves; ++v) nu0max = fmax(nu0max, red_v[v]);
+  __syncthreads();
+
+  int kcap = k_max;
+  if (kcap > l) kcap = l;
+  if (kcap > n) kcap = n;
+  int status = 0, taken = 0;
+  if (any_bad) {
+    status = 2;   // SPID_BLOCK_NONFINITE
+  } else {
+    for (int s = 0; s < kcap; ++s) {
+      double bv = live ? nu : -1.0;
+      int bj = live ? j : 0x7fffffff;
+      wave_argmax(bv, bj);
+      if (lane == 0) {
+        red_v[wave] = bv;
+        red_i[wave] = bj;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double v = red_v[0];
+        int i = red_i[0];
+        for (int x = 1; x < nwaves; ++x)
+          if (red_v[x] > v || (red_v[x] == v && red_i[x] < i)) {
+            v = red_v[x];
+            i = red_i[x];
+          }
+        bc_v = v;
+        bc_i = i;
+      }
+      __syncthreads();
+      const double best = bc_v;
+      const int p = bc_i;
+      if (!(best > 0.0)) {
+        status = 1;   // SPID_BLOCK_RANK_DEFICIENT
+        break;
+      }
+      if (rank_floor > 0.0 && best <= rank_floor * rank_floor * nu0max) {
+        status = 1;
+        break;
+      }
+      // the two lanes of the pivot column publish their rows and its norm
+      if (j == p) {
+        double pn = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          pn += w[i] * w[i];
+          q_lds[r0 + i] = w[i];
+        }
+        live = false;
+        nu = 0.0;
+        pn += __shfl_xor(pn, 1, kWave);   // both lanes of the column are active here
+        if (h == 0) {
+          const double rss = sqrt(pn);
+          bc_rss = rss;
+          Rb[(int64_t)s * n + p] = rss;
+          S_ws[(int64_t)b * k_max + s] = p;
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < 2 * RPT; e += nthr) q_lds[e] = q_lds[e] / bc_rss;
+      __syncthreads();
+      taken = s + 1;
+      double d = 0.0;
+#pragma unroll
+      for (int i0 = 0; i0 < RPT; i0 += 8) {
+#pragma unroll
+        for (int i = i0; i < i0 + 8; ++i) d += q_lds[r0 + i] * w[i];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      d += __shfl_xor(d, 1, kWave);
+      if (live && h == 0) Rb[(int64_t)s * n + j] = d;
+      d = live ? d : 0.0;
+      double a2 = 0.0;
+#pragma unroll
+      for (int i0 = 0; i0 < RPT; i0 += 8) {
+#pragma unroll
+        for (int i = i0; i < i0 + 8; ++i) {
+          const double qr =
+              __hip_atomic_load(q_lds + r0 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          w[i] -= d * qr;
+          a2 += w[i] * w[i];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      a2 += __shfl_xor(a2, 1, kWave);
+      nu = live ? a2 : 0.0;
+      if (tol > 0.0) {
+        double rest = h == 0 ? nu : 0.0;
+        rest = wave_sum(rest);
+        if (lane == 0) red_v[wave] = rest;
+        __syncthreads();
+        double tot = 0.0;
+        for (int v = 0; v < nwaves; ++v) tot += red_v[v];
+        if (sqrt(tot) <= tol * sqrt(F2)) {
+          __syncthreads();
+          break;
+        }
+        if (s == kcap - 1) status = 3;   // SPID_BLOCK_TOL_NOT_MET
+      }
+      __syncthreads();   // q_lds and red_v reused by the next step
+    }
+  }
+  if (tid == 0) {
+    k_ws[b] = taken;
+    st_ws[b] = status;
+  }
+  for (int s = taken + tid; s < k_max; s += nthr) S_ws[(int64_t)b * k_max + s] = -1;
+}
+
+// ---------------------------------------------------------------------------
 // Column selection for sketches too large for registers alone: thread t owns
 // column t; rows [0, RR) of its sketch column live in registers, rows
 // [RR, l) in LDS laid out row-major over the threads ([r - RR][t], so a

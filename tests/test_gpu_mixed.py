@@ -138,8 +138,8 @@ def test_wide_blocks_hybrid_selection(prec):
         assert e_gpu <= 1e-3 and r2 <= 1e-3
 
 
-def test_tall_sketch_hybrid_selection_f64():
-    """l = 96, n = 384 in double precision: the selection's hybrid register/LDS kernel
+def test_tall_sketch_pair_selection_f64():
+    """l = 96, n = 384 in double precision: the two-lanes-per-column selection kernel
     against the oracle by the FP64 gap rule."""
     rng = np.random.default_rng(25)
     blocks = []
@@ -150,5 +150,24 @@ def test_tall_sketch_hybrid_selection_f64():
     from _harness import compare
     g = gpu_run(blocks, 96, 64, 13)
     o = oracle_run(blocks, 96, 64, 13)
+    st = compare(g, o)
+    assert min(st["prefix"]) >= 10
+
+
+@pytest.mark.parametrize("l,k,shapes,tol", [
+    (60, 40, [(2560, 600, 50), (1800, 520, 30)], 0.0),     # n > 512: register + LDS rows
+    (120, 70, [(3000, 300, 90), (2000, 256, 40)], 1e-6),   # l > 96: 64 rows per lane, tolerance
+])
+def test_tall_sketch_selection_variants_f64(l, k, shapes, tol):
+    rng = np.random.default_rng(26 + l)
+    blocks = []
+    for (m, n, r) in shapes:
+        U = np.linalg.qr(rng.standard_normal((m, r)))[0]
+        V = np.linalg.qr(rng.standard_normal((n, r)))[0]
+        blocks.append(np.asfortranarray((U * 10.0 ** (-0.05 * np.arange(r))) @ V.T))
+    from _harness import compare
+    print(f"case: tall selection l={l} k={k} shapes={shapes}", flush=True)
+    g = gpu_run(blocks, l, k, 14, tol=tol)
+    o = oracle_run(blocks, l, k, 14, tol=tol)
     st = compare(g, o)
     assert min(st["prefix"]) >= 10
