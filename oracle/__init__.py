@@ -15,6 +15,13 @@ follows in arXiv 2103.01380:
 * ``coeffs``                  -- Section 2 / Algorithm 1, C = [I | R11^+ R12] Z^T.
 * ``reconstruct``             -- Section 5.1, relative Frobenius error.
 * ``compression_factor``      -- equation (cf), summed over blocks (Section 3.2).
+* ``coarse_rows`` / ``subsample`` -- Section 2 / Algorithm 2, the deterministic
+                                 coarse-grid sketch B = A(J,:) (every s-th point
+                                 per direction, Section 5.2).
+* ``interp_row`` / ``interp_matrix`` / ``interp_error`` -- Section 2,
+                                 equation (single_ID) / Algorithm 3, the
+                                 single-pass approximation M B(:,S) C with a
+                                 trilinear M (Section 5.2).
 * ``run_batch``               -- Section 3.2, independent blocks, threaded.
 
 Parity pins: every function is pinned by the ``-m "not gpu"`` tests in
@@ -89,7 +96,19 @@ def _load():
         lib.spid_ref_run_batch.argtypes = [
             c.c_int32, P, P, P, P, c.c_int32, c.c_int32, c.c_int32, c.c_double, c.c_double,
             c.c_uint64, c.c_int32, c.c_int32, P, P, c.c_int32,
-            P, P, P, P, P, P, P, P]
+            P, P, P, P, P, P, P, P, P, P]
+        lib.spid_ref_coarse_count.argtypes = [P]
+        lib.spid_ref_coarse_count.restype = c.c_int32
+        lib.spid_ref_coarse_rows.argtypes = [P, P]
+        lib.spid_ref_coarse_rows.restype = c.c_int32
+        lib.spid_ref_interp_row.argtypes = [P, c.c_int64, P, P]
+        lib.spid_ref_interp_row.restype = c.c_int
+        lib.spid_ref_subsample.argtypes = [c.c_int64, c.c_int32, P, c.c_int64, c.c_int32, P,
+                                           c.c_int32, c.c_int32, c.c_int32, c.c_int32, P]
+        lib.spid_ref_subsample.restype = c.c_int
+        lib.spid_ref_interp_error.argtypes = [P, c.c_int64, c.c_int32, P, c.c_int64, c.c_int32,
+                                              P, c.c_int32, c.c_int32, c.c_int32, P, P, P, P]
+        lib.spid_ref_interp_error.restype = c.c_int
         lib.spid_ref_run_batch.restype = c.c_int
         _lib = lib
     return _lib
@@ -155,6 +174,77 @@ def sketch(A: np.ndarray, l: int, seed: int, block_key: int = 0, prec: int = OME
     if rc != 0:
         raise ValueError("spid_ref_sketch: invalid arguments")
     return Y
+
+
+# ------------------------------------------------------------- coarse-grid sketch
+def _grid(grid) -> np.ndarray:
+    g = np.ascontiguousarray(grid, dtype=np.int32)
+    if g.shape != (7,):
+        raise ValueError("grid = (nx, ny, nz, nfields, sx, sy, sz)")
+    return g
+
+
+def coarse_rows(grid) -> np.ndarray:
+    """Rows J of the coarse grid (every s-th point per direction, all fields)."""
+    g = _grid(grid)
+    mc = _load().spid_ref_coarse_count(_ptr(g))
+    if mc < 0:
+        raise ValueError("invalid grid")
+    J = np.zeros(mc, dtype=np.int32)
+    _load().spid_ref_coarse_rows(_ptr(g), _ptr(J))
+    return J
+
+
+def subsample(A: np.ndarray, grid) -> np.ndarray:
+    """B = A(J,:) for the grid's coarse rows J, m_c x n column-major float64."""
+    A, lda, code = _a_args(A)
+    m, n = A.shape
+    J = coarse_rows(grid)
+    Y = np.zeros((len(J), n), dtype=np.float64, order="F")
+    rc = _load().spid_ref_subsample(m, n, _ptr(A), lda, code, _ptr(J), len(J), len(J), 0, n,
+                                    _ptr(Y))
+    if rc != 0:
+        raise ValueError("spid_ref_subsample: invalid arguments")
+    return Y
+
+
+def interp_row(grid, i: int):
+    """(coarse rows[8], weights[8]) of row i of the trilinear operator M."""
+    g = _grid(grid)
+    idx = np.zeros(8, dtype=np.int32)
+    w = np.zeros(8, dtype=np.float64)
+    if _load().spid_ref_interp_row(_ptr(g), int(i), _ptr(idx), _ptr(w)) != 0:
+        raise ValueError("invalid grid or row")
+    return idx, w
+
+
+def interp_matrix(grid) -> np.ndarray:
+    """Dense M (m x m_c), for small grids."""
+    g = _grid(grid)
+    m = int(g[0]) * int(g[1]) * int(g[2]) * int(g[3])
+    M = np.zeros((m, len(coarse_rows(g))))
+    for i in range(m):
+        idx, w = interp_row(g, i)
+        for c in range(8):
+            M[i, idx[c]] += w[c]
+    return M
+
+
+def interp_error(grid, A: np.ndarray, B: np.ndarray, S: np.ndarray, k: int, P: np.ndarray):
+    """(err2, nrm2) = (||A - M B(:,S) P||_F^2, ||A||_F^2), Algorithm 3's approximation."""
+    g = _grid(grid)
+    A, lda, code = _a_args(A)
+    m, n = A.shape
+    B = np.asfortranarray(B, dtype=np.float64)
+    P = np.asfortranarray(P, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.int32)
+    e = np.zeros(1)
+    a = np.zeros(1)
+    rc = _load().spid_ref_interp_error(_ptr(g), m, n, _ptr(A), lda, code, _ptr(B), B.shape[0], k,
+                                       P.shape[0], _ptr(S), _ptr(P), _ptr(e), _ptr(a))
+    if rc != 0:
+        raise ValueError("spid_ref_interp_error: invalid arguments")
+    return float(e[0]), float(a[0])
 
 
 @dataclass
@@ -234,19 +324,27 @@ class BatchResult:
     gaps: np.ndarray     # [nblocks, k_max]
     err2: np.ndarray
     nrm2: np.ndarray
+    ierr2: np.ndarray | None = None   # single-pass (interpolated) error, grids only
 
     @property
     def rel_error(self) -> float:
         return float(np.sqrt(self.err2.sum() / self.nrm2.sum()))
 
+    @property
+    def rel_interp_error(self) -> float:
+        return float(np.sqrt(self.ierr2.sum() / self.nrm2.sum()))
+
 
 def run_batch(blocks, l: int, k_max: int, seed: int, tol: float = 0.0, rank_floor: float = 0.0,
               omega_per_block: bool = False, prec: int = OMEGA_F64,
-              block_ids=None, nthreads: int | None = None) -> BatchResult:
+              block_ids=None, nthreads: int | None = None, grids=None) -> BatchResult:
     """The whole pipeline on a list of column-major blocks, one thread pool.
 
     ``block_ids`` gives each block's index in the full batch (it keys Omega
-    when ``omega_per_block``); defaults to 0..len-1.
+    when ``omega_per_block``); defaults to 0..len-1.  ``grids`` (one
+    ``(nx, ny, nz, nfields, sx, sy, sz)`` per block) switches the sketch to the
+    coarse-grid subsample B = A(J,:) (SubID) and adds the single-pass error
+    (``ierr2``); l must then be at least every block's m_c.
     """
     blocks = [np.asfortranarray(b) for b in blocks]
     dt = blocks[0].dtype
@@ -272,7 +370,12 @@ def run_batch(blocks, l: int, k_max: int, seed: int, tol: float = 0.0, rank_floo
     nrm2 = np.zeros(nb)
     if nthreads is None:
         nthreads = len(os.sched_getaffinity(0))
-    if block_ids is not None and omega_per_block:
+    g_arr = None
+    ierr2 = None
+    if grids is not None:
+        g_arr = np.ascontiguousarray(np.asarray(grids, dtype=np.int32).reshape(nb, 7))
+        ierr2 = np.zeros(nb)
+    if block_ids is not None and omega_per_block and grids is None:
         # per-block keys follow the caller's numbering: run blocks one by one
         for idx, (blk, bid) in enumerate(zip(blocks, block_ids)):
             bkey = int(bid) + 1
@@ -292,9 +395,10 @@ def run_batch(blocks, l: int, k_max: int, seed: int, tol: float = 0.0, rank_floo
                                         rank_floor, seed, int(bool(omega_per_block)), prec,
                                         _ptr(offY), _ptr(offP), int(nthreads), _ptr(Y), _ptr(S),
                                         _ptr(k), _ptr(st), _ptr(P), _ptr(gaps), _ptr(err2),
-                                        _ptr(nrm2))
+                                        _ptr(nrm2), None if g_arr is None else _ptr(g_arr),
+                                        None if ierr2 is None else _ptr(ierr2))
         if rc != 0:
             raise ValueError("spid_ref_run_batch: invalid arguments")
     Ys = [Y[offY[b]:offY[b] + l * n[b]].reshape((l, n[b]), order="F") for b in range(nb)]
     Ps = [P[offP[b]:offP[b] + k_max * n[b]].reshape((k_max, n[b]), order="F") for b in range(nb)]
-    return BatchResult(Ys, S, k, st, Ps, gaps, err2, nrm2)
+    return BatchResult(Ys, S, k, st, Ps, gaps, err2, nrm2, ierr2)

@@ -19,6 +19,11 @@
  *     sketch B (l x n, k < l << m) and transferred to A as A ~ A(:,I_B) C_B;
  *     the sketch used here is the Gaussian random projection B = Omega A with
  *     i.i.d. standard normal Omega (l x m).
+ *   - Section 2, the deterministic coarse-grid sketch B = A(J,:) (Algorithm
+ *     2, SubID: A ~ A(:,I_B) C_B) and the single-pass form A ~ M B(:,I_B) C_B
+ *     with an interpolation operator M (equation (single_ID), Algorithm 3);
+ *     Section 5.2 subsamples every s-th point per direction and interpolates
+ *     trilinearly.
  *   - Remark 2.1: the pivoted QR may stop at a tolerance instead of a fixed
  *     rank.
  *   - Section 3.2: every spatial block is compressed independently.
@@ -39,6 +44,11 @@
  *     is the inverse).
  *   - Tolerance stop: after a step, stop when the Frobenius norm of the
  *     sketch residual is at most tol times the Frobenius norm of the sketch.
+ *   - Coarse grid: coordinates 0, s, 2s, ... below the point count of each
+ *     direction (ceil(N/s) points, which ends on the last point when s divides
+ *     N - 1, as for the paper's 64-point intervals 3, 7 and 9); a fine point
+ *     past the last coarse coordinate takes that coordinate's value.  Fields
+ *     are interpolated separately.
  *   - Optional low-precision sketch matrix: Omega entries rounded to nearest
  *     even bfloat16 or OCP fp8-e4m3 from the double-precision normal (this
  *     defines a different Gaussian-like sketch matrix; the arithmetic stays in
@@ -206,6 +216,112 @@ int spid_ref_sketch(int64_t m, int32_t n, const void* A, int64_t lda,
     }
   }
   free(om);
+  return REF_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coarse grid of the deterministic sketch (Section 2: B = A(J,:) keeps the   */
+/* rows of a coarse-grid representation; Section 5.2 subsamples every s-th  */
+/* point in each spatial direction).                                          */
+/*                                                                           */
+/* grid[7] = {nx, ny, nz, nf, sx, sy, sz}: the block stacks nf fields, each   */
+/* on an nx x ny x nz structured grid; fine row = f*nx*ny*nz + x + nx*(y +   */
+/* ny*z).  Coarse coordinates per direction are 0, s, 2s, ... below the      */
+/* point count (ceil(N/s) of them); the coarse rows J are ordered the same   */
+/* way (field, then z, y, x with x fastest).                                 */
+/* ------------------------------------------------------------------------- */
+static int32_t coarse_points(int32_t npts, int32_t s) { return (npts + s - 1) / s; }
+
+/* Number of coarse rows m_c of a grid, or -1 when the grid is invalid. */
+int32_t spid_ref_coarse_count(const int32_t* grid) {
+  for (int d = 0; d < 7; d++)
+    if (grid[d] < 1) return -1;
+  int64_t c = (int64_t)grid[3] * coarse_points(grid[0], grid[4]) *
+              coarse_points(grid[1], grid[5]) * coarse_points(grid[2], grid[6]);
+  return c > INT32_MAX ? -1 : (int32_t)c;
+}
+
+/* The coarse rows J (ascending), m_c of them; returns m_c or -1. */
+int32_t spid_ref_coarse_rows(const int32_t* grid, int32_t* J) {
+  int32_t mc = spid_ref_coarse_count(grid);
+  if (mc < 0) return -1;
+  int32_t nx = grid[0], ny = grid[1], nz = grid[2], nf = grid[3];
+  int32_t cx = coarse_points(nx, grid[4]), cy = coarse_points(ny, grid[5]);
+  int32_t cz = coarse_points(nz, grid[6]);
+  int64_t pts = (int64_t)nx * ny * nz;
+  int32_t r = 0;
+  for (int32_t f = 0; f < nf; f++)
+    for (int32_t tz = 0; tz < cz; tz++)
+      for (int32_t ty = 0; ty < cy; ty++)
+        for (int32_t tx = 0; tx < cx; tx++)
+          J[r++] = (int32_t)(f * pts + (int64_t)tx * grid[4] +
+                             (int64_t)nx * ((int64_t)ty * grid[5] + (int64_t)ny * tz * grid[6]));
+  return mc;
+}
+
+/* Linear interpolation weights along one direction: fine coordinate x from   */
+/* coarse points t*s, t < nc.  Between two coarse points the usual two        */
+/* weights; at or beyond the last coarse point (a direction whose point count */
+/* is not 1 + a multiple of s) the value of the last coarse point.            */
+static void lin_weights(int32_t x, int32_t s, int32_t nc, int32_t t[2], double w[2]) {
+  int32_t t0 = x / s;
+  if (t0 >= nc - 1) {
+    t[0] = t[1] = nc - 1;
+    w[0] = 1.0;
+    w[1] = 0.0;
+    return;
+  }
+  double frac = (double)(x - t0 * s) / (double)s;
+  t[0] = t0;
+  t[1] = t0 + 1;
+  w[0] = 1.0 - frac;
+  w[1] = frac;
+}
+
+/* Row i of the trilinear interpolation operator M (fine grid <- coarse grid, */
+/* field by field): 8 coarse-row indices and weights (the tensor product of   */
+/* the three directions' linear weights).  Returns 0, or -1 for a bad row.    */
+int spid_ref_interp_row(const int32_t* grid, int64_t i, int32_t idx[8], double w[8]) {
+  if (spid_ref_coarse_count(grid) < 0) return -1;
+  int32_t nx = grid[0], ny = grid[1], nz = grid[2], nf = grid[3];
+  int64_t pts = (int64_t)nx * ny * nz;
+  if (i < 0 || i >= pts * nf) return -1;
+  int32_t f = (int32_t)(i / pts);
+  int64_t p = i - f * pts;
+  int32_t x = (int32_t)(p % nx), y = (int32_t)((p / nx) % ny), z = (int32_t)(p / ((int64_t)nx * ny));
+  int32_t cx = coarse_points(nx, grid[4]), cy = coarse_points(ny, grid[5]);
+  int32_t cz = coarse_points(nz, grid[6]);
+  int32_t tx[2], ty[2], tz[2];
+  double wx[2], wy[2], wz[2];
+  lin_weights(x, grid[4], cx, tx, wx);
+  lin_weights(y, grid[5], cy, ty, wy);
+  lin_weights(z, grid[6], cz, tz, wz);
+  int c = 0;
+  for (int a = 0; a < 2; a++)
+    for (int b = 0; b < 2; b++)
+      for (int d = 0; d < 2; d++) {
+        idx[c] = f * cx * cy * cz + tx[d] + cx * (ty[b] + cy * tz[a]);
+        w[c] = wz[a] * wy[b] * wx[d];
+        c++;
+      }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Subsampled sketch B = A(J, :) (Section 2; Algorithm 2, step 3): row r of  */
+/* B is row J[r] of A, widened exactly to double.  Y: mc x n column-major,   */
+/* leading dimension ldy >= mc.  Only columns j0 .. j0+w-1 are written.      */
+/* ------------------------------------------------------------------------- */
+int spid_ref_subsample(int64_t m, int32_t n, const void* A, int64_t lda,
+                       int32_t a_dtype, const int32_t* J, int32_t mc, int32_t ldy,
+                       int32_t j0, int32_t w, double* Y) {
+  if (m < 0 || n < 0 || mc <= 0 || ldy < mc || lda < m || j0 < 0 || w < 0 || j0 + w > n || !J)
+    return REF_EINVAL;
+  for (int32_t r = 0; r < mc; r++)
+    if (J[r] < 0 || J[r] >= m) return REF_EINVAL;
+  for (int32_t j = j0; j < j0 + w; j++)
+    for (int32_t r = 0; r < mc; r++)
+      Y[(int64_t)j * ldy + r] = a_entry(A, a_dtype, lda, J[r], j);
   return REF_OK;
 }
 
@@ -392,6 +508,54 @@ int spid_ref_reconstruct(int64_t m, int32_t n, const void* A, int64_t lda,
   return REF_OK;
 }
 
+/* Single-pass error (Section 2, equation (single_ID); Algorithm 3): the     */
+/* approximation is M B(:,S) P, with M the trilinear interpolation of         */
+/* spid_ref_interp_row and B the coarse sketch (mc x n, leading dimension     */
+/* ldb).  err2 = sum_j ||A(:,j) - (M B(:,S) P)(:,j)||^2, nrm2 = ||A||_F^2.    */
+/* The interpolated skeleton K = M B(:,S) (m x k) is formed first, then K P;  */
+/* sums in ascending i, then ascending j.                                     */
+int spid_ref_interp_error(const int32_t* grid, int64_t m, int32_t n, const void* A,
+                          int64_t lda, int32_t a_dtype, const double* B, int32_t ldb,
+                          int32_t k_eff, int32_t k_max, const int32_t* S,
+                          const double* P, double* err2, double* nrm2) {
+  int32_t mc = spid_ref_coarse_count(grid);
+  if (mc < 0 || (int64_t)grid[0] * grid[1] * grid[2] * grid[3] != m || ldb < mc ||
+      n <= 0 || lda < m || k_eff < 0 || k_eff > k_max)
+    return REF_EINVAL;
+  double* K = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) *
+                              (size_t)(k_eff > 0 ? k_eff : 1));
+  if (!K) return REF_EINVAL;
+  for (int64_t i = 0; i < m; i++) {
+    int32_t idx[8];
+    double w[8];
+    spid_ref_interp_row(grid, i, idx, w);
+    for (int32_t t = 0; t < k_eff; t++) {
+      double v = 0.0;
+      for (int c = 0; c < 8; c++) v += w[c] * B[(int64_t)S[t] * ldb + idx[c]];
+      K[(int64_t)t * m + i] = v;
+    }
+  }
+  double e2 = 0.0, a2 = 0.0;
+  for (int32_t j = 0; j < n; j++) {
+    double ej = 0.0, aj = 0.0;
+    for (int64_t i = 0; i < m; i++) {
+      double approx = 0.0;
+      for (int32_t t = 0; t < k_eff; t++)
+        approx += K[(int64_t)t * m + i] * P[(int64_t)j * k_max + t];
+      double a = a_entry(A, a_dtype, lda, i, j);
+      double r = a - approx;
+      ej += r * r;
+      aj += a * a;
+    }
+    e2 += ej;
+    a2 += aj;
+  }
+  free(K);
+  *err2 = e2;
+  *nrm2 = a2;
+  return REF_OK;
+}
+
 /* Compression factor, equation (cf), summed over blocks as in Section 3.2:
  * CF = sum_b m_b n_b / sum_b k_b (ms_b + n_b), counting matrix entries.  ms_b is the
  * row count of the stored skeleton: m_b for the ID and SubID, the coarse m_c for
@@ -418,6 +582,9 @@ double spid_ref_compression_factor(int32_t nblocks, const int64_t* m,
 /* off_P = sum_{c<b} k_max*n[c], off_Y = sum_{c<b} l*n[c]:                   */
 /*   S[b*k_max ...], k[b], status[b], P (k_max x n[b] column-major), Y,      */
 /*   gaps[b*k_max ...], err2[b], nrm2[b].                                    */
+/* grids (NULL: Gaussian sketch): grids[7*b ...] is block b's coarse grid;   */
+/* the sketch is then B = A(J,:) (SubID, Algorithm 2) and, if ierr2 is not   */
+/* NULL, ierr2[b] receives the single-pass error of Algorithm 3.             */
 /* ------------------------------------------------------------------------- */
 typedef struct {
   int32_t nblocks;
@@ -432,6 +599,8 @@ typedef struct {
   int32_t *S, *k, *status;
   double *P, *Y, *gaps, *err2, *nrm2;
   const int64_t *off_P, *off_Y;
+  const int32_t* grids; /* non-NULL: coarse-grid sketch, grids[7*b ...] */
+  double* ierr2;        /* with grids, non-NULL: single-pass error */
   int32_t next; /* next block to take, guarded by mu */
   pthread_mutex_t mu;
   int32_t rc;
@@ -443,11 +612,30 @@ static void run_one_block(batch_job* jb, int32_t b) {
   double* Y = jb->Y + jb->off_Y[b];
   double* P = jb->P + jb->off_P[b];
   uint32_t bkey = jb->omega_per_block ? (uint32_t)(b + 1) : 0u;
-  int rc = spid_ref_sketch(m, n, jb->A[b], jb->lda[b], jb->a_dtype, jb->l,
-                           jb->seed, bkey, jb->omega_prec, 0, n, Y);
+  int32_t ly = jb->l; /* rows the selection sees */
+  int rc = REF_OK;
+  if (jb->grids) {
+    /* SubID / SPID: B = A(J,:) with J the block's coarse rows; rows of the  */
+    /* l-row output past m_c stay zero (they change no sum of the selection) */
+    const int32_t* g = jb->grids + 7 * (int64_t)b;
+    int32_t mc = spid_ref_coarse_count(g);
+    int32_t* J = mc > 0 ? (int32_t*)malloc(sizeof(int32_t) * (size_t)mc) : NULL;
+    if (!J || mc > jb->l || (int64_t)g[0] * g[1] * g[2] * g[3] != m) {
+      rc = REF_EINVAL;
+    } else {
+      spid_ref_coarse_rows(g, J);
+      memset(Y, 0, sizeof(double) * (size_t)jb->l * (size_t)n);
+      rc = spid_ref_subsample(m, n, jb->A[b], jb->lda[b], jb->a_dtype, J, mc, jb->l, 0, n, Y);
+      ly = jb->l;
+    }
+    free(J);
+  } else {
+    rc = spid_ref_sketch(m, n, jb->A[b], jb->lda[b], jb->a_dtype, jb->l, jb->seed, bkey,
+                         jb->omega_prec, 0, n, Y);
+  }
   double* R = (double*)malloc(sizeof(double) * (size_t)jb->k_max * (size_t)n);
   if (rc == REF_OK && R) {
-    rc = spid_ref_select(jb->l, n, Y, jb->k_max, jb->tol, jb->rank_floor,
+    rc = spid_ref_select(ly, n, Y, jb->k_max, jb->tol, jb->rank_floor,
                          jb->S + (int64_t)b * jb->k_max, jb->k + b, R, NULL,
                          jb->gaps + (int64_t)b * jb->k_max, jb->status + b, NULL);
   }
@@ -457,6 +645,12 @@ static void run_one_block(batch_job* jb, int32_t b) {
     rc = spid_ref_reconstruct(m, n, jb->A[b], jb->lda[b], jb->a_dtype, jb->k[b],
                               jb->k_max, jb->S + (int64_t)b * jb->k_max, P,
                               jb->err2 + b, jb->nrm2 + b);
+  if (rc == REF_OK && R && jb->grids && jb->ierr2) {
+    double a2;
+    rc = spid_ref_interp_error(jb->grids + 7 * (int64_t)b, m, n, jb->A[b], jb->lda[b],
+                               jb->a_dtype, Y, jb->l, jb->k[b], jb->k_max,
+                               jb->S + (int64_t)b * jb->k_max, P, jb->ierr2 + b, &a2);
+  }
   free(R);
   if (rc != REF_OK || !R) {
     pthread_mutex_lock(&jb->mu);
@@ -483,7 +677,8 @@ int spid_ref_run_batch(int32_t nblocks, const int64_t* m, const int32_t* n,
                        uint64_t seed, int32_t omega_per_block, int32_t omega_prec,
                        const int64_t* off_Y, const int64_t* off_P, int32_t nthreads,
                        double* Y, int32_t* S, int32_t* k, int32_t* status, double* P,
-                       double* gaps, double* err2, double* nrm2) {
+                       double* gaps, double* err2, double* nrm2, const int32_t* grids,
+                       double* ierr2) {
   if (nblocks <= 0 || l <= 0 || k_max <= 0) return REF_EINVAL;
   batch_job jb;
   memset(&jb, 0, sizeof jb);
@@ -492,7 +687,7 @@ int spid_ref_run_batch(int32_t nblocks, const int64_t* m, const int32_t* n,
   jb.rank_floor = rank_floor; jb.seed = seed; jb.omega_per_block = omega_per_block;
   jb.omega_prec = omega_prec; jb.S = S; jb.k = k; jb.status = status; jb.P = P;
   jb.Y = Y; jb.gaps = gaps; jb.err2 = err2; jb.nrm2 = nrm2; jb.off_P = off_P;
-  jb.off_Y = off_Y; jb.next = 0; jb.rc = REF_OK;
+  jb.off_Y = off_Y; jb.grids = grids; jb.ierr2 = ierr2; jb.next = 0; jb.rc = REF_OK;
   pthread_mutex_init(&jb.mu, NULL);
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
