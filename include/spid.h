@@ -16,6 +16,9 @@
  *     3. coeffs      P_b = [I_k | R11^+ R12] Z^T (Section 2, Algorithm 1);
  *     4. reconstruct ||A_b - A_b(:,S_b) P_b||_F^2 and ||A_b||_F^2, the parts of
  *                    the relative Frobenius error of Section 5.1.
+ *   With the coarse-grid sketch (SPID_SK_SUBSAMPLE) step 1 is the row
+ *   subsample B = A(J,:) (Algorithm 2, SubID) and step 4 also has the
+ *   single-pass form M B(:,S) P (Algorithm 3, spid_reconstruct_interp).
  *
  * Conventions for every entry point:
  *   - Pointers marked d_ are device (HBM) pointers, h_ are host pointers.  The
@@ -70,13 +73,37 @@ typedef enum { SPID_A_F64 = 0, SPID_A_F32 = 1 } spid_adtype;
  * low-precision terms (hi + lo [+ lo2]) with FP32 accumulation; for FP8 every
  * 32 consecutive rows of a column carry their own power-of-two scale (the
  * per-block scaling).  Selection and coefficients are always FP64. */
-typedef enum { SPID_SK_F64 = 0, SPID_SK_BF16 = 1, SPID_SK_FP8E4M3 = 2 } spid_skprec;
+typedef enum {
+  SPID_SK_F64 = 0,
+  SPID_SK_BF16 = 1,
+  SPID_SK_FP8E4M3 = 2,
+  /* Deterministic coarse-grid sketch (Section 2; Algorithm 2, SubID): the
+   * sketch is the row subsample Y_b = A_b(J_b, :), J_b every s-th point per
+   * direction of block b's grid (h_grid[b]), copied exactly (widened to
+   * FP64).  Rows m_c,b .. l-1 of Y_b are zero.  No Omega: seed,
+   * omega_per_block and lp_terms are ignored. */
+  SPID_SK_SUBSAMPLE = 3
+} spid_skprec;
+
+/* Structured grid of one block for the coarse-grid sketch (Section 2,
+ * coarse-grid representation; Section 5.2 subsamples every s-th point per
+ * spatial direction).  The block stacks nfields fields, each an
+ * nx x ny x nz grid: row f*nx*ny*nz + x + nx*(y + ny*z), so
+ * m_b = nfields*nx*ny*nz.  Coarse coordinates per direction are
+ * 0, s, 2s, ... < N (ceil(N/s) points); the coarse rows J_b keep the same
+ * ordering, m_c,b = nfields * prod ceil(N/s). */
+typedef struct {
+  int32_t nx, ny, nz;  /* fine points per direction (>= 1) */
+  int32_t nfields;     /* fields stacked along the rows (>= 1) */
+  int32_t sx, sy, sz;  /* subsampling interval per direction (>= 1) */
+} spid_grid;
 
 typedef struct {
   int32_t nblocks;          /* number of spatial blocks (>= 1) */
   const int64_t* h_m;       /* host [nblocks]: rows m_b (>= 1) */
   const int32_t* h_n;       /* host [nblocks]: snapshots n_b, 1..1024 */
-  int32_t l;                /* sketch rows, 1 <= l <= 128 */
+  int32_t l;                /* sketch rows: 1 <= l <= 128 (Gaussian); coarse
+                               grid: max_b m_c,b <= l <= 2^22 */
   int32_t k_max;            /* rank (tol == 0) or rank cap (tol > 0), <= 96;
                                fixed rank requires k_max <= min(l, n_b) */
   double tol;               /* 0: fixed rank.  > 0: stop after the first step
@@ -92,6 +119,8 @@ typedef struct {
   int32_t prec;             /* spid_skprec */
   int32_t lp_terms;         /* 1..3 split terms of A for BF16/FP8 (ignored
                                for F64) */
+  const spid_grid* h_grid;  /* host [nblocks]: block grids, required for
+                               SPID_SK_SUBSAMPLE (NULL otherwise) */
 } spid_desc;
 
 /* Launch-shape choices (the batching schedule of Section 3.2's independent
@@ -180,6 +209,22 @@ spid_status spid_coeffs(spid_ctx* ctx, double* d_P, void* stream);
  * (fixed reduction order).  ESTATE before spid_coeffs. */
 spid_status spid_reconstruct(spid_ctx* ctx, const double* d_P, double* d_err2, double* d_nrm2,
                              void* d_skeleton, void* stream);
+
+/* Single-pass ID error (Section 2, equation (single_ID); Algorithm 3),
+ * coarse-grid sketch only:
+ *   d_err2[b] = ||A_b - M_b B_b(:,S_b) P_b||_F^2 (FP64 sum of squares),
+ *   d_nrm2[b] = ||A_b||_F^2,
+ * B_b = Y_b the coarse sketch and M_b the trilinear interpolation from the
+ * coarse grid to the fine grid, field by field (fine points at or past the
+ * last coarse coordinate of a direction take that coordinate's value).
+ * d_coarse_skeleton (nullable) receives B_b(:,S_b), m_c,b x k_max
+ * column-major in the A dtype at element offset k_max * sum_{c<b} m_c,c
+ * (columns >= k_b untouched): with P_b and the grid, what Algorithm 3
+ * stores.  Reads A once; the skeleton-gather pass of spid_reconstruct (the
+ * SubID error) is independent of it.  EINVAL for a Gaussian sketch, ESTATE
+ * before spid_coeffs. */
+spid_status spid_reconstruct_interp(spid_ctx* ctx, const double* d_P, double* d_err2,
+                                    double* d_nrm2, void* d_coarse_skeleton, void* stream);
 
 /* Test/diagnostic access: copy the sketch Y, widened to FP64, into d_Y
  * (block b: l x n_b column-major at element offset l * sum_{c<b} n_c). */

@@ -8,9 +8,9 @@ immediately; there is no CPU fallback.
 The functions carry the C names (``spid_workspace_bytes``, ``spid_create``,
 ``spid_bind_A``, ``spid_sketch_update``, ``spid_select``, ``spid_coeffs``,
 ``spid_reconstruct``, ``spid_copy_sketch``, ``spid_destroy``,
-``spid_last_error``, and the launch-shape variants ``spid_workspace_bytes_tuned``,
-``spid_create_tuned``, ``spid_get_tuning``); :class:`SPID` bundles them for a
-batch of blocks.
+``spid_last_error``, the launch-shape variants ``spid_workspace_bytes_tuned``,
+``spid_create_tuned``, ``spid_get_tuning``, and ``spid_reconstruct_interp`` of the
+coarse-grid sketch); :class:`SPID` bundles them for a batch of blocks.
 """
 from __future__ import annotations
 
@@ -25,18 +25,22 @@ LIB_PATH = os.path.join(_HERE, "libspid.so")
 SPID_OK, SPID_EINVAL, SPID_EWORKSPACE, SPID_EHIP, SPID_ESTATE = 0, -1, -2, -3, -4
 BLOCK_OK, BLOCK_RANK_DEFICIENT, BLOCK_NONFINITE, BLOCK_TOL_NOT_MET = 0, 1, 2, 3
 A_F64, A_F32 = 0, 1
-SK_F64, SK_BF16, SK_FP8E4M3 = 0, 1, 2
+SK_F64, SK_BF16, SK_FP8E4M3, SK_SUBSAMPLE = 0, 1, 2, 3
 
 EXPORTS = ("spid_workspace_bytes", "spid_workspace_bytes_tuned", "spid_create",
            "spid_create_tuned", "spid_get_tuning", "spid_bind_A", "spid_sketch_update",
            "spid_select", "spid_coeffs", "spid_reconstruct", "spid_copy_sketch",
-           "spid_destroy", "spid_last_error")
+           "spid_destroy", "spid_last_error", "spid_reconstruct_interp")
 
 
 class SpidError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"spid status {status}: {msg}")
         self.status = status
+
+
+class spid_grid(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in ("nx", "ny", "nz", "nfields", "sx", "sy", "sz")]
 
 
 class spid_desc(ctypes.Structure):
@@ -53,6 +57,7 @@ class spid_desc(ctypes.Structure):
         ("a_dtype", ctypes.c_int32),
         ("prec", ctypes.c_int32),
         ("lp_terms", ctypes.c_int32),
+        ("h_grid", ctypes.c_void_p),
     ]
 
 
@@ -114,6 +119,8 @@ def load_library(path: str = LIB_PATH):
     lib.spid_coeffs.restype = ctypes.c_int
     lib.spid_reconstruct.argtypes = [P, P, P, P, P, P]
     lib.spid_reconstruct.restype = ctypes.c_int
+    lib.spid_reconstruct_interp.argtypes = [P, P, P, P, P, P]
+    lib.spid_reconstruct_interp.restype = ctypes.c_int
     lib.spid_copy_sketch.argtypes = [P, P, P]
     lib.spid_copy_sketch.restype = ctypes.c_int
     lib.spid_destroy.argtypes = [P]
@@ -146,7 +153,9 @@ def _stream(stream):
 
 
 def make_desc(m, n, l, k_max, tol=0.0, rank_floor=0.0, seed=0, omega_per_block=False,
-              a_dtype=A_F64, prec=SK_F64, lp_terms=1):
+              a_dtype=A_F64, prec=SK_F64, lp_terms=1, grids=None):
+    """``grids``: ``[nblocks, 7]`` (nx, ny, nz, nfields, sx, sy, sz) for the coarse-grid
+    sketch, else None."""
     m = np.ascontiguousarray(m, dtype=np.int64)
     n = np.ascontiguousarray(n, dtype=np.int32)
     d = spid_desc()
@@ -157,7 +166,11 @@ def make_desc(m, n, l, k_max, tol=0.0, rank_floor=0.0, seed=0, omega_per_block=F
     d.seed = int(seed)
     d.omega_per_block = int(bool(omega_per_block))
     d.a_dtype, d.prec, d.lp_terms = int(a_dtype), int(prec), int(lp_terms)
-    d._keep = (m, n)       # keep the host arrays alive with the struct
+    g = None
+    if grids is not None:
+        g = np.ascontiguousarray(np.asarray(grids, dtype=np.int32).reshape(len(m), 7))
+        d.h_grid = g.ctypes.data
+    d._keep = (m, n, g)    # keep the host arrays alive with the struct
     return d
 
 
@@ -218,6 +231,11 @@ def spid_reconstruct(ctx, P, err2, nrm2, skeleton=None, stream=None):
                                            _ptr(skeleton), _stream(stream)))
 
 
+def spid_reconstruct_interp(ctx, P, err2, nrm2, coarse_skeleton=None, stream=None):
+    _check(load_library().spid_reconstruct_interp(ctx, _ptr(P), _ptr(err2), _ptr(nrm2),
+                                                  _ptr(coarse_skeleton), _stream(stream)))
+
+
 def spid_copy_sketch(ctx, Y, stream=None):
     _check(load_library().spid_copy_sketch(ctx, _ptr(Y), _stream(stream)))
 
@@ -227,7 +245,13 @@ def spid_destroy(ctx):
 
 
 # ------------------------------------------------------------------- convenience
-_PREC = {"f64": SK_F64, "bf16": SK_BF16, "fp8": SK_FP8E4M3}
+_PREC = {"f64": SK_F64, "bf16": SK_BF16, "fp8": SK_FP8E4M3, "subsample": SK_SUBSAMPLE}
+
+
+def coarse_rows_count(grid) -> int:
+    """m_c of one block grid (nx, ny, nz, nfields, sx, sy, sz)."""
+    nx, ny, nz, nf, sx, sy, sz = (int(v) for v in grid)
+    return nf * (-(-nx // sx)) * (-(-ny // sy)) * (-(-nz // sz))
 
 
 class SPID:
@@ -238,17 +262,31 @@ class SPID:
     ``[nblocks, n, m]`` tensor of equal blocks.  Outputs are torch tensors on the
     same device: ``k``, ``S`` ([nblocks, k_max]), ``status``, ``P`` (flat,
     per-block k_max x n_b column-major), ``err2``, ``nrm2``.
+
+    ``prec="subsample"`` with ``grids`` (one ``(nx, ny, nz, nfields, sx, sy, sz)`` per
+    block, or one for all) selects the coarse-grid sketch B = A(J,:); ``l`` then
+    defaults to the largest coarse row count, and :meth:`reconstruct_interp` gives
+    the single-pass error into ``err2_interp``.
     """
 
     def __init__(self, m, n, l, k_max, tol=0.0, rank_floor=0.0, seed=0, omega_per_block=False,
-                 a_dtype="f64", prec="f64", lp_terms=1, device="cuda", tuning=None):
+                 a_dtype="f64", prec="f64", lp_terms=1, device="cuda", tuning=None, grids=None):
         import torch
         self.m = np.ascontiguousarray(m, dtype=np.int64)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
         self.nblocks = len(self.m)
+        self.grids = None
+        if grids is not None:
+            g = np.asarray(grids, dtype=np.int32)
+            self.grids = np.ascontiguousarray(np.broadcast_to(g.reshape(-1, 7),
+                                                              (self.nblocks, 7)))
+            self.mc = np.array([coarse_rows_count(x) for x in self.grids], dtype=np.int64)
+            if l is None:
+                l = int(self.mc.max())
         self.l, self.k_max = int(l), int(k_max)
         self.desc = make_desc(self.m, self.n, l, k_max, tol, rank_floor, seed, omega_per_block,
-                              A_F64 if a_dtype == "f64" else A_F32, _PREC[prec], lp_terms)
+                              A_F64 if a_dtype == "f64" else A_F32, _PREC[prec], lp_terms,
+                              self.grids)
         self._tuning = make_tuning(tuning)
         nbytes = spid_workspace_bytes_tuned(self.desc, self._tuning)
         if nbytes == 0:
@@ -267,6 +305,7 @@ class SPID:
         self.P = torch.zeros(self.k_max * sum_n, dtype=torch.float64, device=self.device)
         self.err2 = torch.zeros(self.nblocks, dtype=torch.float64, device=self.device)
         self.nrm2 = torch.zeros(self.nblocks, dtype=torch.float64, device=self.device)
+        self.err2_interp = torch.zeros(self.nblocks, dtype=torch.float64, device=self.device)
         self.p_off = np.zeros(self.nblocks, dtype=np.int64)
         self.p_off[1:] = np.cumsum(self.k_max * self.n[:-1].astype(np.int64))
         self.y_off = np.zeros(self.nblocks, dtype=np.int64)
@@ -300,6 +339,11 @@ class SPID:
 
     def reconstruct(self, skeleton=None, stream=None):
         spid_reconstruct(self.ctx, self.P, self.err2, self.nrm2, skeleton, stream)
+
+    def reconstruct_interp(self, coarse_skeleton=None, stream=None):
+        """Single-pass error ||A - M B(:,S) P||^2 per block into ``err2_interp``."""
+        spid_reconstruct_interp(self.ctx, self.P, self.err2_interp, self.nrm2, coarse_skeleton,
+                                stream)
 
     def run(self, stream=None):
         """One pass of the whole method: sketch, select, coeffs, reconstruct."""

@@ -15,6 +15,7 @@
 
 #include "../../include/spid.h"
 #include "spid_kernels.h"
+#include "spid_subsample.h"
 
 using namespace spid;
 
@@ -33,6 +34,7 @@ spid_status fail(spid_status st, const char* fmt, ...) {
 }
 
 constexpr int kMaxL = 128;
+constexpr int kMaxLCoarse = 1 << 22;               // coarse-grid sketch rows
 constexpr int kMaxK = 96;
 constexpr int kMaxN = 1024;
 constexpr int kStreamNW = 8;                       // waves of a one-snapshot sketch workgroup
@@ -63,6 +65,7 @@ struct Shape {
   int rc_bf16;   // 1: split-bfloat16 error pass (FP32 data, low-precision sketch)
   int KS32;      // k-steps of 32 selected columns in the split-bfloat16 error pass
   int sk_items;  // target number of sketch work items
+  int sel_tall;  // 1: selection of a tall coarse sketch in global memory
 };
 
 int pick_mt(int l) {
@@ -103,28 +106,42 @@ struct Plan {
   std::vector<int32_t> sheads;
   std::vector<int32_t> ritems;   // FP8 resident-Omega items: (first stream item, count, stride)
   int64_t st_part_elems = 0;
+  // coarse-grid sketch: grids, interpolation-error items (kIpRows rows each)
+  bool coarse = false;
+  std::vector<GridInfo> grid;
+  std::vector<RcItem> ip;
+  std::vector<int64_t> ip_first;
+  int64_t sum_mc = 0;
   int64_t sum_n = 0, sum_m = 0, part_elems = 0;
   int max_n = 0, max_split_n = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
       off_st, off_rcpart, off_perm, off_sitems, off_sheads, off_ritems, off_pt, off_cols, off_ncols,
-      total;
+      off_grid, off_W, off_ip, off_ipfirst, off_ippart, total;
 };
 
 spid_status validate(const spid_desc* d) {
   if (!d) return fail(SPID_EINVAL, "descriptor is NULL");
   if (d->nblocks < 1) return fail(SPID_EINVAL, "nblocks must be >= 1 (got %d)", d->nblocks);
   if (!d->h_m || !d->h_n) return fail(SPID_EINVAL, "h_m and h_n must be host arrays");
-  if (d->l < 1 || d->l > kMaxL) return fail(SPID_EINVAL, "l must be in [1, %d] (got %d)", kMaxL, d->l);
+  const bool coarse = d->prec == SPID_SK_SUBSAMPLE;
+  if (!coarse && (d->l < 1 || d->l > kMaxL))
+    return fail(SPID_EINVAL, "l must be in [1, %d] (got %d)", kMaxL, d->l);
+  if (coarse && (d->l < 1 || d->l > kMaxLCoarse))
+    return fail(SPID_EINVAL, "coarse-grid sketch: l must be in [1, %d] (got %d)", kMaxLCoarse,
+                d->l);
   if (d->k_max < 1 || d->k_max > kMaxK)
     return fail(SPID_EINVAL, "k_max must be in [1, %d] (got %d)", kMaxK, d->k_max);
   if (!(d->tol >= 0.0)) return fail(SPID_EINVAL, "tol must be >= 0");
   if (!(d->rank_floor >= 0.0)) return fail(SPID_EINVAL, "rank_floor must be >= 0");
   if (d->a_dtype != SPID_A_F64 && d->a_dtype != SPID_A_F32)
     return fail(SPID_EINVAL, "a_dtype must be SPID_A_F64 or SPID_A_F32");
-  if (d->prec != SPID_SK_F64 && d->prec != SPID_SK_BF16 && d->prec != SPID_SK_FP8E4M3)
-    return fail(SPID_EINVAL, "sketch precision must be SPID_SK_F64, _BF16 or _FP8E4M3 (got %d)",
-                d->prec);
-  if (d->prec != SPID_SK_F64 && (d->lp_terms < 1 || d->lp_terms > 3))
+  if (d->prec != SPID_SK_F64 && d->prec != SPID_SK_BF16 && d->prec != SPID_SK_FP8E4M3 && !coarse)
+    return fail(SPID_EINVAL,
+                "sketch must be SPID_SK_F64, _BF16, _FP8E4M3 or _SUBSAMPLE (got %d)", d->prec);
+  if (coarse && !d->h_grid)
+    return fail(SPID_EINVAL, "coarse-grid sketch: h_grid must be a host array of block grids");
+  if ((d->prec == SPID_SK_BF16 || d->prec == SPID_SK_FP8E4M3) &&
+      (d->lp_terms < 1 || d->lp_terms > 3))
     return fail(SPID_EINVAL, "lp_terms must be 1..3 (got %d)", d->lp_terms);
   for (int b = 0; b < d->nblocks; ++b) {
     const int64_t m = d->h_m[b];
@@ -136,6 +153,20 @@ spid_status validate(const spid_desc* d) {
     if (d->tol == 0.0 && (d->k_max > d->l || d->k_max > n))
       return fail(SPID_EINVAL,
                   "block %d: fixed rank k_max=%d exceeds min(l=%d, n=%d)", b, d->k_max, d->l, n);
+    if (coarse) {
+      const spid_grid& g = d->h_grid[b];
+      if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nfields < 1 || g.sx < 1 || g.sy < 1 || g.sz < 1)
+        return fail(SPID_EINVAL, "block %d: grid sizes and intervals must be >= 1", b);
+      const int64_t pts = (int64_t)g.nx * g.ny * g.nz * g.nfields;
+      if (pts != m)
+        return fail(SPID_EINVAL, "block %d: grid has %lld rows, m = %lld", b, (long long)pts,
+                    (long long)m);
+      const int64_t mc = (int64_t)g.nfields * ((g.nx + g.sx - 1) / g.sx) *
+                         ((g.ny + g.sy - 1) / g.sy) * ((g.nz + g.sz - 1) / g.sz);
+      if (mc > d->l)
+        return fail(SPID_EINVAL, "block %d: %lld coarse rows exceed l = %d", b, (long long)mc,
+                    d->l);
+    }
   }
   return SPID_OK;
 }
@@ -169,7 +200,8 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   st = validate_tuning(d, tune, pick_mt(d->l));
   if (st != SPID_OK) return st;
   const int nb = d->nblocks;
-  p.ydt = (d->prec == SPID_SK_F64) ? 0 : 1;
+  p.coarse = d->prec == SPID_SK_SUBSAMPLE;
+  p.ydt = (d->prec == SPID_SK_F64 || p.coarse) ? 0 : 1;
   for (int b = 0; b < nb; ++b) {
     p.sum_n += d->h_n[b];
     p.sum_m += d->h_m[b];
@@ -196,6 +228,7 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     sh.NW = 8;
   }
   sh.LMAX = pick_lmax(d->l);
+  sh.sel_tall = (p.coarse && d->l > kMaxL) ? 1 : 0;
   sh.CPT = (p.max_n > 512) ? 2 : 1;
   {
     int need = (p.max_n + sh.CPT - 1) / sh.CPT;
@@ -204,7 +237,9 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   sh.sel_rr = 0;
   sh.sel_lds = 0;
   sh.sel_pair = 0;
-  if (sh.LMAX > 56 && p.max_n <= 384) {
+  if (sh.sel_tall) {
+    // coarse sketch taller than the register/LDS kernels take: global memory
+  } else if (sh.LMAX > 56 && p.max_n <= 384) {
     // two lanes per column, every row in registers
     sh.sel_pair = d->l <= 64 ? 32 : (d->l <= 96 ? 48 : 64);
     sh.sel_thr = std::max(64, (2 * p.max_n + 63) / 64 * 64);
@@ -222,7 +257,8 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
         break;
       }
     }
-    if (sh.sel_rr == 0)
+    if (sh.sel_rr == 0 && p.coarse) sh.sel_tall = 1;
+    if (sh.sel_rr == 0 && !p.coarse)
       return fail(SPID_EINVAL, "l=%d with n up to %d exceeds the selection register/LDS budget",
                   d->l, p.max_n);
   }
@@ -236,7 +272,8 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
         sh.KS = o;
         break;
       }
-    sh.rc_bf16 = (d->a_dtype == SPID_A_F32 && d->prec != SPID_SK_F64) ? 1 : 0;
+    sh.rc_bf16 = (d->a_dtype == SPID_A_F32 &&
+                  (d->prec == SPID_SK_BF16 || d->prec == SPID_SK_FP8E4M3)) ? 1 : 0;
     sh.KS32 = (d->k_max + 31) / 32;
     sh.MTR = sh.rc_bf16 ? 2 : (sh.KS <= 8 ? 4 : 2);
     sh.RC_SUB = 4 * 16 * sh.MTR;
@@ -277,6 +314,7 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     const double tile_cost = (double)m * std::min(n, tile_cols);
     int nsplit = (int)std::ceil(tile_cost / target_cost);
     nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nsplit, m / min_rows));
+    if (p.coarse) nsplit = 1;
     // rows per split, multiple of the chunk
     int64_t rows = (m + nsplit - 1) / nsplit;
     rows = (rows + kKC - 1) / kKC * kKC;
@@ -303,7 +341,7 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
       p.split_blocks.push_back(b);
       p.max_split_n = std::max(p.max_split_n, (int)n);
     }
-    for (int c0 = 0; c0 < n; c0 += tile_cols)
+    for (int c0 = 0; c0 < n && !p.coarse; c0 += tile_cols)
       for (int s = 0; s < nsplit; ++s) {
         SkItem it{};
         it.blk = b;
@@ -326,8 +364,41 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.rc_first.push_back((int64_t)p.rc.size());
   p.part_elems = part_off;
 
+  if (p.coarse) {
+    p.grid.resize(nb);
+    int64_t cs_off = 0;
+    for (int b = 0; b < nb; ++b) {
+      const spid_grid& g = d->h_grid[b];
+      GridInfo gi{};
+      gi.nx = g.nx;
+      gi.ny = g.ny;
+      gi.nz = g.nz;
+      gi.nf = g.nfields;
+      gi.sx = g.sx;
+      gi.sy = g.sy;
+      gi.sz = g.sz;
+      gi.cx = (g.nx + g.sx - 1) / g.sx;
+      gi.cy = (g.ny + g.sy - 1) / g.sy;
+      gi.cz = (g.nz + g.sz - 1) / g.sz;
+      gi.mc = g.nfields * gi.cx * gi.cy * gi.cz;
+      gi.cs_off = cs_off;
+      cs_off += (int64_t)gi.mc * d->k_max;
+      p.sum_mc += gi.mc;
+      p.grid[b] = gi;
+      p.ip_first.push_back((int64_t)p.ip.size());
+      for (int64_t i0 = 0; i0 < d->h_m[b]; i0 += kIpRows) {
+        RcItem r{};
+        r.blk = b;
+        r.i0 = i0;
+        r.nsub = 1;
+        p.ip.push_back(r);
+      }
+    }
+    p.ip_first.push_back((int64_t)p.ip.size());
+  }
+
   // one-snapshot (stream) plan: needs Omega shared by all blocks
-  p.st_ok = d->omega_per_block == 0;
+  p.st_ok = d->omega_per_block == 0 && !p.coarse;
   if (p.st_ok) {
     p.perm.resize(nb);
     for (int b = 0; b < nb; ++b) p.perm[b] = b;
@@ -432,6 +503,11 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_pt = take(sh.rc_bf16 ? sizeof(uint16_t) * 3 * kp_bf * (size_t)p.sum_n : 256);
   p.off_cols = take(sh.rc_bf16 ? sizeof(int32_t) * (size_t)p.sum_n : 256);
   p.off_ncols = take(sizeof(int32_t) * nb);
+  p.off_grid = take(sizeof(GridInfo) * std::max<size_t>(1, p.grid.size()));
+  p.off_W = take(sh.sel_tall ? sizeof(double) * (size_t)d->l * p.sum_n : 256);
+  p.off_ip = take(sizeof(RcItem) * std::max<size_t>(1, p.ip.size()));
+  p.off_ipfirst = take(sizeof(int64_t) * std::max<size_t>(1, p.ip_first.size()));
+  p.off_ippart = take(sizeof(double) * 2 * std::max<size_t>(1, p.ip.size()));
   p.total = off;
   return SPID_OK;
 }
@@ -773,6 +849,7 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
     return fail(SPID_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, p.total);
   }
   c->desc = *desc;
+  c->desc.h_grid = nullptr;   // the grids live in the plan
   c->m.assign(desc->h_m, desc->h_m + desc->nblocks);
   c->n.assign(desc->h_n, desc->h_n + desc->nblocks);
   c->desc.h_m = c->m.data();
@@ -781,7 +858,7 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
   c->covered.assign(p.max_n, 0);
   hipError_t e = hipMemcpy(c->ws + p.off_blk, p.blk.data(), sizeof(BlkInfo) * p.blk.size(),
                            hipMemcpyHostToDevice);
-  if (e == hipSuccess)
+  if (e == hipSuccess && !p.items.empty())
     e = hipMemcpy(c->ws + p.off_items, p.items.data(), sizeof(SkItem) * p.items.size(),
                   hipMemcpyHostToDevice);
   if (e == hipSuccess && !p.split_blocks.empty())
@@ -804,6 +881,15 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
                   hipMemcpyHostToDevice);
   if (e == hipSuccess && !p.ritems.empty())
     e = hipMemcpy(c->ws + p.off_ritems, p.ritems.data(), sizeof(int32_t) * p.ritems.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && p.coarse)
+    e = hipMemcpy(c->ws + p.off_grid, p.grid.data(), sizeof(GridInfo) * p.grid.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && p.coarse)
+    e = hipMemcpy(c->ws + p.off_ip, p.ip.data(), sizeof(RcItem) * p.ip.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && p.coarse)
+    e = hipMemcpy(c->ws + p.off_ipfirst, p.ip_first.data(), sizeof(int64_t) * p.ip_first.size(),
                   hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete c;
@@ -854,6 +940,25 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
   const int j1 = (int)std::min<int64_t>((int64_t)j0 + w, p.max_n);
   if (j0 >= p.max_n) return fail(SPID_EINVAL, "j0=%d is past every block's last column", j0);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p.coarse) {
+    const int64_t per_blk = (int64_t)c->desc.l * (j1 - j0);
+    dim3 grid((unsigned)std::min<int64_t>((per_blk + 255) / 256, 1 << 20),
+              (unsigned)std::min(c->desc.nblocks, 65535));
+    if (c->desc.a_dtype == SPID_A_F64)
+      hipLaunchKernelGGL((subsample_kernel<double>), grid, dim3(256), 0, s,
+                         c->at<BlkInfo>(p.off_blk), c->at<GridInfo>(p.off_grid),
+                         c->desc.nblocks, c->desc.l, j0, j1, c->at<double>(p.off_Y));
+    else
+      hipLaunchKernelGGL((subsample_kernel<float>), grid, dim3(256), 0, s,
+                         c->at<BlkInfo>(p.off_blk), c->at<GridInfo>(p.off_grid),
+                         c->desc.nblocks, c->desc.l, j0, j1, c->at<double>(p.off_Y));
+    spid_status st = hip_check("subsample kernel launch");
+    if (st != SPID_OK) return st;
+    for (int j = j0; j < j1; ++j) c->covered[j] = 1;
+    c->selected = false;
+    c->coeffs_done = false;
+    return SPID_OK;
+  }
   if (p.st_ok && j1 - j0 <= kStreamMaxW) {
     // a few snapshots: one launch per snapshot with the blocks as MFMA columns
     for (int j = j0; j < j1; ++j) {
@@ -919,7 +1024,14 @@ extern "C" spid_status spid_select(spid_ctx* c, int32_t* d_k, int32_t* d_S, int3
     if (!c->covered[j])
       return fail(SPID_ESTATE, "spid_select: sketch column %d has not been computed", j);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (c->plan.ydt == 0)
+  if (c->plan.sh.sel_tall)
+    hipLaunchKernelGGL(select_tall_kernel, dim3(c->desc.nblocks), dim3(kTallThreads), 0, s,
+                       c->at<BlkInfo>(c->plan.off_blk), c->desc.l, c->desc.k_max, c->desc.tol,
+                       c->desc.rank_floor, c->at<double>(c->plan.off_Y),
+                       c->at<double>(c->plan.off_W), c->at<double>(c->plan.off_R),
+                       c->at<int32_t>(c->plan.off_S), c->at<int32_t>(c->plan.off_k),
+                       c->at<int32_t>(c->plan.off_st));
+  else if (c->plan.ydt == 0)
     launch_select_y<double>(c, s);
   else
     launch_select_y<float>(c, s);
@@ -974,6 +1086,67 @@ extern "C" spid_status spid_reconstruct(spid_ctx* c, const double* d_P, double* 
                      c->desc.nblocks, c->at<int64_t>(p.off_rcfirst), c->at<double>(p.off_rcpart),
                      d_err2, d_nrm2);
   return hip_check("reconstruct reduce launch");
+}
+
+namespace {
+
+template <typename TA, int KMAX>
+void launch_interp_t(spid_ctx* c, const double* P, hipStream_t s) {
+  const Plan& p = c->plan;
+  hipLaunchKernelGGL((interp_error_kernel<TA, KMAX>), dim3((unsigned)p.ip.size()), dim3(kIpRows),
+                     0, s, c->at<BlkInfo>(p.off_blk), c->at<GridInfo>(p.off_grid),
+                     c->at<RcItem>(p.off_ip), c->desc.l, c->desc.k_max, c->at<int32_t>(p.off_S),
+                     c->at<int32_t>(p.off_k), c->at<double>(p.off_Y), P,
+                     c->at<double>(p.off_ippart));
+}
+
+template <typename TA>
+void launch_interp_a(spid_ctx* c, const double* P, void* cskel, hipStream_t s) {
+  switch (c->plan.sh.KMAX) {
+    case 8: launch_interp_t<TA, 8>(c, P, s); break;
+    case 16: launch_interp_t<TA, 16>(c, P, s); break;
+    case 32: launch_interp_t<TA, 32>(c, P, s); break;
+    case 48: launch_interp_t<TA, 48>(c, P, s); break;
+    case 64: launch_interp_t<TA, 64>(c, P, s); break;
+    default: launch_interp_t<TA, 96>(c, P, s); break;
+  }
+  if (cskel) {
+    const Plan& p = c->plan;
+    int mcmax = 1;
+    for (const GridInfo& g : p.grid) mcmax = std::max(mcmax, g.mc);
+    const int64_t per_blk = (int64_t)mcmax * c->desc.k_max;
+    dim3 grid((unsigned)std::min<int64_t>((per_blk + 255) / 256, 1 << 20),
+              (unsigned)std::min(c->desc.nblocks, 65535));
+    hipLaunchKernelGGL((coarse_skeleton_kernel<TA>), grid, dim3(256), 0, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<GridInfo>(p.off_grid), c->desc.nblocks,
+                       c->desc.l, c->desc.k_max, c->at<int32_t>(p.off_S),
+                       c->at<int32_t>(p.off_k), c->at<double>(p.off_Y), static_cast<TA*>(cskel));
+  }
+}
+
+}  // namespace
+
+extern "C" spid_status spid_reconstruct_interp(spid_ctx* c, const double* d_P, double* d_err2,
+                                               double* d_nrm2, void* d_coarse_skeleton,
+                                               void* stream) {
+  if (!c || !d_P || !d_err2 || !d_nrm2)
+    return fail(SPID_EINVAL, "NULL argument to spid_reconstruct_interp");
+  if (!c->plan.coarse)
+    return fail(SPID_EINVAL, "spid_reconstruct_interp needs the coarse-grid sketch");
+  if (!c->selected) return fail(SPID_ESTATE, "spid_reconstruct_interp before spid_select");
+  if (!c->coeffs_done) return fail(SPID_ESTATE, "spid_reconstruct_interp before spid_coeffs");
+  const Plan& p = c->plan;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->desc.a_dtype == SPID_A_F64)
+    launch_interp_a<double>(c, d_P, d_coarse_skeleton, s);
+  else
+    launch_interp_a<float>(c, d_P, d_coarse_skeleton, s);
+  spid_status st = hip_check("interpolated error kernel launch");
+  if (st != SPID_OK) return st;
+  hipLaunchKernelGGL(recon_reduce_kernel, dim3((c->desc.nblocks + 255) / 256), dim3(256), 0, s,
+                     c->desc.nblocks, c->at<int64_t>(p.off_ipfirst), c->at<double>(p.off_ippart),
+                     d_err2, d_nrm2);
+  return hip_check("interpolated error reduce launch");
 }
 
 extern "C" spid_status spid_copy_sketch(spid_ctx* c, double* d_Y, void* stream) {

@@ -1,0 +1,386 @@
+// spid_subsample.h -- device kernels of the deterministic coarse-grid sketch
+// (arXiv 2103.01380, Section 2): the sketch is the row subsample
+// B = A(J,:) of a coarse grid (Algorithm 2, SubID), the selection runs on B,
+// and the single-pass approximation M B(:,S) C interpolates the coarse
+// skeleton back to the fine grid (equation (single_ID), Algorithm 3) with a
+// trilinear M (Section 5.2).
+//
+// Grid convention: block b stacks nf fields, each on an nx x ny x nz
+// structured grid, fine row f*nx*ny*nz + x + nx*(y + ny*z).  Coarse
+// coordinates per direction are 0, s, 2s, ... below the point count
+// (ceil(N/s) points); coarse rows use the same ordering.  A fine point at or
+// past the last coarse coordinate of a direction takes that coordinate's
+// value (the grid is not extended).
+#pragma once
+
+#include "spid_kernels.h"
+
+namespace spid {
+
+struct GridInfo {
+  int32_t nx, ny, nz, nf;  // fine points per direction, fields
+  int32_t sx, sy, sz;      // subsampling interval per direction
+  int32_t cx, cy, cz;      // coarse points per direction
+  int32_t mc;              // coarse rows of the block, nf * cx * cy * cz
+  int32_t pad;
+  int64_t cs_off;          // element offset of the block's coarse skeleton (mc x k_max)
+};
+
+// fine row of coarse row r
+__device__ __forceinline__ int64_t coarse_to_fine(const GridInfo& g, int r) {
+  const int cxyz = g.cx * g.cy * g.cz;
+  const int f = r / cxyz;
+  int p = r - f * cxyz;
+  const int tx = p % g.cx;
+  p /= g.cx;
+  const int ty = p % g.cy;
+  const int tz = p / g.cy;
+  return (int64_t)f * g.nx * g.ny * g.nz + (int64_t)tx * g.sx +
+         (int64_t)g.nx * ((int64_t)ty * g.sy + (int64_t)g.ny * tz * g.sz);
+}
+
+// linear weights of fine coordinate x between coarse points t*s, t < nc
+__device__ __forceinline__ void lin_weights(int x, int s, int nc, int& t0, int& t1, double& w0,
+                                            double& w1) {
+  const int t = x / s;
+  if (t >= nc - 1) {
+    t0 = t1 = nc - 1;
+    w0 = 1.0;
+    w1 = 0.0;
+  } else {
+    const double frac = (double)(x - t * s) / (double)s;
+    t0 = t;
+    t1 = t + 1;
+    w0 = 1.0 - frac;
+    w1 = frac;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sketch update of the coarse-grid sketch: Y_b(r, j) = A_b(J_b[r], j) for
+// r < mc_b and 0 for mc_b <= r < l (zero rows change no sum of the
+// selection), columns [j0, min(j1, n_b)).  One thread per sketch entry, rows
+// fastest (coalesced sketch writes; the reads are the subsample's stride).
+// Grid: x covers l * (j1 - j0) entries, y strides over blocks.
+// ---------------------------------------------------------------------------
+template <typename TA>
+__global__ __launch_bounds__(256) void subsample_kernel(const BlkInfo* __restrict__ blks,
+                                                        const GridInfo* __restrict__ grids,
+                                                        int nblocks, int l, int j0, int j1,
+                                                        double* __restrict__ Y) {
+  for (int b = blockIdx.y; b < nblocks; b += gridDim.y) {
+    const int n = blks[b].n;
+    const int je = min(j1, n);
+    if (je <= j0) continue;
+    const int64_t lda = blks[b].lda;
+    const int64_t y_off = blks[b].y_off;
+    const TA* __restrict__ A = static_cast<const TA*>(blks[b].A);
+    const GridInfo g = grids[b];
+    const int64_t total = (int64_t)l * (je - j0);
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+      const int jj = (int)(e / l);
+      const int r = (int)(e - (int64_t)jj * l);
+      const int j = j0 + jj;
+      double v = 0.0;
+      if (r < g.mc) v = (double)A[(int64_t)j * lda + coarse_to_fine(g, r)];
+      Y[y_off + (int64_t)j * l + r] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column selection of tall sketches (Section 2, Algorithm 1 mgsqr on B; the
+// coarse grid can have far more rows than registers and LDS hold): the
+// working copy W of the block's sketch lives in global memory (L2-resident
+// for the block being processed), one workgroup of four waves per block,
+// one wave per column with the rows over the lanes (coalesced), so every
+// dot product and norm is a wave reduction.  Same steps, stopping rules and
+// outputs as the register kernels: pivot = largest residual norm (ties to
+// the lowest index), q = W(:,p)/||W(:,p)|| (stored over W(:,p)), one
+// Gram-Schmidt sweep, norms recomputed.
+// ---------------------------------------------------------------------------
+constexpr int kTallThreads = 256;
+constexpr int kTallMaxN = 1024;
+
+__global__ __launch_bounds__(kTallThreads) void select_tall_kernel(
+    const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor,
+    const double* __restrict__ Y, double* __restrict__ W, double* __restrict__ R,
+    int32_t* __restrict__ S_ws, int32_t* __restrict__ k_ws, int32_t* __restrict__ st_ws) {
+  __shared__ double nu[kTallMaxN];
+  __shared__ unsigned char used[kTallMaxN];
+  __shared__ double red_v[kTallThreads / kWave];
+  __shared__ int red_i[kTallThreads / kWave];
+  constexpr int NWV = kTallThreads / kWave;
+  const int b = blockIdx.x;
+  const BlkInfo bi = blks[b];
+  const int n = bi.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* __restrict__ Yb = Y + bi.y_off;
+  double* __restrict__ Wb = W + bi.y_off;
+  double* __restrict__ Rb = R + bi.r_off;
+
+  int bad = 0;
+  for (int j = wave; j < n; j += NWV) {
+    double acc = 0.0;
+    for (int r = lane; r < l; r += kWave) {
+      const double v = Yb[(int64_t)j * l + r];
+      Wb[(int64_t)j * l + r] = v;
+      if (!isfinite(v)) bad = 1;
+      acc += v * v;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      nu[j] = acc;
+      used[j] = 0;
+    }
+  }
+  const int any_bad = __syncthreads_or(bad);
+
+  // ||Y||_F^2 and the largest initial column norm
+  double fs = 0.0, fm = 0.0;
+  for (int j = tid; j < n; j += kTallThreads) {
+    fs += nu[j];
+    fm = fmax(fm, nu[j]);
+  }
+  fs = wave_sum(fs);
+  fm = wave_max(fm);
+  if (lane == 0) red_v[wave] = fs;
+  __syncthreads();
+  double F2 = 0.0;
+  for (int v = 0; v < NWV; ++v) F2 += red_v[v];
+  __syncthreads();
+  if (lane == 0) red_v[wave] = fm;
+  __syncthreads();
+  double nu0max = 0.0;
+  for (int v = 0; v < NWV; ++v) nu0max = fmax(nu0max, red_v[v]);
+  __syncthreads();
+
+  int kcap = k_max;
+  if (kcap > l) kcap = l;
+  if (kcap > n) kcap = n;
+  int status = 0, taken = 0;
+  if (any_bad) {
+    status = 2;
+  } else {
+    for (int s = 0; s < kcap; ++s) {
+      double bv = -1.0;
+      int bj = 0x7fffffff;
+      for (int j = tid; j < n; j += kTallThreads)
+        if (!used[j] && nu[j] > bv) {   // ascending j: ties keep the lowest index
+          bv = nu[j];
+          bj = j;
+        }
+      wave_argmax(bv, bj);
+      if (lane == 0) {
+        red_v[wave] = bv;
+        red_i[wave] = bj;
+      }
+      __syncthreads();
+      double best = red_v[0];
+      int p = red_i[0];
+      for (int x = 1; x < NWV; ++x)
+        if (red_v[x] > best || (red_v[x] == best && red_i[x] < p)) {
+          best = red_v[x];
+          p = red_i[x];
+        }
+      __syncthreads();
+      if (!(best > 0.0)) {
+        status = 1;
+        break;
+      }
+      if (rank_floor > 0.0 && best <= rank_floor * rank_floor * nu0max) {
+        status = 1;
+        break;
+      }
+      if (wave == 0) {
+        double pn = 0.0;
+        for (int r = lane; r < l; r += kWave) {
+          const double v = Wb[(int64_t)p * l + r];
+          pn += v * v;
+        }
+        const double rss = sqrt(wave_sum(pn));
+        for (int r = lane; r < l; r += kWave) Wb[(int64_t)p * l + r] /= rss;
+        if (lane == 0) {
+          Rb[(int64_t)s * n + p] = rss;
+          S_ws[(int64_t)b * k_max + s] = p;
+          used[p] = 1;
+          nu[p] = 0.0;
+        }
+      }
+      __syncthreads();
+      taken = s + 1;
+      const double* __restrict__ q = Wb + (int64_t)p * l;
+      for (int j = wave; j < n; j += NWV) {
+        if (used[j]) continue;   // uniform over the wave
+        double d = 0.0;
+        for (int r = lane; r < l; r += kWave) d += q[r] * Wb[(int64_t)j * l + r];
+        d = wave_sum(d);
+        double a2 = 0.0;
+        for (int r = lane; r < l; r += kWave) {
+          const double v = Wb[(int64_t)j * l + r] - d * q[r];
+          Wb[(int64_t)j * l + r] = v;
+          a2 += v * v;
+        }
+        a2 = wave_sum(a2);
+        if (lane == 0) {
+          Rb[(int64_t)s * n + j] = d;
+          nu[j] = a2;
+        }
+      }
+      __syncthreads();
+      if (tol > 0.0) {
+        double rest = 0.0;
+        for (int j = tid; j < n; j += kTallThreads)
+          if (!used[j]) rest += nu[j];
+        rest = wave_sum(rest);
+        if (lane == 0) red_v[wave] = rest;
+        __syncthreads();
+        double tot = 0.0;
+        for (int v = 0; v < NWV; ++v) tot += red_v[v];
+        __syncthreads();
+        if (sqrt(tot) <= tol * sqrt(F2)) break;
+        if (s == kcap - 1) status = 3;
+      }
+    }
+  }
+  if (tid == 0) {
+    k_ws[b] = taken;
+    st_ws[b] = status;
+  }
+  for (int s = taken + tid; s < k_max; s += kTallThreads) S_ws[(int64_t)b * k_max + s] = -1;
+}
+
+// ---------------------------------------------------------------------------
+// Single-pass error (equation (single_ID), Algorithm 3): for the fine rows of
+// one work item (kIpRows consecutive rows, one per thread),
+//   K(i,:) = M(i,:) B(:,S)   (8-point trilinear stencil on the coarse sketch)
+// is formed once in registers, then every column j gives
+//   r = A(i,j) - K(i,:) P(:,j),  err2 += r^2,  nrm2 += A(i,j)^2,
+// with P staged in LDS kIpCols columns at a time.  FP64 throughout; A is
+// read once, coalesced along the rows.  Partial sums per item, reduced per
+// block in a fixed order afterwards.
+// ---------------------------------------------------------------------------
+constexpr int kIpRows = 256;
+constexpr int kIpCols = 32;
+
+template <typename TA, int KMAX>
+__global__ __launch_bounds__(kIpRows) void interp_error_kernel(
+    const BlkInfo* __restrict__ blks, const GridInfo* __restrict__ grids,
+    const RcItem* __restrict__ items, int l, int k_max, const int32_t* __restrict__ S_ws,
+    const int32_t* __restrict__ k_ws, const double* __restrict__ Y,
+    const double* __restrict__ P, double* __restrict__ part) {
+  __shared__ double pc[kIpCols][KMAX];
+  __shared__ double red[2 * (kIpRows / kWave)];
+  const RcItem it = items[blockIdx.x];
+  const BlkInfo bi = blks[it.blk];
+  const GridInfo g = grids[it.blk];
+  const int k = k_ws[it.blk];
+  const int32_t* __restrict__ S = S_ws + (int64_t)it.blk * k_max;
+  const double* __restrict__ Yb = Y + bi.y_off;
+  const double* __restrict__ Pb = P + bi.p_off;
+  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i = it.i0 + tid;
+  const bool row = i < bi.m;
+
+  double kr[KMAX];
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t) kr[t] = 0.0;
+  if (row) {
+    const int64_t pts = (int64_t)g.nx * g.ny * g.nz;
+    const int f = (int)(i / pts);
+    const int64_t pp = i - f * pts;
+    const int x = (int)(pp % g.nx);
+    const int y = (int)((pp / g.nx) % g.ny);
+    const int z = (int)(pp / ((int64_t)g.nx * g.ny));
+    int tx0, tx1, ty0, ty1, tz0, tz1;
+    double wx0, wx1, wy0, wy1, wz0, wz1;
+    lin_weights(x, g.sx, g.cx, tx0, tx1, wx0, wx1);
+    lin_weights(y, g.sy, g.cy, ty0, ty1, wy0, wy1);
+    lin_weights(z, g.sz, g.cz, tz0, tz1, wz0, wz1);
+    const int fb = f * g.cx * g.cy * g.cz;
+    int idx[8];
+    double w[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int a = c >> 2, bb = (c >> 1) & 1, d = c & 1;
+      idx[c] = fb + (d ? tx1 : tx0) + g.cx * ((bb ? ty1 : ty0) + g.cy * (a ? tz1 : tz0));
+      w[c] = (a ? wz1 : wz0) * (bb ? wy1 : wy0) * (d ? wx1 : wx0);
+    }
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t) {
+      if (t < k) {
+        const double* __restrict__ col = Yb + (int64_t)S[t] * l;
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v += w[c] * col[idx[c]];
+        kr[t] = v;
+      }
+    }
+  }
+
+  double e2 = 0.0, a2 = 0.0;
+  const int n = bi.n;
+  for (int j0 = 0; j0 < n; j0 += kIpCols) {
+    const int jc = min(kIpCols, n - j0);
+    __syncthreads();
+    for (int e = tid; e < kIpCols * KMAX; e += kIpRows) {
+      const int q = e / KMAX, t = e - q * KMAX;
+      pc[q][t] = (q < jc && t < k) ? Pb[(int64_t)(j0 + q) * k_max + t] : 0.0;
+    }
+    __syncthreads();
+    if (row) {
+      for (int q = 0; q < jc; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t) acc += kr[t] * pc[q][t];
+        const double a = (double)A[(int64_t)(j0 + q) * bi.lda + i];
+        const double r = a - acc;
+        e2 += r * r;
+        a2 += a * a;
+      }
+    }
+  }
+  e2 = wave_sum(e2);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    red[wave] = e2;
+    red[kIpRows / kWave + wave] = a2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double se = 0.0, sa = 0.0;
+    for (int v = 0; v < kIpRows / kWave; ++v) {
+      se += red[v];
+      sa += red[kIpRows / kWave + v];
+    }
+    part[2 * (int64_t)blockIdx.x] = se;
+    part[2 * (int64_t)blockIdx.x + 1] = sa;
+  }
+}
+
+// Coarse skeleton B_b(:, S_b) (what Algorithm 3 stores): mc_b x k_max
+// column-major in the A dtype at grids[b].cs_off; columns >= k_b untouched.
+template <typename TA>
+__global__ __launch_bounds__(256) void coarse_skeleton_kernel(
+    const BlkInfo* __restrict__ blks, const GridInfo* __restrict__ grids, int nblocks, int l,
+    int k_max, const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
+    const double* __restrict__ Y, TA* __restrict__ out) {
+  for (int b = blockIdx.y; b < nblocks; b += gridDim.y) {
+    const int k = k_ws[b];
+    const int mc = grids[b].mc;
+    const int64_t cs = grids[b].cs_off;
+    const int64_t y_off = blks[b].y_off;
+    const int64_t total = (int64_t)mc * k;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+      const int t = (int)(e / mc);
+      const int r = (int)(e - (int64_t)t * mc);
+      out[cs + (int64_t)t * mc + r] =
+          (TA)Y[y_off + (int64_t)S_ws[(int64_t)b * k_max + t] * l + r];
+    }
+  }
+}
+
+}  // namespace spid

@@ -23,6 +23,12 @@ class GpuResult:
     err2: np.ndarray
     nrm2: np.ndarray
     skel: list | None = None
+    ierr2: np.ndarray | None = None      # single-pass (interpolated) error, coarse grids
+    cskel: list | None = None            # coarse skeleton B(:,S), coarse grids
+
+    @property
+    def rel_interp_error(self):
+        return float(math.sqrt(self.ierr2.sum() / self.nrm2.sum()))
 
     @property
     def rel_error(self):
@@ -30,8 +36,10 @@ class GpuResult:
 
 
 def gpu_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=False,
-            prec="f64", lp_terms=1, skeleton=False, stream_columns=False, lda_pad=0):
-    """Run the four stages on the GPU for host column-major blocks."""
+            prec="f64", lp_terms=1, skeleton=False, stream_columns=False, lda_pad=0,
+            grids=None):
+    """Run the four stages on the GPU for host column-major blocks.  ``grids``: the
+    coarse-grid sketch (SubID) plus the single-pass error and coarse skeleton."""
     import paper_2103_01380_amd as sp
     dt = blocks[0].dtype
     a_dtype = "f64" if dt == np.float64 else "f32"
@@ -47,9 +55,12 @@ def gpu_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=Fal
         v[:, :m[b]] = blk.T
         flat[off[b]:off[b] + sizes[b]] = v.ravel()
     A = torch.from_numpy(flat).cuda()
+    if grids is not None:
+        prec = "subsample"
     ctx = sp.SPID(m, n, l, k_max, tol=tol, rank_floor=rank_floor, seed=seed,
                   omega_per_block=omega_per_block, a_dtype=a_dtype, prec=prec,
-                  lp_terms=lp_terms)
+                  lp_terms=lp_terms, grids=grids)
+    l = ctx.l
     ctx.bind(A, offsets=off, lda=lda)
     if stream_columns:
         for j in range(int(n.max())):
@@ -62,6 +73,11 @@ def gpu_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=Fal
     if skeleton:
         skel_t = torch.full((int((m * k_max).sum()),), float("nan"), dtype=A.dtype, device=A.device)
     ctx.reconstruct(skeleton=skel_t)
+    cs_t = None
+    if grids is not None:
+        mc = ctx.mc
+        cs_t = torch.full((int((mc * k_max).sum()),), float("nan"), dtype=A.dtype, device=A.device)
+        ctx.reconstruct_interp(coarse_skeleton=cs_t)
     torch.cuda.synchronize()
     Yf = ctx.sketch().cpu().numpy()
     Ys = [Yf[ctx.y_off[b]:ctx.y_off[b] + l * n[b]].reshape(n[b], l).T for b in range(len(blocks))]
@@ -72,17 +88,25 @@ def gpu_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=Fal
         so = np.zeros(len(blocks), dtype=np.int64)
         so[1:] = np.cumsum((m * k_max)[:-1])
         skel = [sk[so[b]:so[b] + m[b] * k_max].reshape(k_max, m[b]).T for b in range(len(blocks))]
+    ierr2 = cskel = None
+    if grids is not None:
+        ierr2 = ctx.err2_interp.cpu().numpy()
+        cs = cs_t.cpu().numpy()
+        co = np.zeros(len(blocks), dtype=np.int64)
+        co[1:] = np.cumsum((ctx.mc * k_max)[:-1])
+        cskel = [cs[co[b]:co[b] + ctx.mc[b] * k_max].reshape(k_max, ctx.mc[b]).T
+                 for b in range(len(blocks))]
     res = GpuResult(Ys, ctx.S.cpu().numpy(), ctx.k.cpu().numpy(), ctx.status.cpu().numpy(), Ps,
-                    ctx.err2.cpu().numpy(), ctx.nrm2.cpu().numpy(), skel)
+                    ctx.err2.cpu().numpy(), ctx.nrm2.cpu().numpy(), skel, ierr2, cskel)
     ctx.close()
     return res
 
 
 def oracle_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=False,
-               prec="f64", block_ids=None):
+               prec="f64", block_ids=None, grids=None):
     return oracle.run_batch(blocks, l=l, k_max=k_max, seed=seed, tol=tol, rank_floor=rank_floor,
                             omega_per_block=omega_per_block, prec=PREC_OMEGA[prec],
-                            block_ids=block_ids)
+                            block_ids=block_ids, grids=grids)
 
 
 def matched_prefix(S_gpu, S_ora, gaps, k_gpu, k_ora, gamma):

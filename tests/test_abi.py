@@ -149,3 +149,26 @@ def test_autotune_signature_separates_batches():
     s2 = at.signature([100, 201], [10, 20], 18, 8, 0.0, "f64", "f64", 1)
     s3 = at.signature([100, 200], [10, 20], 18, 8, 0.0, "f64", "f64", 1, stream_columns=True)
     assert len({s1, s2, s3}) == 3
+
+
+def test_coarse_grid_descriptor_validation():
+    import paper_2103_01380_amd as sp
+    g = np.array([[16, 16, 16, 3, 7, 7, 7]], dtype=np.int32)
+    ok = sp.make_desc([12288], [64], 81, 8, prec=sp.SK_SUBSAMPLE, grids=g)
+    assert sp.spid_workspace_bytes(ok) > 0
+    short = sp.make_desc([12288], [64], 80, 8, prec=sp.SK_SUBSAMPLE, grids=g)
+    assert sp.spid_workspace_bytes(short) == 0 and "coarse rows" in sp.spid_last_error()
+    wrong_m = sp.make_desc([12000], [64], 81, 8, prec=sp.SK_SUBSAMPLE, grids=g)
+    assert sp.spid_workspace_bytes(wrong_m) == 0 and "grid has" in sp.spid_last_error()
+    no_grid = sp.make_desc([12288], [64], 81, 8, prec=sp.SK_SUBSAMPLE)
+    assert sp.spid_workspace_bytes(no_grid) == 0 and "h_grid" in sp.spid_last_error()
+    bad = sp.make_desc([12288], [64], 81, 8, prec=sp.SK_SUBSAMPLE,
+                       grids=np.array([[16, 16, 16, 3, 0, 7, 7]], dtype=np.int32))
+    assert sp.spid_workspace_bytes(bad) == 0 and ">= 1" in sp.spid_last_error()
+    # tall coarse grids: allowed beyond the 128 rows of the Gaussian sketch, and the
+    # global-memory selection needs a working copy of the sketch
+    tall = sp.make_desc([12288], [64], 648, 8, prec=sp.SK_SUBSAMPLE,
+                        grids=np.array([[16, 16, 16, 3, 3, 3, 3]], dtype=np.int32))
+    assert sp.spid_workspace_bytes(tall) >= 2 * 648 * 64 * 8
+    gauss = sp.make_desc([12288], [64], 648, 8)
+    assert sp.spid_workspace_bytes(gauss) == 0
