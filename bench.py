@@ -24,7 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+PEAK_TFLOPS = {"f64": 78.6, "f64_vector": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 
 
 def parse():
@@ -77,7 +77,8 @@ def main():
     nbytes = int((m * n.astype(np.int64)).sum()) * w.elem_bytes
     stream = torch.cuda.current_stream()
     tuning = None
-    if not args.no_autotune:
+    coarse = w.subsample > 0
+    if not args.no_autotune and not coarse:
         from paper_2103_01380_amd import autotune as at
         t0 = time.time()
         tuning = at.autotune(A, m, n, w.l, w.k_max, offsets=off, tol=w.tol, seed=w.omega_seed,
@@ -86,7 +87,8 @@ def main():
                              log=(lambda s: log(args, s)))
         log(args, f"launch shapes {tuning} ({time.time() - t0:.1f}s)")
     ctx = sp.SPID(m, n, w.l, w.k_max, tol=w.tol, seed=w.omega_seed,
-                  a_dtype=w.a_dtype, prec=w.prec, lp_terms=w.lp_terms, device=dev, tuning=tuning)
+                  a_dtype=w.a_dtype, prec=w.prec, lp_terms=w.lp_terms, device=dev, tuning=tuning,
+                  grids=w.grids() if coarse else None)
     ctx.bind(A, offsets=off)
     ms_step, stage, wall = time_steps(args, ctx, w, stream)
     graph_ms = None
@@ -108,13 +110,19 @@ def main():
         graph_ms = (time.perf_counter() - t0g) * 1e3 / args.steps
         log(args, f"graph replay: {graph_ms:.3f} ms per step")
     value = nbytes / (ms_step * 1e-3) / 1e9
-    rel_err = ctx.rel_error()
     kk = ctx.k.cpu().numpy()
-    cf = float((m * n.astype(np.int64)).sum() / max(1, (kk * (m + n)).sum()))
+    if coarse:
+        # single-pass ID: the error of M B(:,S) C, the stored skeleton has m_c rows
+        rel_err = float((ctx.err2_interp.sum() / ctx.nrm2.sum()).sqrt())
+        ms_rows = ctx.mc
+    else:
+        rel_err = ctx.rel_error()
+        ms_rows = m
+    cf = float((m * n.astype(np.int64)).sum() / max(1, (kk * (ms_rows + n)).sum()))
     log(args, f"stage ms: sketch {stage[0]:.3f} select {stage[1]:.3f} coeffs {stage[2]:.3f} "
               f"recon {stage[3]:.3f}; step {ms_step:.3f} ms; rel err {rel_err:.3e}")
 
-    work = stage_work(w, m, n, kk, nbytes)
+    work = stage_work(w, m, n, kk, nbytes, ctx)
     roof = dominant_roofline(w, stage, work)
     step_roof = step_roofline(w, stage, work, ms_step)
 
@@ -124,7 +132,7 @@ def main():
         cpu, agree = cpu_baseline(args, w, A, m, n, off, ctx)
 
     fp64 = None
-    if w.prec != "f64" and not args.no_fp64_compare:
+    if w.prec not in ("f64", "subsample") and not args.no_fp64_compare:
         # the plain FP64 method on the same resident data: FP64 sketch and FP64 error pass
         ctx64 = sp.SPID(m, n, w.l, w.k_max, tol=w.tol, seed=w.omega_seed, a_dtype=w.a_dtype,
                         prec="f64", device=dev)
@@ -148,12 +156,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if w.prec == "f64" else f"{w.prec}-sketch/f64",
+        "dtype": "f64" if w.prec in ("f64", "subsample") else f"{w.prec}-sketch/f64",
         "data": "synthetic",
         "config": {"workload": w.name, "description": w.description,
                    "nblocks": int(len(m)), "bytes": nbytes, "l": w.l, "k_max": w.k_max,
                    "tol": w.tol, "sketch_update": "one snapshot per call" if w.stream
-                   else "all snapshots in one call"},
+                   else "all snapshots in one call",
+                   "sketch": (f"coarse grid, every {w.subsample}th point; error of M B(:,S) C"
+                              if coarse else "Gaussian, " + w.prec)},
         "rel_error": rel_err,
         "error_gate_1e-3": bool(rel_err <= 1e-3),
         "compression_factor": round(cf, 3),
@@ -198,7 +208,10 @@ def time_steps(args, ctx, w, stream):
         ctx.coeffs(stream)
         if ev is not None:
             ev[3].record(stream)
-        ctx.reconstruct(stream=stream)
+        if w.subsample:
+            ctx.reconstruct_interp(stream=stream)
+        else:
+            ctx.reconstruct(stream=stream)
         if ev is not None:
             ev[4].record(stream)
 
@@ -220,10 +233,25 @@ def time_steps(args, ctx, w, stream):
     return wall * 1e3 / args.steps, stage, wall
 
 
-def stage_work(w, m, n, kk, nbytes):
+def stage_work(w, m, n, kk, nbytes, ctx=None):
     """Algorithmic (bytes, flops, flop peak) per stage: what the method must do."""
     n64 = n.astype(np.int64)
     k64 = kk.astype(np.int64)
+    if w.subsample:
+        # coarse grid: the sketch gathers m_c rows and writes the l-row sketch; the
+        # error pass reads A once, 2k flops per entry plus the 8-point stencil of each
+        # skeleton entry (FP64 vector arithmetic)
+        mc = ctx.mc.astype(np.int64)
+        sk_bytes = int((mc * n64).sum()) * w.elem_bytes + 8 * w.l * int(n64.sum())
+        sel_flops = float((4.0 * w.l * k64 * (n64 - (k64 - 1) / 2.0)).sum())
+        co_flops = float((k64 * k64 * (n64 - k64)).sum())
+        ip_flops = 2.0 * float((m * n64 * k64).sum()) + 16.0 * float((m * k64).sum())
+        return {
+            "sketch": (sk_bytes, 0.0, PEAK_TFLOPS["f64_vector"]),
+            "select": (0, sel_flops, PEAK_TFLOPS["f64_vector"]),
+            "coeffs": (0, co_flops, PEAK_TFLOPS["f64_vector"]),
+            "reconstruct": (nbytes, ip_flops, PEAK_TFLOPS["f64_vector"]),
+        }
     sk_flops = 2.0 * w.l * float((m * n64).sum())
     sel_flops = float((4.0 * w.l * k64 * (n64 - (k64 - 1) / 2.0)).sum())
     co_flops = float((k64 * k64 * (n64 - k64)).sum())
@@ -248,8 +276,8 @@ def dominant_roofline(w, stage, work):
     gbs = b_alg / t_s / 1e9
     tfl = f_alg / t_s / 1e12
     if tfl / peak_t > gbs / PEAK_HBM_GBS:
-        roof = {"bound": "mfma", "achieved": round(tfl, 3), "peak": peak_t, "unit": "TFLOP/s",
-                "frac": round(tfl / peak_t, 4)}
+        roof = {"bound": "alu" if w.subsample else "mfma", "achieved": round(tfl, 3),
+                "peak": peak_t, "unit": "TFLOP/s", "frac": round(tfl / peak_t, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs / PEAK_HBM_GBS, 4)}
@@ -305,7 +333,7 @@ def oracle_agreement(w, A, m, n, off, ctx, idx, res):
     relative errors of both, the A-space difference of the two reconstructions
     (R2) and how many blocks select the oracle's columns over the decidable prefix."""
     import torch
-    gamma = {"f64": 1e-10, "bf16": 1e-3, "fp8": 1e-2}[w.prec]
+    gamma = {"f64": 1e-10, "subsample": 1e-10, "bf16": 1e-3, "fp8": 1e-2}[w.prec]
     S = ctx.S.cpu().numpy()
     k = ctx.k.cpu().numpy()
     e2g = ctx.err2.cpu().numpy()
@@ -331,7 +359,12 @@ def oracle_agreement(w, A, m, n, off, ctx, idx, res):
             match += 1
         if s_star == ko and kg == ko and np.array_equal(S[b][:kg], res.S[r][:ko]):
             full += 1
-    return {"blocks": int(len(idx)),
+    extra = {}
+    if w.subsample:
+        i2g = ctx.err2_interp.cpu().numpy()
+        extra = {"gpu_rel_interp_error": float(np.sqrt(i2g[idx].sum() / n2g[idx].sum())),
+                 "oracle_rel_interp_error": res.rel_interp_error}
+    return {"blocks": int(len(idx)), **extra,
             "gpu_rel_error": float(np.sqrt(e2g[idx].sum() / n2g[idx].sum())),
             "oracle_rel_error": res.rel_error,
             "R2": float(np.sqrt(num / den)) if den > 0 else 0.0,
@@ -351,13 +384,16 @@ def cpu_baseline(args, w, A, m, n, off, ctx):
     threads = len(os.sched_getaffinity(0))
     rng = np.random.default_rng(0)
     order = rng.permutation(nb)
-    prec = {"f64": oracle.OMEGA_F64, "bf16": oracle.OMEGA_BF16, "fp8": oracle.OMEGA_FP8E4M3}
+    prec = {"f64": oracle.OMEGA_F64, "bf16": oracle.OMEGA_BF16, "fp8": oracle.OMEGA_FP8E4M3,
+            "subsample": oracle.OMEGA_F64}
+    grids = w.grids() if w.subsample else None
 
     def run(idx):
         blocks = [si.block_view(A, m, n, off, int(b)) for b in idx]
         t0 = time.perf_counter()
         res = oracle.run_batch(blocks, l=w.l, k_max=w.k_max, seed=w.omega_seed, tol=w.tol,
-                               prec=prec[w.prec], nthreads=threads)
+                               prec=prec[w.prec], nthreads=threads,
+                               grids=None if grids is None else grids[idx])
         dt = time.perf_counter() - t0
         return dt, int(sum(b.shape[0] * b.shape[1] for b in blocks)) * w.elem_bytes, res
 
@@ -376,7 +412,8 @@ def cpu_baseline(args, w, A, m, n, off, ctx):
             "kind": "oracle",
             "sample": f"{len(idx)} of {nb} blocks (seeded choice), whole method per block "
                       f"(sketch, select, coefficients, error), {dt:.1f} s wall on {threads} "
-                      f"threads"}, agree
+                      f"threads" + ("; the oracle also forms the SubID error (a second pass "
+                                    "over A)" if w.subsample else "")}, agree
 
 
 if __name__ == "__main__":

@@ -106,17 +106,15 @@ struct Plan {
   std::vector<int32_t> sheads;
   std::vector<int32_t> ritems;   // FP8 resident-Omega items: (first stream item, count, stride)
   int64_t st_part_elems = 0;
-  // coarse-grid sketch: grids, interpolation-error items (kIpRows rows each)
+  // coarse-grid sketch: block grids (the single-pass error uses the error-pass items)
   bool coarse = false;
   std::vector<GridInfo> grid;
-  std::vector<RcItem> ip;
-  std::vector<int64_t> ip_first;
   int64_t sum_mc = 0;
   int64_t sum_n = 0, sum_m = 0, part_elems = 0;
   int max_n = 0, max_split_n = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
       off_st, off_rcpart, off_perm, off_sitems, off_sheads, off_ritems, off_pt, off_cols, off_ncols,
-      off_grid, off_W, off_ip, off_ipfirst, off_ippart, total;
+      off_grid, off_W, total;
 };
 
 spid_status validate(const spid_desc* d) {
@@ -385,16 +383,7 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
       cs_off += (int64_t)gi.mc * d->k_max;
       p.sum_mc += gi.mc;
       p.grid[b] = gi;
-      p.ip_first.push_back((int64_t)p.ip.size());
-      for (int64_t i0 = 0; i0 < d->h_m[b]; i0 += kIpRows) {
-        RcItem r{};
-        r.blk = b;
-        r.i0 = i0;
-        r.nsub = 1;
-        p.ip.push_back(r);
-      }
     }
-    p.ip_first.push_back((int64_t)p.ip.size());
   }
 
   // one-snapshot (stream) plan: needs Omega shared by all blocks
@@ -505,9 +494,6 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_ncols = take(sizeof(int32_t) * nb);
   p.off_grid = take(sizeof(GridInfo) * std::max<size_t>(1, p.grid.size()));
   p.off_W = take(sh.sel_tall ? sizeof(double) * (size_t)d->l * p.sum_n : 256);
-  p.off_ip = take(sizeof(RcItem) * std::max<size_t>(1, p.ip.size()));
-  p.off_ipfirst = take(sizeof(int64_t) * std::max<size_t>(1, p.ip_first.size()));
-  p.off_ippart = take(sizeof(double) * 2 * std::max<size_t>(1, p.ip.size()));
   p.total = off;
   return SPID_OK;
 }
@@ -885,12 +871,7 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
   if (e == hipSuccess && p.coarse)
     e = hipMemcpy(c->ws + p.off_grid, p.grid.data(), sizeof(GridInfo) * p.grid.size(),
                   hipMemcpyHostToDevice);
-  if (e == hipSuccess && p.coarse)
-    e = hipMemcpy(c->ws + p.off_ip, p.ip.data(), sizeof(RcItem) * p.ip.size(),
-                  hipMemcpyHostToDevice);
-  if (e == hipSuccess && p.coarse)
-    e = hipMemcpy(c->ws + p.off_ipfirst, p.ip_first.data(), sizeof(int64_t) * p.ip_first.size(),
-                  hipMemcpyHostToDevice);
+
   if (e != hipSuccess) {
     delete c;
     return fail(SPID_EHIP, "spid_create: %s", hipGetErrorString(e));
@@ -1024,14 +1005,21 @@ extern "C" spid_status spid_select(spid_ctx* c, int32_t* d_k, int32_t* d_S, int3
     if (!c->covered[j])
       return fail(SPID_ESTATE, "spid_select: sketch column %d has not been computed", j);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (c->plan.sh.sel_tall)
-    hipLaunchKernelGGL(select_tall_kernel, dim3(c->desc.nblocks), dim3(kTallThreads), 0, s,
-                       c->at<BlkInfo>(c->plan.off_blk), c->desc.l, c->desc.k_max, c->desc.tol,
-                       c->desc.rank_floor, c->at<double>(c->plan.off_Y),
-                       c->at<double>(c->plan.off_W), c->at<double>(c->plan.off_R),
-                       c->at<int32_t>(c->plan.off_S), c->at<int32_t>(c->plan.off_k),
-                       c->at<int32_t>(c->plan.off_st));
-  else if (c->plan.ydt == 0)
+  if (c->plan.sh.sel_tall) {
+    auto launch = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(c->desc.nblocks), dim3(kTallThreads), 0, s,
+                         c->at<BlkInfo>(c->plan.off_blk), c->desc.l, c->desc.k_max, c->desc.tol,
+                         c->desc.rank_floor, c->at<double>(c->plan.off_Y),
+                         c->at<double>(c->plan.off_W), c->at<double>(c->plan.off_R),
+                         c->at<int32_t>(c->plan.off_S), c->at<int32_t>(c->plan.off_k),
+                         c->at<int32_t>(c->plan.off_st));
+    };
+    const int l = c->desc.l;
+    if (l <= 4 * kWave) launch(select_tall_kernel<4>);
+    else if (l <= 8 * kWave) launch(select_tall_kernel<8>);
+    else if (l <= 16 * kWave) launch(select_tall_kernel<16>);
+    else launch(select_tall_kernel<0>);
+  } else if (c->plan.ydt == 0)
     launch_select_y<double>(c, s);
   else
     launch_select_y<float>(c, s);
@@ -1090,26 +1078,36 @@ extern "C" spid_status spid_reconstruct(spid_ctx* c, const double* d_P, double* 
 
 namespace {
 
-template <typename TA, int KMAX>
-void launch_interp_t(spid_ctx* c, const double* P, hipStream_t s) {
+template <typename TA, int KS, int MTR>
+bool launch_interp_t(spid_ctx* c, const double* P, hipStream_t s) {
   const Plan& p = c->plan;
-  hipLaunchKernelGGL((interp_error_kernel<TA, KMAX>), dim3((unsigned)p.ip.size()), dim3(kIpRows),
-                     0, s, c->at<BlkInfo>(p.off_blk), c->at<GridInfo>(p.off_grid),
-                     c->at<RcItem>(p.off_ip), c->desc.l, c->desc.k_max, c->at<int32_t>(p.off_S),
-                     c->at<int32_t>(p.off_k), c->at<double>(p.off_Y), P,
-                     c->at<double>(p.off_ippart));
+  const size_t lds = sizeof(double) * p.sh.PCAP * 4 * KS;
+  auto launch = [&](auto kern) {
+    if (!allow_lds((const void*)kern, lds)) return false;
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), lds, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<GridInfo>(p.off_grid),
+                       c->at<RcItem>(p.off_rc), c->desc.l, c->desc.k_max, p.sh.PCAP,
+                       c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
+                       c->at<double>(p.off_Y), P, c->at<double>(p.off_rcpart));
+    return true;
+  };
+  if (c->all_vec4) return launch(interp_mfma_kernel<TA, KS, MTR, true>);
+  return launch(interp_mfma_kernel<TA, KS, MTR, false>);
 }
 
 template <typename TA>
-void launch_interp_a(spid_ctx* c, const double* P, void* cskel, hipStream_t s) {
-  switch (c->plan.sh.KMAX) {
-    case 8: launch_interp_t<TA, 8>(c, P, s); break;
-    case 16: launch_interp_t<TA, 16>(c, P, s); break;
-    case 32: launch_interp_t<TA, 32>(c, P, s); break;
-    case 48: launch_interp_t<TA, 48>(c, P, s); break;
-    case 64: launch_interp_t<TA, 64>(c, P, s); break;
-    default: launch_interp_t<TA, 96>(c, P, s); break;
+bool launch_interp_a(spid_ctx* c, const double* P, void* cskel, hipStream_t s) {
+  bool ok;
+  switch (c->plan.sh.KS) {
+    case 1: ok = launch_interp_t<TA, 1, 4>(c, P, s); break;
+    case 2: ok = launch_interp_t<TA, 2, 4>(c, P, s); break;
+    case 4: ok = launch_interp_t<TA, 4, 4>(c, P, s); break;
+    case 8: ok = launch_interp_t<TA, 8, 4>(c, P, s); break;
+    case 12: ok = launch_interp_t<TA, 12, 2>(c, P, s); break;
+    case 16: ok = launch_interp_t<TA, 16, 2>(c, P, s); break;
+    default: ok = launch_interp_t<TA, 24, 2>(c, P, s); break;
   }
+  if (!ok) return false;
   if (cskel) {
     const Plan& p = c->plan;
     int mcmax = 1;
@@ -1122,6 +1120,7 @@ void launch_interp_a(spid_ctx* c, const double* P, void* cskel, hipStream_t s) {
                        c->desc.l, c->desc.k_max, c->at<int32_t>(p.off_S),
                        c->at<int32_t>(p.off_k), c->at<double>(p.off_Y), static_cast<TA*>(cskel));
   }
+  return true;
 }
 
 }  // namespace
@@ -1137,14 +1136,14 @@ extern "C" spid_status spid_reconstruct_interp(spid_ctx* c, const double* d_P, d
   if (!c->coeffs_done) return fail(SPID_ESTATE, "spid_reconstruct_interp before spid_coeffs");
   const Plan& p = c->plan;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (c->desc.a_dtype == SPID_A_F64)
-    launch_interp_a<double>(c, d_P, d_coarse_skeleton, s);
-  else
-    launch_interp_a<float>(c, d_P, d_coarse_skeleton, s);
+  const bool ok = c->desc.a_dtype == SPID_A_F64
+                      ? launch_interp_a<double>(c, d_P, d_coarse_skeleton, s)
+                      : launch_interp_a<float>(c, d_P, d_coarse_skeleton, s);
+  if (!ok) return fail(SPID_EHIP, "reconstruct_interp: cannot reserve the coefficient LDS");
   spid_status st = hip_check("interpolated error kernel launch");
   if (st != SPID_OK) return st;
   hipLaunchKernelGGL(recon_reduce_kernel, dim3((c->desc.nblocks + 255) / 256), dim3(256), 0, s,
-                     c->desc.nblocks, c->at<int64_t>(p.off_ipfirst), c->at<double>(p.off_ippart),
+                     c->desc.nblocks, c->at<int64_t>(p.off_rcfirst), c->at<double>(p.off_rcpart),
                      d_err2, d_nrm2);
   return hip_check("interpolated error reduce launch");
 }

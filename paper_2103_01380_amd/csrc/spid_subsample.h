@@ -93,16 +93,22 @@ __global__ __launch_bounds__(256) void subsample_kernel(const BlkInfo* __restric
 // Column selection of tall sketches (Section 2, Algorithm 1 mgsqr on B; the
 // coarse grid can have far more rows than registers and LDS hold): the
 // working copy W of the block's sketch lives in global memory (L2-resident
-// for the block being processed), one workgroup of four waves per block,
-// one wave per column with the rows over the lanes (coalesced), so every
-// dot product and norm is a wave reduction.  Same steps, stopping rules and
+// for the block being processed), one workgroup per block, one wave per
+// column with the rows over the lanes (coalesced), so every
+// dot product and norm is a wave reduction (16 waves per workgroup, four
+// row loads per lane in flight).  Same steps, stopping rules and
 // outputs as the register kernels: pivot = largest residual norm (ties to
 // the lowest index), q = W(:,p)/||W(:,p)|| (stored over W(:,p)), one
 // Gram-Schmidt sweep, norms recomputed.
 // ---------------------------------------------------------------------------
-constexpr int kTallThreads = 256;
+constexpr int kTallThreads = 1024;
+constexpr int kTallUnroll = 4;   // independent row loads per lane in flight
 constexpr int kTallMaxN = 1024;
 
+// RPL > 0 (l <= 64 RPL): each wave keeps the pivot column q and the column
+// it updates in registers, so a column is read once and written once per
+// step; RPL = 0: any l, two streaming passes per column.
+template <int RPL>
 __global__ __launch_bounds__(kTallThreads) void select_tall_kernel(
     const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor,
     const double* __restrict__ Y, double* __restrict__ W, double* __restrict__ R,
@@ -123,11 +129,20 @@ __global__ __launch_bounds__(kTallThreads) void select_tall_kernel(
   int bad = 0;
   for (int j = wave; j < n; j += NWV) {
     double acc = 0.0;
-    for (int r = lane; r < l; r += kWave) {
-      const double v = Yb[(int64_t)j * l + r];
-      Wb[(int64_t)j * l + r] = v;
-      if (!isfinite(v)) bad = 1;
-      acc += v * v;
+    for (int r0 = lane; r0 < l; r0 += kTallUnroll * kWave) {
+      double v[kTallUnroll];
+#pragma unroll
+      for (int u = 0; u < kTallUnroll; ++u) {
+        const int r = r0 + u * kWave;
+        v[u] = r < l ? Yb[(int64_t)j * l + r] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kTallUnroll; ++u) {
+        const int r = r0 + u * kWave;
+        if (r < l) Wb[(int64_t)j * l + r] = v[u];
+        if (!isfinite(v[u])) bad = 1;
+        acc += v[u] * v[u];
+      }
     }
     acc = wave_sum(acc);
     if (lane == 0) {
@@ -195,9 +210,15 @@ __global__ __launch_bounds__(kTallThreads) void select_tall_kernel(
       }
       if (wave == 0) {
         double pn = 0.0;
-        for (int r = lane; r < l; r += kWave) {
-          const double v = Wb[(int64_t)p * l + r];
-          pn += v * v;
+        for (int r0 = lane; r0 < l; r0 += kTallUnroll * kWave) {
+          double v[kTallUnroll];
+#pragma unroll
+          for (int u = 0; u < kTallUnroll; ++u) {
+            const int r = r0 + u * kWave;
+            v[u] = r < l ? Wb[(int64_t)p * l + r] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kTallUnroll; ++u) pn += v[u] * v[u];
         }
         const double rss = sqrt(wave_sum(pn));
         for (int r = lane; r < l; r += kWave) Wb[(int64_t)p * l + r] /= rss;
@@ -211,22 +232,80 @@ __global__ __launch_bounds__(kTallThreads) void select_tall_kernel(
       __syncthreads();
       taken = s + 1;
       const double* __restrict__ q = Wb + (int64_t)p * l;
+      if constexpr (RPL > 0) {
+        double qr[RPL];
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          const int r = lane + u * kWave;
+          qr[u] = r < l ? q[r] : 0.0;
+        }
+        for (int j = wave; j < n; j += NWV) {
+          if (used[j]) continue;   // uniform over the wave
+          double* __restrict__ wj = Wb + (int64_t)j * l;
+          double wv[RPL];
+          double d = 0.0;
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) {
+            const int r = lane + u * kWave;
+            wv[u] = r < l ? wj[r] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) d += qr[u] * wv[u];
+          d = wave_sum(d);
+          double a2 = 0.0;
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) {
+            const int r = lane + u * kWave;
+            const double v = wv[u] - d * qr[u];
+            if (r < l) wj[r] = v;
+            a2 += v * v;
+          }
+          a2 = wave_sum(a2);
+          if (lane == 0) {
+            Rb[(int64_t)s * n + j] = d;
+            nu[j] = a2;
+          }
+        }
+      } else {
       for (int j = wave; j < n; j += NWV) {
         if (used[j]) continue;   // uniform over the wave
+        double* __restrict__ wj = Wb + (int64_t)j * l;
         double d = 0.0;
-        for (int r = lane; r < l; r += kWave) d += q[r] * Wb[(int64_t)j * l + r];
+        for (int r0 = lane; r0 < l; r0 += kTallUnroll * kWave) {
+          double qv[kTallUnroll], wv[kTallUnroll];
+#pragma unroll
+          for (int u = 0; u < kTallUnroll; ++u) {
+            const int r = r0 + u * kWave;
+            qv[u] = r < l ? q[r] : 0.0;
+            wv[u] = r < l ? wj[r] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kTallUnroll; ++u) d += qv[u] * wv[u];
+        }
         d = wave_sum(d);
         double a2 = 0.0;
-        for (int r = lane; r < l; r += kWave) {
-          const double v = Wb[(int64_t)j * l + r] - d * q[r];
-          Wb[(int64_t)j * l + r] = v;
-          a2 += v * v;
+        for (int r0 = lane; r0 < l; r0 += kTallUnroll * kWave) {
+          double qv[kTallUnroll], wv[kTallUnroll];
+#pragma unroll
+          for (int u = 0; u < kTallUnroll; ++u) {
+            const int r = r0 + u * kWave;
+            qv[u] = r < l ? q[r] : 0.0;
+            wv[u] = r < l ? wj[r] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kTallUnroll; ++u) {
+            const int r = r0 + u * kWave;
+            const double v = wv[u] - d * qv[u];
+            if (r < l) wj[r] = v;
+            a2 += v * v;
+          }
         }
         a2 = wave_sum(a2);
         if (lane == 0) {
           Rb[(int64_t)s * n + j] = d;
           nu[j] = a2;
         }
+      }
       }
       __syncthreads();
       if (tol > 0.0) {
@@ -252,111 +331,136 @@ __global__ __launch_bounds__(kTallThreads) void select_tall_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Single-pass error (equation (single_ID), Algorithm 3): for the fine rows of
-// one work item (kIpRows consecutive rows, one per thread),
-//   K(i,:) = M(i,:) B(:,S)   (8-point trilinear stencil on the coarse sketch)
-// is formed once in registers, then every column j gives
-//   r = A(i,j) - K(i,:) P(:,j),  err2 += r^2,  nrm2 += A(i,j)^2,
-// with P staged in LDS kIpCols columns at a time.  FP64 throughout; A is
-// read once, coalesced along the rows.  Partial sums per item, reduced per
-// block in a fixed order afterwards.
+// Single-pass error (equation (single_ID), Algorithm 3) on the FP64 matrix
+// cores: Ahat(rows, cols) = K(rows, :) P(:, cols) with the interpolated
+// skeleton K = M B(:,S) as the A operand of v_mfma_f64_16x16x4 (16 rows x 4
+// selected columns per k-step, each entry an 8-point trilinear stencil over
+// the coarse sketch, which stays in L2), P as the B operand, and the
+// residual A - Ahat accumulated per lane.  Same tiling as the error pass of
+// spid_reconstruct (row permutation inside a 16-row tile so that lane (g, c)
+// owns rows 4g..4g+3 of column c; work item = it.nsub sub-tiles of
+// 4 * 16 * MTR rows; coefficients staged in LDS pcap columns at a time) but
+// over every column: the interpolated skeleton does not reproduce A on the
+// selected columns.  Dynamic LDS: pcap * 4 * KS doubles.
 // ---------------------------------------------------------------------------
-constexpr int kIpRows = 256;
-constexpr int kIpCols = 32;
-
-template <typename TA, int KMAX>
-__global__ __launch_bounds__(kIpRows) void interp_error_kernel(
+template <typename TA, int KS, int MTR, bool VEC>
+__global__ __launch_bounds__(kRcThreads) void interp_mfma_kernel(
     const BlkInfo* __restrict__ blks, const GridInfo* __restrict__ grids,
-    const RcItem* __restrict__ items, int l, int k_max, const int32_t* __restrict__ S_ws,
-    const int32_t* __restrict__ k_ws, const double* __restrict__ Y,
-    const double* __restrict__ P, double* __restrict__ part) {
-  __shared__ double pc[kIpCols][KMAX];
-  __shared__ double red[2 * (kIpRows / kWave)];
+    const RcItem* __restrict__ items, int l, int k_max, int pcap,
+    const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
+    const double* __restrict__ Y, const double* __restrict__ P, double* __restrict__ part) {
+  extern __shared__ __attribute__((aligned(16))) double p_lds[];   // [pcap][kp]
+  __shared__ double red[8];
+  constexpr int kp = 4 * KS;
+  constexpr int kSub = 4 * 16 * MTR;
   const RcItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
-  const GridInfo g = grids[it.blk];
+  const GridInfo gr = grids[it.blk];
+  const int n = bi.n;
   const int k = k_ws[it.blk];
   const int32_t* __restrict__ S = S_ws + (int64_t)it.blk * k_max;
-  const double* __restrict__ Yb = Y + bi.y_off;
-  const double* __restrict__ Pb = P + bi.p_off;
   const TA* __restrict__ A = static_cast<const TA*>(bi.A);
+  const double* __restrict__ Pb = P + bi.p_off;
+  const double* __restrict__ Yb = Y + bi.y_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t i = it.i0 + tid;
-  const bool row = i < bi.m;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int arow = 4 * (c16 & 3) + (c16 >> 2);
+  const int64_t pts = (int64_t)gr.nx * gr.ny * gr.nz;
+  const int cxyz = gr.cx * gr.cy * gr.cz;
+  double a2 = 0.0, e2 = 0.0;
 
-  double kr[KMAX];
-#pragma unroll
-  for (int t = 0; t < KMAX; ++t) kr[t] = 0.0;
-  if (row) {
-    const int64_t pts = (int64_t)g.nx * g.ny * g.nz;
-    const int f = (int)(i / pts);
-    const int64_t pp = i - f * pts;
-    const int x = (int)(pp % g.nx);
-    const int y = (int)((pp / g.nx) % g.ny);
-    const int z = (int)(pp / ((int64_t)g.nx * g.ny));
-    int tx0, tx1, ty0, ty1, tz0, tz1;
-    double wx0, wx1, wy0, wy1, wz0, wz1;
-    lin_weights(x, g.sx, g.cx, tx0, tx1, wx0, wx1);
-    lin_weights(y, g.sy, g.cy, ty0, ty1, wy0, wy1);
-    lin_weights(z, g.sz, g.cz, tz0, tz1, wz0, wz1);
-    const int fb = f * g.cx * g.cy * g.cz;
-    int idx[8];
-    double w[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int a = c >> 2, bb = (c >> 1) & 1, d = c & 1;
-      idx[c] = fb + (d ? tx1 : tx0) + g.cx * ((bb ? ty1 : ty0) + g.cy * (a ? tz1 : tz0));
-      w[c] = (a ? wz1 : wz0) * (bb ? wy1 : wy0) * (d ? wx1 : wx0);
-    }
-#pragma unroll
-    for (int t = 0; t < KMAX; ++t) {
-      if (t < k) {
-        const double* __restrict__ col = Yb + (int64_t)S[t] * l;
-        double v = 0.0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) v += w[c] * col[idx[c]];
-        kr[t] = v;
-      }
-    }
-  }
-
-  double e2 = 0.0, a2 = 0.0;
-  const int n = bi.n;
-  for (int j0 = 0; j0 < n; j0 += kIpCols) {
-    const int jc = min(kIpCols, n - j0);
-    __syncthreads();
-    for (int e = tid; e < kIpCols * KMAX; e += kIpRows) {
-      const int q = e / KMAX, t = e - q * KMAX;
-      pc[q][t] = (q < jc && t < k) ? Pb[(int64_t)(j0 + q) * k_max + t] : 0.0;
+  for (int c0 = 0; c0 < n; c0 += pcap) {
+    const int cc = min(pcap, n - c0);
+    const int ntile = (cc + 15) / 16;
+    for (int e = tid; e < ntile * 16 * kp; e += kRcThreads) {
+      const int q = e / kp, t = e - q * kp;
+      const bool ok = q < cc && t < k_max;
+      const double x = Pb[(int64_t)(c0 + min(q, cc - 1)) * k_max + min(t, k_max - 1)];
+      p_lds[e] = ok ? x : 0.0;   // P rows k..k_max-1 are zero
     }
     __syncthreads();
-    if (row) {
-      for (int q = 0; q < jc; ++q) {
-        double acc = 0.0;
+    for (int rs = 0; rs < it.nsub; ++rs) {
+      const int64_t rbase = it.i0 + (int64_t)rs * kSub + (int64_t)wave * 16 * MTR;
+      double as[MTR][KS];
 #pragma unroll
-        for (int t = 0; t < KMAX; ++t) acc += kr[t] * pc[q][t];
-        const double a = (double)A[(int64_t)(j0 + q) * bi.lda + i];
-        const double r = a - acc;
-        e2 += r * r;
-        a2 += a * a;
+      for (int mt = 0; mt < MTR; ++mt) {
+        const int64_t i = rbase + 16 * mt + arow;
+        const bool row = i < bi.m;
+        int idx[8];
+        double w[8];
+        {
+          const int64_t ii = row ? i : 0;
+          const int f = (int)(ii / pts);
+          const int64_t pp = ii - f * pts;
+          const int x = (int)(pp % gr.nx);
+          const int y = (int)((pp / gr.nx) % gr.ny);
+          const int z = (int)(pp / ((int64_t)gr.nx * gr.ny));
+          int tx0, tx1, ty0, ty1, tz0, tz1;
+          double wx0, wx1, wy0, wy1, wz0, wz1;
+          lin_weights(x, gr.sx, gr.cx, tx0, tx1, wx0, wx1);
+          lin_weights(y, gr.sy, gr.cy, ty0, ty1, wy0, wy1);
+          lin_weights(z, gr.sz, gr.cz, tz0, tz1, wz0, wz1);
+          const int fb = f * cxyz;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int a = c >> 2, bb = (c >> 1) & 1, d = c & 1;
+            idx[c] = fb + (d ? tx1 : tx0) + gr.cx * ((bb ? ty1 : ty0) + gr.cy * (a ? tz1 : tz0));
+            w[c] = (a ? wz1 : wz0) * (bb ? wy1 : wy0) * (d ? wx1 : wx0);
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int t = 4 * s + g;
+          double v = 0.0;
+          if (t < k && row) {
+            const double* __restrict__ col = Yb + (int64_t)S[t] * l;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) v += w[c] * col[idx[c]];
+          }
+          as[mt][s] = v;
+        }
+      }
+      for (int tq = 0; tq < ntile; ++tq) {
+        const int q = 16 * tq + c16;
+        const bool cok = q < cc;
+        const TA* colp = A + (int64_t)(c0 + (cok ? q : cc - 1)) * bi.lda;
+        double av[MTR][4];
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt)
+          rc_load4<TA, VEC>(colp, rbase + 16 * mt + 4 * g, bi.m, cok, av[mt]);
+        const double* pc = p_lds + q * kp + g;
+        f64x4 acc[MTR];
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const double pv = pc[4 * s];
+#pragma unroll
+          for (int mt = 0; mt < MTR; ++mt) acc[mt] = mfma_f64(as[mt][s], pv, acc[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MTR; ++mt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double r = av[mt][v] - acc[mt][v];
+            e2 += r * r;
+            a2 += av[mt][v] * av[mt][v];
+          }
       }
     }
+    __syncthreads();
   }
+
   e2 = wave_sum(e2);
   a2 = wave_sum(a2);
   if (lane == 0) {
     red[wave] = e2;
-    red[kIpRows / kWave + wave] = a2;
+    red[4 + wave] = a2;
   }
   __syncthreads();
   if (tid == 0) {
-    double se = 0.0, sa = 0.0;
-    for (int v = 0; v < kIpRows / kWave; ++v) {
-      se += red[v];
-      sa += red[kIpRows / kWave + v];
-    }
-    part[2 * (int64_t)blockIdx.x] = se;
-    part[2 * (int64_t)blockIdx.x + 1] = sa;
+    part[2 * (int64_t)blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    part[2 * (int64_t)blockIdx.x + 1] = red[4] + red[5] + red[6] + red[7];
   }
 }
 

@@ -53,6 +53,7 @@ class Workload:
     data_seed: int = 0
     omega_seed: int = 0
     nblocks_uneven: int = 0       # lowrank
+    subsample: int = 0            # > 0: coarse-grid sketch, every s-th point per direction
     extra: dict = field(default_factory=dict)
 
     @property
@@ -72,6 +73,18 @@ class Workload:
     @property
     def elem_bytes(self) -> int:
         return 8 if self.a_dtype == "f64" else 4
+
+    def grids(self) -> np.ndarray:
+        """Per-block grids (nx, ny, nz, fields, sx, sy, sz) of the coarse-grid sketch:
+        every block is an E^3 cube (E = N / B) of ``fields`` stacked fields."""
+        E, s = self.N // self.B, self.subsample
+        return np.tile(np.array([E, E, E, self.fields, s, s, s], dtype=np.int32),
+                       (self.nblocks, 1))
+
+    @property
+    def coarse_rows(self) -> int:
+        E, s = self.N // self.B, self.subsample
+        return self.fields * (-(-E // s)) ** 3
 
 
 WORKLOADS = {
@@ -113,6 +126,28 @@ WORKLOADS = {
                     "8^3 (m_b=2560), k=64, l=96, FP8-e4m3 sketch, one snapshot per update",
         kind="turbulence", N=256, B=32, n=384, fields=5, dt=0.02, a_dtype="f32",
         l=96, k_max=64, prec="fp8", lp_terms=3, stream=True, data_seed=2005, omega_seed=1005),
+    # the paper's own sketch (Section 2, Algorithms 2-3; Section 5.2.3's 64^3 single
+    # partition at interval 3): coarse-grid subsample, trilinear single-pass error
+    "tgv64_single_sub3": Workload(
+        name="tgv64_single_sub3",
+        description="analytic TGV 64^3 (u,v,w), 100 snapshots in [0,10], nu=0.01, one block, "
+                    "coarse-grid sketch every 3rd point per direction (3*22^3=31944 rows), "
+                    "tolerance 1e-10 with k<=4, single-pass (trilinear) error",
+        kind="tgv", N=64, B=1, n=100, fields=3, nu=0.01, T=10.0, a_dtype="f64",
+        l=31944, k_max=4, tol=1e-10, prec="subsample", subsample=3, data_seed=2006),
+    # the 512-block TGV data of the double-precision Gaussian workload, coarse-grid sketch
+    "tgv128_b512_sub3": Workload(
+        name="tgv128_b512_sub3",
+        description="analytic TGV 128^3 (u,v,w) + 1e-6 relative Gaussian noise, 512 blocks of "
+                    "16^3 (m_b=12288), 256 snapshots in [0,10], nu=0.005, coarse-grid sketch "
+                    "every 3rd point (648 rows), tolerance 1e-8 with k<=32, single-pass error",
+        kind="tgv", N=128, B=8, n=256, fields=3, nu=0.005, T=10.0, noise=1e-6, a_dtype="f64",
+        l=648, k_max=32, tol=1e-8, prec="subsample", subsample=3, data_seed=2002),
+    "tgv128_b512_sub7": Workload(
+        name="tgv128_b512_sub7",
+        description="as tgv128_b512_sub3 with every 7th point (3*3^3=81 coarse rows)",
+        kind="tgv", N=128, B=8, n=256, fields=3, nu=0.005, T=10.0, noise=1e-6, a_dtype="f64",
+        l=81, k_max=32, tol=1e-8, prec="subsample", subsample=7, data_seed=2002),
 }
 
 

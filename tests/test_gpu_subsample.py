@@ -131,3 +131,17 @@ def test_interval_one_equals_the_plain_id_and_state_errors():
         ctx.reconstruct_interp()
     assert e.value.status == sp.SPID_ESTATE
     ctx.close()
+
+
+@pytest.mark.parametrize("grid", [(16, 16, 16, 1, 3, 3, 3), (24, 20, 12, 2, 2, 2, 2)])
+def test_tall_selection_row_caching_variants(grid):
+    """Coarse sketches of 129..256 and 1025+ rows (the register-cached and the
+    streaming forms of the global-memory selection)."""
+    grids = [grid] * 5
+    l = len(oracle.coarse_rows(grid))
+    assert 128 < l <= 256 or l > 1024
+    blocks = _field_blocks(grids, 120, 5, noise=1e-8)
+    print("case: tall variant", l, flush=True)
+    g = gpu_run(blocks, None, 24, 0, tol=1e-7, grids=grids)
+    o = oracle_run(blocks, l, 24, 0, tol=1e-7, grids=grids)
+    _check(g, o, blocks, grids)

@@ -68,3 +68,13 @@ def test_lowrank_block_singular_values():
         s = np.linalg.svd(blk, compute_uv=False)
         assert np.allclose(s[:r], 10.0 ** (-0.25 * np.arange(r)), rtol=1e-10)
         assert np.all(s[r:] < 1e-12)
+
+
+@pytest.mark.parametrize("name", ["tgv64_single_sub3", "tgv128_b512_sub3", "tgv128_b512_sub7"])
+def test_coarse_grid_workloads_match_the_oracle_grid(name):
+    import oracle
+    w = si.WORKLOADS[name]
+    g = w.grids()
+    assert g.shape == (w.nblocks, 7)
+    assert int(np.prod(g[0][:4])) == (w.N // w.B) ** 3 * w.fields
+    assert len(oracle.coarse_rows(g[0])) == w.coarse_rows == w.l
