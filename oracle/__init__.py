@@ -22,6 +22,10 @@ follows in arXiv 2103.01380:
                                  equation (single_ID) / Algorithm 3, the
                                  single-pass approximation M B(:,S) C with a
                                  trilinear M (Section 5.2).
+* ``two_stage``               -- Section 3.4.2, the modified (two-stage) ID:
+                                 rank-k IDs of temporal windows, then a
+                                 tolerance ID of the concatenated skeletons,
+                                 C^{1'} = C^1 C^{0'}.
 * ``run_batch``               -- Section 3.2, independent blocks, threaded.
 
 Parity pins: every function is pinned by the ``-m "not gpu"`` tests in
@@ -109,6 +113,9 @@ def _load():
         lib.spid_ref_interp_error.argtypes = [P, c.c_int64, c.c_int32, P, c.c_int64, c.c_int32,
                                               P, c.c_int32, c.c_int32, c.c_int32, P, P, P, P]
         lib.spid_ref_interp_error.restype = c.c_int
+        lib.spid_ref_two_stage.argtypes = [c.c_int32, c.c_int32, P, c.c_int32, c.c_int32,
+                                           c.c_double, c.c_int32, c.c_double, P, P, P, P, P]
+        lib.spid_ref_two_stage.restype = c.c_int
         lib.spid_ref_run_batch.restype = c.c_int
         _lib = lib
     return _lib
@@ -312,6 +319,32 @@ def compression_factor(m, n, k, m_stored=None) -> float:
         return _load().spid_ref_compression_factor(len(m), _ptr(m), _ptr(n), _ptr(k), None)
     ms = np.ascontiguousarray(m_stored, dtype=np.int64)
     return _load().spid_ref_compression_factor(len(m), _ptr(m), _ptr(n), _ptr(k), _ptr(ms))
+
+
+@dataclass
+class TwoStage:
+    S: np.ndarray        # int32 [k_max], columns of A in stage-2 pivot order, -1 past k
+    k: int
+    status: int
+    P: np.ndarray        # k_max x n, C^1 C^{0'}
+    gaps: np.ndarray     # stage-2 relative top-two gaps
+
+
+def two_stage(Y: np.ndarray, nwin: int, k1: int, k_max: int, tol2: float,
+              rank_floor: float = 0.0) -> TwoStage:
+    """Modified (two-stage) ID on a block's sketch Y (Section 3.4.2)."""
+    Y = np.asfortranarray(Y, dtype=np.float64)
+    l, n = Y.shape
+    S = np.full(k_max, -1, dtype=np.int32)
+    k = np.zeros(1, dtype=np.int32)
+    st = np.zeros(1, dtype=np.int32)
+    P = np.zeros((k_max, n), dtype=np.float64, order="F")
+    gaps = np.zeros(k_max, dtype=np.float64)
+    rc = _load().spid_ref_two_stage(l, n, _ptr(Y), nwin, k1, rank_floor, k_max, tol2, _ptr(S),
+                                    _ptr(k), _ptr(st), _ptr(P), _ptr(gaps))
+    if rc != 0:
+        raise ValueError("spid_ref_two_stage: invalid arguments")
+    return TwoStage(S, int(k[0]), int(st[0]), P, gaps)
 
 
 @dataclass

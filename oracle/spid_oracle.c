@@ -479,6 +479,104 @@ int spid_ref_coeffs(int32_t k_eff, int32_t k_max, int32_t n, const double* R,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Modified (two-stage) ID (Section 3.4.2) on the sketch Y (l x n) of one     */
+/* block.  Windows w = 0..nwin-1 hold columns [c_w, c_{w+1}), c_w =          */
+/* floor(w n / nwin) (n/N time steps each when nwin divides n).              */
+/*   Stage 1: rank-k1 ID of each window: I_w (window positions), C_w.        */
+/*   Stage 2: the concatenated skeleton A^{0'} = A(:, I_U), I_U the union of  */
+/*     the I_w shifted by c_w in window order, has the sketch Y(:, I_U) (one  */
+/*     sketch matrix serves every column); its ID with tolerance tol2 and at  */
+/*     most k_max columns gives I_1 (positions in I_U) and C^1.              */
+/*   Result: S = I_U(I_1) in stage-2 pivot order, P = C^1 C^{0'} (k_max x n, */
+/*     column-major, rows >= k zero), C^{0'} block-diagonal of the C_w.      */
+/* status: the stage-2 status, or NONFINITE (k = 0) when a window's sketch   */
+/* holds a non-finite entry.  gaps: the stage-2 relative top-two gaps.       */
+/* ------------------------------------------------------------------------- */
+int spid_ref_two_stage(int32_t l, int32_t n, const double* Y, int32_t nwin, int32_t k1,
+                       double rank_floor, int32_t k_max, double tol2, int32_t* S,
+                       int32_t* k_eff, int32_t* status, double* P, double* gaps) {
+  if (l <= 0 || n <= 0 || nwin < 1 || nwin > n || k1 < 1 || k_max < 1 || tol2 < 0.0)
+    return REF_EINVAL;
+  int rc = REF_OK;
+  int32_t* I1 = (int32_t*)malloc(sizeof(int32_t) * (size_t)nwin * k1);
+  int32_t* kw = (int32_t*)calloc((size_t)nwin, sizeof(int32_t));
+  int32_t* IU = (int32_t*)malloc(sizeof(int32_t) * (size_t)nwin * k1);
+  int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * (size_t)nwin * k1);
+  double* Cw = (double*)calloc((size_t)k1 * n, sizeof(double));       /* C_w, window by window */
+  double* R1 = (double*)malloc(sizeof(double) * (size_t)k1 * n);
+  double* g1 = (double*)malloc(sizeof(double) * (size_t)k1);
+  double* Y2 = (double*)malloc(sizeof(double) * (size_t)l * nwin * k1);
+  double* R2 = (double*)malloc(sizeof(double) * (size_t)k_max * nwin * k1);
+  double* C1 = (double*)malloc(sizeof(double) * (size_t)k_max * nwin * k1);
+  if (!I1 || !kw || !IU || !owner || !Cw || !R1 || !g1 || !Y2 || !R2 || !C1) {
+    rc = REF_EINVAL;
+    goto done;
+  }
+  for (int64_t t = 0; t < (int64_t)k_max * n; t++) P[t] = 0.0;
+  for (int32_t s = 0; s < k_max; s++) {
+    S[s] = -1;
+    gaps[s] = 0.0;
+  }
+  *k_eff = 0;
+  /* Stage 1 */
+  int32_t nu_cols = 0, nonfinite = 0;
+  for (int32_t w = 0; w < nwin; w++) {
+    int32_t c0 = (int32_t)((int64_t)w * n / nwin), c1 = (int32_t)((int64_t)(w + 1) * n / nwin);
+    int32_t nw = c1 - c0, st1;
+    rc = spid_ref_select(l, nw, Y + (int64_t)c0 * l, k1, 0.0, rank_floor, I1 + (int64_t)w * k1,
+                         kw + w, R1, NULL, g1, &st1, NULL);
+    if (rc != REF_OK) goto done;
+    if (st1 == REF_ST_NONFINITE) nonfinite = 1;
+    rc = spid_ref_coeffs(kw[w], k1, nw, R1, I1 + (int64_t)w * k1, Cw + (int64_t)c0 * k1);
+    if (rc != REF_OK) goto done;
+    for (int32_t t = 0; t < kw[w]; t++) {
+      IU[nu_cols] = c0 + I1[(int64_t)w * k1 + t];
+      owner[nu_cols] = w;
+      nu_cols++;
+    }
+  }
+  if (nonfinite || nu_cols == 0) {
+    *status = nonfinite ? REF_ST_NONFINITE : REF_ST_RANK_DEFICIENT;
+    goto done;
+  }
+  /* Stage 2: the sketch of A(:, I_U) is Y(:, I_U) */
+  for (int32_t c = 0; c < nu_cols; c++)
+    memcpy(Y2 + (int64_t)c * l, Y + (int64_t)IU[c] * l, sizeof(double) * (size_t)l);
+  int32_t S2[1024], k2 = 0;
+  if (k_max > 1024) {
+    rc = REF_EINVAL;
+    goto done;
+  }
+  rc = spid_ref_select(l, nu_cols, Y2, k_max, tol2, rank_floor, S2, &k2, R2, NULL, gaps, status,
+                       NULL);
+  if (rc != REF_OK) goto done;
+  rc = spid_ref_coeffs(k2, k_max, nu_cols, R2, S2, C1);
+  if (rc != REF_OK) goto done;
+  /* C^{1'} = C^1 C^{0'}: column j of window w combines the stage-2 columns of   */
+  /* that window's skeleton with the stage-1 coefficients of j                   */
+  for (int32_t w = 0; w < nwin; w++) {
+    int32_t c0 = (int32_t)((int64_t)w * n / nwin), c1 = (int32_t)((int64_t)(w + 1) * n / nwin);
+    for (int32_t j = c0; j < c1; j++)
+      for (int32_t s = 0; s < k2; s++) {
+        double acc = 0.0;
+        int32_t t = 0;
+        for (int32_t c = 0; c < nu_cols; c++) {
+          if (owner[c] != w) continue;
+          acc += C1[(int64_t)c * k_max + s] * Cw[(int64_t)j * k1 + t];
+          t++;
+        }
+        P[(int64_t)j * k_max + s] = acc;
+      }
+  }
+  for (int32_t s = 0; s < k2; s++) S[s] = IU[S2[s]];
+  *k_eff = k2;
+done:
+  free(I1); free(kw); free(IU); free(owner); free(Cw); free(R1); free(g1); free(Y2); free(R2);
+  free(C1);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Reconstruction error against the stored A (Section 5.1):                  */
 /* err2 = sum_j ||A(:,j) - sum_t A(:,S[t]) P(t,j)||^2 over every column,     */
 /* nrm2 = ||A||_F^2.  Sums in ascending i, then ascending j.                 */
