@@ -121,6 +121,11 @@ typedef struct {
                                for F64) */
   const spid_grid* h_grid;  /* host [nblocks]: block grids, required for
                                SPID_SK_SUBSAMPLE (NULL otherwise) */
+  int32_t ts_windows;       /* > 0: reserve the modified two-stage ID of
+                               spid_select_two_stage with this many temporal
+                               windows per block (<= every n_b); 0: off */
+  int32_t ts_k1;            /* two-stage: stage-1 rank of every window,
+                               1..96, ts_windows * ts_k1 <= 1024 */
 } spid_desc;
 
 /* Launch-shape choices (the batching schedule of Section 3.2's independent
@@ -189,6 +194,25 @@ spid_status spid_sketch_update(spid_ctx* ctx, int32_t j0, int32_t w, void* strea
  * workspace for spid_coeffs.  ESTATE unless every column was sketched. */
 spid_status spid_select(spid_ctx* ctx, int32_t* d_k, int32_t* d_S, int32_t* d_status,
                         void* stream);
+
+/* Modified (two-stage) ID (Section 3.4.2), in place of spid_select +
+ * spid_coeffs; needs desc.ts_windows > 0.  Block b's columns form ts_windows
+ * consecutive windows, window w = columns [floor(w n_b / W), floor((w+1) n_b / W)).
+ *   Stage 1: rank-ts_k1 ID of every window's sketch (rank_floor applies):
+ *            pivots I_w and coefficients C_w.
+ *   Stage 2: ID of the concatenated window skeletons A_b(:, I_U) (I_U the
+ *            stage-1 pivots shifted to columns of A_b, window order) with the
+ *            descriptor's tol (0: fixed rank k_max), at most k_max columns.
+ *            Its sketch is Y_b(:, I_U), gathered from the resident sketch: no
+ *            pass over A.
+ * Outputs as spid_select (d_S = columns of A_b in stage-2 pivot order) plus
+ * d_P = C^1 C^{0'} (k_max x n_b per block, the layout of spid_coeffs, rows
+ * >= k_b zero, P_b(:, S[t]) = e_t).  Afterwards spid_reconstruct measures
+ * ||A_b - A_b(:,S_b) P_b||.  A window whose sketch is non-finite makes the
+ * block NONFINITE (k_b = 0).  ESTATE unless every column was sketched;
+ * EINVAL without ts_windows.  Any of d_k, d_S, d_status may be NULL. */
+spid_status spid_select_two_stage(spid_ctx* ctx, int32_t* d_k, int32_t* d_S, int32_t* d_status,
+                                  double* d_P, void* stream);
 
 /* Coefficients (Section 2, Algorithm 1): P_b = [I | R11^+ R12] Z^T, FP64.
  * d_P holds every block's k_max x n_b column-major matrix (leading dimension

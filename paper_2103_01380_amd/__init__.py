@@ -9,8 +9,9 @@ The functions carry the C names (``spid_workspace_bytes``, ``spid_create``,
 ``spid_bind_A``, ``spid_sketch_update``, ``spid_select``, ``spid_coeffs``,
 ``spid_reconstruct``, ``spid_copy_sketch``, ``spid_destroy``,
 ``spid_last_error``, the launch-shape variants ``spid_workspace_bytes_tuned``,
-``spid_create_tuned``, ``spid_get_tuning``, and ``spid_reconstruct_interp`` of the
-coarse-grid sketch); :class:`SPID` bundles them for a batch of blocks.
+``spid_create_tuned``, ``spid_get_tuning``, ``spid_reconstruct_interp`` of the
+coarse-grid sketch and ``spid_select_two_stage`` of the modified two-stage ID);
+:class:`SPID` bundles them for a batch of blocks.
 """
 from __future__ import annotations
 
@@ -30,7 +31,8 @@ SK_F64, SK_BF16, SK_FP8E4M3, SK_SUBSAMPLE = 0, 1, 2, 3
 EXPORTS = ("spid_workspace_bytes", "spid_workspace_bytes_tuned", "spid_create",
            "spid_create_tuned", "spid_get_tuning", "spid_bind_A", "spid_sketch_update",
            "spid_select", "spid_coeffs", "spid_reconstruct", "spid_copy_sketch",
-           "spid_destroy", "spid_last_error", "spid_reconstruct_interp")
+           "spid_destroy", "spid_last_error", "spid_reconstruct_interp",
+           "spid_select_two_stage")
 
 
 class SpidError(RuntimeError):
@@ -58,6 +60,8 @@ class spid_desc(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("lp_terms", ctypes.c_int32),
         ("h_grid", ctypes.c_void_p),
+        ("ts_windows", ctypes.c_int32),
+        ("ts_k1", ctypes.c_int32),
     ]
 
 
@@ -121,6 +125,8 @@ def load_library(path: str = LIB_PATH):
     lib.spid_reconstruct.restype = ctypes.c_int
     lib.spid_reconstruct_interp.argtypes = [P, P, P, P, P, P]
     lib.spid_reconstruct_interp.restype = ctypes.c_int
+    lib.spid_select_two_stage.argtypes = [P, P, P, P, P, P]
+    lib.spid_select_two_stage.restype = ctypes.c_int
     lib.spid_copy_sketch.argtypes = [P, P, P]
     lib.spid_copy_sketch.restype = ctypes.c_int
     lib.spid_destroy.argtypes = [P]
@@ -153,7 +159,7 @@ def _stream(stream):
 
 
 def make_desc(m, n, l, k_max, tol=0.0, rank_floor=0.0, seed=0, omega_per_block=False,
-              a_dtype=A_F64, prec=SK_F64, lp_terms=1, grids=None):
+              a_dtype=A_F64, prec=SK_F64, lp_terms=1, grids=None, ts_windows=0, ts_k1=0):
     """``grids``: ``[nblocks, 7]`` (nx, ny, nz, nfields, sx, sy, sz) for the coarse-grid
     sketch, else None."""
     m = np.ascontiguousarray(m, dtype=np.int64)
@@ -166,6 +172,7 @@ def make_desc(m, n, l, k_max, tol=0.0, rank_floor=0.0, seed=0, omega_per_block=F
     d.seed = int(seed)
     d.omega_per_block = int(bool(omega_per_block))
     d.a_dtype, d.prec, d.lp_terms = int(a_dtype), int(prec), int(lp_terms)
+    d.ts_windows, d.ts_k1 = int(ts_windows), int(ts_k1)
     g = None
     if grids is not None:
         g = np.ascontiguousarray(np.asarray(grids, dtype=np.int32).reshape(len(m), 7))
@@ -236,6 +243,11 @@ def spid_reconstruct_interp(ctx, P, err2, nrm2, coarse_skeleton=None, stream=Non
                                                   _ptr(coarse_skeleton), _stream(stream)))
 
 
+def spid_select_two_stage(ctx, P, k=None, S=None, status=None, stream=None):
+    _check(load_library().spid_select_two_stage(ctx, _ptr(k), _ptr(S), _ptr(status), _ptr(P),
+                                                _stream(stream)))
+
+
 def spid_copy_sketch(ctx, Y, stream=None):
     _check(load_library().spid_copy_sketch(ctx, _ptr(Y), _stream(stream)))
 
@@ -263,6 +275,9 @@ class SPID:
     same device: ``k``, ``S`` ([nblocks, k_max]), ``status``, ``P`` (flat,
     per-block k_max x n_b column-major), ``err2``, ``nrm2``.
 
+    ``ts_windows`` / ``ts_k1`` reserve the modified two-stage ID
+    (:meth:`select_two_stage` in place of :meth:`select` + :meth:`coeffs`).
+
     ``prec="subsample"`` with ``grids`` (one ``(nx, ny, nz, nfields, sx, sy, sz)`` per
     block, or one for all) selects the coarse-grid sketch B = A(J,:); ``l`` then
     defaults to the largest coarse row count, and :meth:`reconstruct_interp` gives
@@ -270,7 +285,8 @@ class SPID:
     """
 
     def __init__(self, m, n, l, k_max, tol=0.0, rank_floor=0.0, seed=0, omega_per_block=False,
-                 a_dtype="f64", prec="f64", lp_terms=1, device="cuda", tuning=None, grids=None):
+                 a_dtype="f64", prec="f64", lp_terms=1, device="cuda", tuning=None, grids=None,
+                 ts_windows=0, ts_k1=0):
         import torch
         self.m = np.ascontiguousarray(m, dtype=np.int64)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
@@ -286,7 +302,7 @@ class SPID:
         self.l, self.k_max = int(l), int(k_max)
         self.desc = make_desc(self.m, self.n, l, k_max, tol, rank_floor, seed, omega_per_block,
                               A_F64 if a_dtype == "f64" else A_F32, _PREC[prec], lp_terms,
-                              self.grids)
+                              self.grids, ts_windows, ts_k1)
         self._tuning = make_tuning(tuning)
         nbytes = spid_workspace_bytes_tuned(self.desc, self._tuning)
         if nbytes == 0:
@@ -339,6 +355,10 @@ class SPID:
 
     def reconstruct(self, skeleton=None, stream=None):
         spid_reconstruct(self.ctx, self.P, self.err2, self.nrm2, skeleton, stream)
+
+    def select_two_stage(self, stream=None):
+        """Modified two-stage ID (needs ``ts_windows``): S, k, status and P in one call."""
+        spid_select_two_stage(self.ctx, self.P, self.k, self.S, self.status, stream)
 
     def reconstruct_interp(self, coarse_skeleton=None, stream=None):
         """Single-pass error ||A - M B(:,S) P||^2 per block into ``err2_interp``."""

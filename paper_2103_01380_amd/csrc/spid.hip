@@ -16,6 +16,7 @@
 #include "../../include/spid.h"
 #include "spid_kernels.h"
 #include "spid_subsample.h"
+#include "spid_two_stage.h"
 
 using namespace spid;
 
@@ -45,17 +46,18 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Selection kernel choice for a sketch height l and widest block max_n.
+struct SelShape {
+  int LMAX = 16, CPT = 1, sel_thr = 64, sel_rr = 0, sel_pair = 0, sel_tall = 0;
+  size_t sel_lds = 0;
+};
+
 // tile/template choices for a descriptor
 struct Shape {
   int MT;        // 16-row MFMA tiles covering l
   int TN;        // 16-column tiles per wave in the sketch
   int NW;        // waves per sketch workgroup (columns per workgroup = 16 * NW * TN)
-  int LMAX;      // register rows of a sketch column in the selection
-  int CPT;       // sketch columns per thread in the selection
-  int sel_thr;   // selection workgroup size
-  int sel_rr;    // 0: all-register selection; else register rows of the hybrid kernel
-  size_t sel_lds;  // dynamic LDS of the hybrid selection kernel
-  int sel_pair;    // 0, or rows per lane of the two-lanes-per-column selection
+  SelShape sel;  // selection kernel
   int KMAX;      // register skeleton width in the error pass
   int KS;        // k-steps of 4 selected columns in the matrix-core error pass
   int MTR;       // 16-row MFMA tiles per wave in the error pass
@@ -65,7 +67,6 @@ struct Shape {
   int rc_bf16;   // 1: split-bfloat16 error pass (FP32 data, low-precision sketch)
   int KS32;      // k-steps of 32 selected columns in the split-bfloat16 error pass
   int sk_items;  // target number of sketch work items
-  int sel_tall;  // 1: selection of a tall coarse sketch in global memory
 };
 
 int pick_mt(int l) {
@@ -89,6 +90,44 @@ int pick_kmax(int k) {
   return 96;
 }
 
+// false: no register/LDS kernel fits and the global-memory kernel is not allowed
+bool pick_sel(int l, int max_n, bool allow_tall, SelShape& sh) {
+  sh = SelShape{};
+  sh.LMAX = pick_lmax(l);
+  sh.sel_tall = (allow_tall && l > kMaxL) ? 1 : 0;
+  sh.CPT = (max_n > 512) ? 2 : 1;
+  {
+    int need = (max_n + sh.CPT - 1) / sh.CPT;
+    sh.sel_thr = std::max(64, (need + 63) / 64 * 64);
+  }
+  if (sh.sel_tall) {
+    // coarse sketch taller than the register/LDS kernels take: global memory
+  } else if (sh.LMAX > 56 && max_n <= 384) {
+    // two lanes per column, every row in registers
+    sh.sel_pair = l <= 64 ? 32 : (l <= 96 ? 48 : 64);
+    sh.sel_thr = std::max(64, (2 * max_n + 63) / 64 * 64);
+  } else if (sh.LMAX > 56 || max_n > 512) {
+    // hybrid: one column per thread, RR rows in registers, the rest in LDS
+    sh.CPT = 1;
+    sh.sel_thr = std::max(64, (max_n + 63) / 64 * 64);
+    const int rr_opts[] = {48, 32, 16};
+    for (int rr : rr_opts) {
+      if (sh.sel_thr > 512 && rr > 32) continue;   // 1024 threads: 128 registers per lane
+      const size_t lds = sizeof(double) * (size_t)std::max(0, l - rr) * sh.sel_thr;
+      if (lds <= 150 * 1024) {
+        sh.sel_rr = rr;
+        sh.sel_lds = lds;
+        break;
+      }
+    }
+    if (sh.sel_rr == 0) {
+      if (!allow_tall) return false;
+      sh.sel_tall = 1;
+    }
+  }
+  return true;
+}
+
 // Workspace plan (sizes in bytes, offsets from the workspace base)
 struct Plan {
   Shape sh;
@@ -110,11 +149,17 @@ struct Plan {
   bool coarse = false;
   std::vector<GridInfo> grid;
   int64_t sum_mc = 0;
+  // modified two-stage ID: window table (nblocks * nwin), stage-2 table (nblocks)
+  int ts_nwin = 0, ts_k1 = 0, ts_kmax1 = 8;
+  SelShape ts_sel1, ts_sel2;
+  std::vector<BlkInfo> ts_win, ts_blk2;
+  int64_t ts_n2sum = 0;
   int64_t sum_n = 0, sum_m = 0, part_elems = 0;
   int max_n = 0, max_split_n = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
       off_st, off_rcpart, off_perm, off_sitems, off_sheads, off_ritems, off_pt, off_cols, off_ncols,
-      off_grid, off_W, total;
+      off_grid, off_W, off_tswin, off_tsblk2, off_tsR1, off_tsP1, off_tsS1, off_tsk1, off_tsst1,
+      off_tsY2, off_tsW2, off_tsR2, off_tsP2, off_tsS2, off_tsk2, off_tsst2, total;
 };
 
 spid_status validate(const spid_desc* d) {
@@ -138,6 +183,17 @@ spid_status validate(const spid_desc* d) {
                 "sketch must be SPID_SK_F64, _BF16, _FP8E4M3 or _SUBSAMPLE (got %d)", d->prec);
   if (coarse && !d->h_grid)
     return fail(SPID_EINVAL, "coarse-grid sketch: h_grid must be a host array of block grids");
+  if (d->ts_windows < 0) return fail(SPID_EINVAL, "ts_windows must be >= 0");
+  if (d->ts_windows > 0) {
+    if (d->ts_k1 < 1 || d->ts_k1 > kMaxK)
+      return fail(SPID_EINVAL, "two-stage: ts_k1 must be in [1, %d] (got %d)", kMaxK, d->ts_k1);
+    if ((int64_t)d->ts_windows * d->ts_k1 > kMaxN)
+      return fail(SPID_EINVAL, "two-stage: ts_windows * ts_k1 must be <= %d", kMaxN);
+    if (d->a_dtype == SPID_A_F32 && (d->prec == SPID_SK_BF16 || d->prec == SPID_SK_FP8E4M3))
+      return fail(SPID_EINVAL,
+                  "two-stage: not available with FP32 data and a BF16/FP8 sketch (the "
+                  "split-bfloat16 error pass needs spid_coeffs)");
+  }
   if ((d->prec == SPID_SK_BF16 || d->prec == SPID_SK_FP8E4M3) &&
       (d->lp_terms < 1 || d->lp_terms > 3))
     return fail(SPID_EINVAL, "lp_terms must be 1..3 (got %d)", d->lp_terms);
@@ -151,6 +207,8 @@ spid_status validate(const spid_desc* d) {
     if (d->tol == 0.0 && (d->k_max > d->l || d->k_max > n))
       return fail(SPID_EINVAL,
                   "block %d: fixed rank k_max=%d exceeds min(l=%d, n=%d)", b, d->k_max, d->l, n);
+    if (d->ts_windows > n)
+      return fail(SPID_EINVAL, "block %d: %d windows exceed n = %d", b, d->ts_windows, n);
     if (coarse) {
       const spid_grid& g = d->h_grid[b];
       if (g.nx < 1 || g.ny < 1 || g.nz < 1 || g.nfields < 1 || g.sx < 1 || g.sy < 1 || g.sz < 1)
@@ -225,41 +283,9 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     if (tune && tune->sk_nw == 4) return fail(SPID_EINVAL, "tuning: sk_nw=4 requires sk_tn=1");
     sh.NW = 8;
   }
-  sh.LMAX = pick_lmax(d->l);
-  sh.sel_tall = (p.coarse && d->l > kMaxL) ? 1 : 0;
-  sh.CPT = (p.max_n > 512) ? 2 : 1;
-  {
-    int need = (p.max_n + sh.CPT - 1) / sh.CPT;
-    sh.sel_thr = std::max(64, (need + 63) / 64 * 64);
-  }
-  sh.sel_rr = 0;
-  sh.sel_lds = 0;
-  sh.sel_pair = 0;
-  if (sh.sel_tall) {
-    // coarse sketch taller than the register/LDS kernels take: global memory
-  } else if (sh.LMAX > 56 && p.max_n <= 384) {
-    // two lanes per column, every row in registers
-    sh.sel_pair = d->l <= 64 ? 32 : (d->l <= 96 ? 48 : 64);
-    sh.sel_thr = std::max(64, (2 * p.max_n + 63) / 64 * 64);
-  } else if (sh.LMAX > 56 || p.max_n > 512) {
-    // hybrid: one column per thread, RR rows in registers, the rest in LDS
-    sh.CPT = 1;
-    sh.sel_thr = std::max(64, (p.max_n + 63) / 64 * 64);
-    const int rr_opts[] = {48, 32, 16};
-    for (int rr : rr_opts) {
-      if (sh.sel_thr > 512 && rr > 32) continue;   // 1024 threads: 128 registers per lane
-      const size_t lds = sizeof(double) * (size_t)std::max(0, d->l - rr) * sh.sel_thr;
-      if (lds <= 150 * 1024) {
-        sh.sel_rr = rr;
-        sh.sel_lds = lds;
-        break;
-      }
-    }
-    if (sh.sel_rr == 0 && p.coarse) sh.sel_tall = 1;
-    if (sh.sel_rr == 0 && !p.coarse)
-      return fail(SPID_EINVAL, "l=%d with n up to %d exceeds the selection register/LDS budget",
-                  d->l, p.max_n);
-  }
+  if (!pick_sel(d->l, p.max_n, p.coarse, sh.sel))
+    return fail(SPID_EINVAL, "l=%d with n up to %d exceeds the selection register/LDS budget",
+                d->l, p.max_n);
   sh.KMAX = pick_kmax(d->k_max);
   {
     const int ks = (d->k_max + 3) / 4;
@@ -386,6 +412,46 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     }
   }
 
+  if (d->ts_windows > 0) {
+    const int nw = d->ts_windows, k1 = d->ts_k1;
+    p.ts_nwin = nw;
+    p.ts_k1 = k1;
+    p.ts_kmax1 = pick_kmax(k1);
+    p.ts_win.resize((size_t)nb * nw);
+    p.ts_blk2.resize(nb);
+    int max_w = 0;
+    int64_t r1 = 0, y2 = 0, r2 = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int32_t n = d->h_n[b];
+      for (int w = 0; w < nw; ++w) {
+        const int c0 = (int)((int64_t)w * n / nw), c1 = (int)((int64_t)(w + 1) * n / nw);
+        BlkInfo wi = p.blk[b];
+        wi.y_off = p.blk[b].y_off + (int64_t)c0 * d->l;
+        wi.n = c1 - c0;
+        wi.r_off = r1;
+        wi.p_off = r1;
+        wi.nsplit = 1;
+        r1 += (int64_t)k1 * wi.n;
+        max_w = std::max(max_w, wi.n);
+        p.ts_win[(size_t)b * nw + w] = wi;
+      }
+      BlkInfo b2 = p.blk[b];
+      b2.n = nw * k1;
+      b2.y_off = y2;
+      b2.r_off = r2;
+      b2.p_off = r2;
+      b2.nsplit = 1;
+      y2 += (int64_t)d->l * b2.n;
+      r2 += (int64_t)d->k_max * b2.n;
+      p.ts_blk2[b] = b2;
+    }
+    p.ts_n2sum = (int64_t)nb * nw * k1;
+    if (!pick_sel(d->l, max_w, p.coarse, p.ts_sel1) ||
+        !pick_sel(d->l, nw * k1, p.coarse, p.ts_sel2))
+      return fail(SPID_EINVAL, "two-stage: l=%d exceeds the selection register/LDS budget",
+                  d->l);
+  }
+
   // one-snapshot (stream) plan: needs Omega shared by all blocks
   p.st_ok = d->omega_per_block == 0 && !p.coarse;
   if (p.st_ok) {
@@ -493,7 +559,27 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_cols = take(sh.rc_bf16 ? sizeof(int32_t) * (size_t)p.sum_n : 256);
   p.off_ncols = take(sizeof(int32_t) * nb);
   p.off_grid = take(sizeof(GridInfo) * std::max<size_t>(1, p.grid.size()));
-  p.off_W = take(sh.sel_tall ? sizeof(double) * (size_t)d->l * p.sum_n : 256);
+  p.off_W = take((sh.sel.sel_tall || p.ts_sel1.sel_tall) ? sizeof(double) * (size_t)d->l * p.sum_n
+                                                         : 256);
+  {
+    const bool ts = p.ts_nwin > 0;
+    const size_t nwt = ts ? p.ts_win.size() : 1;
+    const size_t k1 = ts ? p.ts_k1 : 1;
+    p.off_tswin = take(sizeof(BlkInfo) * nwt);
+    p.off_tsblk2 = take(sizeof(BlkInfo) * std::max<size_t>(1, p.ts_blk2.size()));
+    p.off_tsR1 = take(ts ? sizeof(double) * k1 * (size_t)p.sum_n : 256);
+    p.off_tsP1 = take(ts ? sizeof(double) * k1 * (size_t)p.sum_n : 256);
+    p.off_tsS1 = take(sizeof(int32_t) * nwt * k1);
+    p.off_tsk1 = take(sizeof(int32_t) * nwt);
+    p.off_tsst1 = take(sizeof(int32_t) * nwt);
+    p.off_tsY2 = take(ts ? ysz * (size_t)d->l * p.ts_n2sum : 256);
+    p.off_tsW2 = take(ts && p.ts_sel2.sel_tall ? sizeof(double) * (size_t)d->l * p.ts_n2sum : 256);
+    p.off_tsR2 = take(ts ? sizeof(double) * (size_t)d->k_max * p.ts_n2sum : 256);
+    p.off_tsP2 = take(ts ? sizeof(double) * (size_t)d->k_max * p.ts_n2sum : 256);
+    p.off_tsS2 = take(sizeof(int32_t) * (size_t)nb * d->k_max);
+    p.off_tsk2 = take(sizeof(int32_t) * nb);
+    p.off_tsst2 = take(sizeof(int32_t) * nb);
+  }
   p.total = off;
   return SPID_OK;
 }
@@ -643,72 +729,90 @@ bool launch_sketch_stream_a(spid_ctx* c, int j, hipStream_t s) {
 }
 
 // ---- selection dispatch
-template <typename TY, int LMAX, int CPT>
-void launch_select_t(spid_ctx* c, hipStream_t s) {
-  const Plan& p = c->plan;
-  hipLaunchKernelGGL((select_kernel<TY, LMAX, CPT>), dim3(c->desc.nblocks), dim3(p.sh.sel_thr), 0,
-                     s, c->at<BlkInfo>(p.off_blk), c->desc.l, c->desc.k_max, c->desc.tol,
-                     c->desc.rank_floor, c->at<TY>(p.off_Y), c->at<double>(p.off_R),
-                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), c->at<int32_t>(p.off_st));
-}
+// One selection launch: a block table (blocks, or temporal windows of blocks),
+// the sketch it points into and where R, S, k and the status go.
+template <typename TY>
+struct SelJob {
+  const BlkInfo* blks;
+  int nblocks, l, k_max;
+  double tol, rank_floor;
+  const TY* Y;
+  double* W;           // working copy of the global-memory kernel (same offsets as Y)
+  double* R;
+  int32_t *S, *k, *st;
+  SelShape sh;
+};
 
 template <typename TY, int LMAX>
-void launch_select_l(spid_ctx* c, hipStream_t s) {
-  launch_select_t<TY, LMAX, 1>(c, s);
+void launch_select_l(const SelJob<TY>& j, hipStream_t s) {
+  hipLaunchKernelGGL((select_kernel<TY, LMAX, 1>), dim3(j.nblocks), dim3(j.sh.sel_thr), 0, s,
+                     j.blks, j.l, j.k_max, j.tol, j.rank_floor, j.Y, j.R, j.S, j.k, j.st);
 }
 
 template <typename TY, int RR, int MAXTHR>
-void launch_select_hybrid_t(spid_ctx* c, hipStream_t s) {
-  const Plan& p = c->plan;
-  static bool lds_set = false;   // one attribute call per instantiation and process
-  if (!lds_set && p.sh.sel_lds > 65536) {
-    if (hipFuncSetAttribute((const void*)select_hybrid_kernel<TY, RR, MAXTHR>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) != hipSuccess)
-      return;   // the launch below then fails and is reported
-    lds_set = true;
-  }
-  hipLaunchKernelGGL((select_hybrid_kernel<TY, RR, MAXTHR>), dim3(c->desc.nblocks),
-                     dim3(p.sh.sel_thr), p.sh.sel_lds, s, c->at<BlkInfo>(p.off_blk), c->desc.l,
-                     c->desc.k_max, c->desc.tol, c->desc.rank_floor, c->at<TY>(p.off_Y),
-                     c->at<double>(p.off_R), c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
-                     c->at<int32_t>(p.off_st));
+bool launch_select_hybrid_t(const SelJob<TY>& j, hipStream_t s) {
+  auto kern = select_hybrid_kernel<TY, RR, MAXTHR>;
+  if (!allow_lds((const void*)kern, j.sh.sel_lds)) return false;
+  hipLaunchKernelGGL(kern, dim3(j.nblocks), dim3(j.sh.sel_thr), j.sh.sel_lds, s, j.blks, j.l,
+                     j.k_max, j.tol, j.rank_floor, j.Y, j.R, j.S, j.k, j.st);
+  return true;
 }
 
 template <typename TY, int RPT>
-void launch_select_pair_t(spid_ctx* c, hipStream_t s) {
-  const Plan& p = c->plan;
-  hipLaunchKernelGGL((select_pair_kernel<TY, RPT>), dim3(c->desc.nblocks), dim3(p.sh.sel_thr), 0,
-                     s, c->at<BlkInfo>(p.off_blk), c->desc.l, c->desc.k_max, c->desc.tol,
-                     c->desc.rank_floor, c->at<TY>(p.off_Y), c->at<double>(p.off_R),
-                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), c->at<int32_t>(p.off_st));
+void launch_select_pair_t(const SelJob<TY>& j, hipStream_t s) {
+  hipLaunchKernelGGL((select_pair_kernel<TY, RPT>), dim3(j.nblocks), dim3(j.sh.sel_thr), 0, s,
+                     j.blks, j.l, j.k_max, j.tol, j.rank_floor, j.Y, j.R, j.S, j.k, j.st);
 }
 
 template <typename TY>
-void launch_select_y(spid_ctx* c, hipStream_t s) {
-  const Shape& sh = c->plan.sh;
+bool launch_select_job(const SelJob<TY>& j, hipStream_t s) {
+  const SelShape& sh = j.sh;
+  if (sh.sel_tall) {
+    if constexpr (std::is_same<TY, double>::value) {
+      auto launch = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(j.nblocks), dim3(kTallThreads), 0, s, j.blks, j.l,
+                           j.k_max, j.tol, j.rank_floor, j.Y, j.W, j.R, j.S, j.k, j.st);
+      };
+      if (j.l <= 4 * kWave) launch(select_tall_kernel<4>);
+      else if (j.l <= 8 * kWave) launch(select_tall_kernel<8>);
+      else if (j.l <= 16 * kWave) launch(select_tall_kernel<16>);
+      else launch(select_tall_kernel<0>);
+      return true;
+    }
+    return false;   // tall sketches are double precision
+  }
   if (sh.sel_pair) {
-    if (sh.sel_pair == 32) launch_select_pair_t<TY, 32>(c, s);
-    else if (sh.sel_pair == 48) launch_select_pair_t<TY, 48>(c, s);
-    else launch_select_pair_t<TY, 64>(c, s);
-    return;
+    if (sh.sel_pair == 32) launch_select_pair_t<TY, 32>(j, s);
+    else if (sh.sel_pair == 48) launch_select_pair_t<TY, 48>(j, s);
+    else launch_select_pair_t<TY, 64>(j, s);
+    return true;
   }
   if (sh.sel_rr) {
     if (sh.sel_thr > 512) {
-      if (sh.sel_rr == 32) launch_select_hybrid_t<TY, 32, 1024>(c, s);
-      else launch_select_hybrid_t<TY, 16, 1024>(c, s);
-    } else {
-      if (sh.sel_rr == 48) launch_select_hybrid_t<TY, 48, 512>(c, s);
-      else if (sh.sel_rr == 32) launch_select_hybrid_t<TY, 32, 512>(c, s);
-      else launch_select_hybrid_t<TY, 16, 512>(c, s);
+      if (sh.sel_rr == 32) return launch_select_hybrid_t<TY, 32, 1024>(j, s);
+      return launch_select_hybrid_t<TY, 16, 1024>(j, s);
     }
-    return;
+    if (sh.sel_rr == 48) return launch_select_hybrid_t<TY, 48, 512>(j, s);
+    if (sh.sel_rr == 32) return launch_select_hybrid_t<TY, 32, 512>(j, s);
+    return launch_select_hybrid_t<TY, 16, 512>(j, s);
   }
-  switch (c->plan.sh.LMAX) {
-    case 16: launch_select_l<TY, 16>(c, s); break;
-    case 32: launch_select_l<TY, 32>(c, s); break;
-    case 48: launch_select_l<TY, 48>(c, s); break;
-    default: launch_select_l<TY, 56>(c, s); break;
+  switch (sh.LMAX) {
+    case 16: launch_select_l<TY, 16>(j, s); break;
+    case 32: launch_select_l<TY, 32>(j, s); break;
+    case 48: launch_select_l<TY, 48>(j, s); break;
+    default: launch_select_l<TY, 56>(j, s); break;
   }
+  return true;
+}
+
+template <typename TY>
+bool launch_select_ctx(spid_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
+  SelJob<TY> j{c->at<BlkInfo>(p.off_blk), c->desc.nblocks, c->desc.l, c->desc.k_max,
+               c->desc.tol, c->desc.rank_floor, c->at<TY>(p.off_Y), c->at<double>(p.off_W),
+               c->at<double>(p.off_R), c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
+               c->at<int32_t>(p.off_st), p.sh.sel};
+  return launch_select_job<TY>(j, s);
 }
 
 // ---- reconstruction dispatch (matrix-core kernels)
@@ -871,6 +975,12 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
   if (e == hipSuccess && p.coarse)
     e = hipMemcpy(c->ws + p.off_grid, p.grid.data(), sizeof(GridInfo) * p.grid.size(),
                   hipMemcpyHostToDevice);
+  if (e == hipSuccess && p.ts_nwin > 0)
+    e = hipMemcpy(c->ws + p.off_tswin, p.ts_win.data(), sizeof(BlkInfo) * p.ts_win.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && p.ts_nwin > 0)
+    e = hipMemcpy(c->ws + p.off_tsblk2, p.ts_blk2.data(), sizeof(BlkInfo) * p.ts_blk2.size(),
+                  hipMemcpyHostToDevice);
 
   if (e != hipSuccess) {
     delete c;
@@ -1005,24 +1115,9 @@ extern "C" spid_status spid_select(spid_ctx* c, int32_t* d_k, int32_t* d_S, int3
     if (!c->covered[j])
       return fail(SPID_ESTATE, "spid_select: sketch column %d has not been computed", j);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (c->plan.sh.sel_tall) {
-    auto launch = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3(c->desc.nblocks), dim3(kTallThreads), 0, s,
-                         c->at<BlkInfo>(c->plan.off_blk), c->desc.l, c->desc.k_max, c->desc.tol,
-                         c->desc.rank_floor, c->at<double>(c->plan.off_Y),
-                         c->at<double>(c->plan.off_W), c->at<double>(c->plan.off_R),
-                         c->at<int32_t>(c->plan.off_S), c->at<int32_t>(c->plan.off_k),
-                         c->at<int32_t>(c->plan.off_st));
-    };
-    const int l = c->desc.l;
-    if (l <= 4 * kWave) launch(select_tall_kernel<4>);
-    else if (l <= 8 * kWave) launch(select_tall_kernel<8>);
-    else if (l <= 16 * kWave) launch(select_tall_kernel<16>);
-    else launch(select_tall_kernel<0>);
-  } else if (c->plan.ydt == 0)
-    launch_select_y<double>(c, s);
-  else
-    launch_select_y<float>(c, s);
+  const bool ok = c->plan.ydt == 0 ? launch_select_ctx<double>(c, s)
+                                    : launch_select_ctx<float>(c, s);
+  if (!ok) return fail(SPID_EHIP, "select: cannot reserve the selection LDS");
   spid_status st = hip_check("select kernel launch");
   if (st != SPID_OK) return st;
   if (d_k || d_S || d_status) {
@@ -1124,6 +1219,112 @@ bool launch_interp_a(spid_ctx* c, const double* P, void* cskel, hipStream_t s) {
 }
 
 }  // namespace
+
+namespace {
+
+template <int KMAX>
+bool launch_coeffs_job(const BlkInfo* blks, int nblocks, int l, int k_max, const double* R,
+                       const int32_t* S, const int32_t* k, double* P, hipStream_t s) {
+  const size_t lds = sizeof(double) * (size_t)k_max * k_max;
+  if (!allow_lds((const void*)coeffs_kernel<KMAX>, lds)) return false;
+  hipLaunchKernelGGL((coeffs_kernel<KMAX>), dim3(nblocks), dim3(kCoThreads), lds, s, blks, l,
+                     k_max, R, S, k, P, (__bf16*)nullptr, 32, (int32_t*)nullptr,
+                     (int32_t*)nullptr);
+  return true;
+}
+
+bool launch_coeffs_any(int kmax_t, const BlkInfo* blks, int nblocks, int l, int k_max,
+                       const double* R, const int32_t* S, const int32_t* k, double* P,
+                       hipStream_t s) {
+  switch (kmax_t) {
+    case 8: return launch_coeffs_job<8>(blks, nblocks, l, k_max, R, S, k, P, s);
+    case 16: return launch_coeffs_job<16>(blks, nblocks, l, k_max, R, S, k, P, s);
+    case 32: return launch_coeffs_job<32>(blks, nblocks, l, k_max, R, S, k, P, s);
+    case 48: return launch_coeffs_job<48>(blks, nblocks, l, k_max, R, S, k, P, s);
+    case 64: return launch_coeffs_job<64>(blks, nblocks, l, k_max, R, S, k, P, s);
+    default: return launch_coeffs_job<96>(blks, nblocks, l, k_max, R, S, k, P, s);
+  }
+}
+
+template <typename TY>
+spid_status two_stage_t(spid_ctx* c, double* d_P, hipStream_t s) {
+  const Plan& p = c->plan;
+  const spid_desc& d = c->desc;
+  const int nb = d.nblocks, nw = p.ts_nwin, k1 = p.ts_k1;
+  const BlkInfo* win = c->at<BlkInfo>(p.off_tswin);
+  const BlkInfo* blk2 = c->at<BlkInfo>(p.off_tsblk2);
+  // stage 1: rank-k1 ID of every window
+  SelJob<TY> j1{win, nb * nw, d.l, k1, 0.0, d.rank_floor, c->at<TY>(p.off_Y),
+                c->at<double>(p.off_W), c->at<double>(p.off_tsR1), c->at<int32_t>(p.off_tsS1),
+                c->at<int32_t>(p.off_tsk1), c->at<int32_t>(p.off_tsst1), p.ts_sel1};
+  if (!launch_select_job<TY>(j1, s)) return fail(SPID_EHIP, "two-stage: stage-1 selection");
+  spid_status st = hip_check("two-stage stage-1 selection launch");
+  if (st != SPID_OK) return st;
+  if (!launch_coeffs_any(p.ts_kmax1, win, nb * nw, d.l, k1, c->at<double>(p.off_tsR1),
+                         c->at<int32_t>(p.off_tsS1), c->at<int32_t>(p.off_tsk1),
+                         c->at<double>(p.off_tsP1), s))
+    return fail(SPID_EHIP, "two-stage: stage-1 coefficients");
+  st = hip_check("two-stage stage-1 coefficients launch");
+  if (st != SPID_OK) return st;
+  // stage 2: the sketch of the concatenated skeletons, gathered from the resident sketch
+  const int64_t per_blk = (int64_t)nw * k1 * d.l;
+  dim3 grid((unsigned)std::min<int64_t>((per_blk + 255) / 256, 1 << 20),
+            (unsigned)std::min(nb, 65535));
+  hipLaunchKernelGGL((ts_gather_kernel<TY>), grid, dim3(256), 0, s, win, blk2, nb, nw, k1, d.l,
+                     c->at<int32_t>(p.off_tsS1), c->at<int32_t>(p.off_tsk1), c->at<TY>(p.off_Y),
+                     c->at<TY>(p.off_tsY2));
+  st = hip_check("two-stage gather launch");
+  if (st != SPID_OK) return st;
+  SelJob<TY> j2{blk2, nb, d.l, d.k_max, d.tol, d.rank_floor, c->at<TY>(p.off_tsY2),
+                c->at<double>(p.off_tsW2), c->at<double>(p.off_tsR2), c->at<int32_t>(p.off_tsS2),
+                c->at<int32_t>(p.off_tsk2), c->at<int32_t>(p.off_tsst2), p.ts_sel2};
+  if (!launch_select_job<TY>(j2, s)) return fail(SPID_EHIP, "two-stage: stage-2 selection");
+  st = hip_check("two-stage stage-2 selection launch");
+  if (st != SPID_OK) return st;
+  if (!launch_coeffs_any(p.sh.KMAX, blk2, nb, d.l, d.k_max, c->at<double>(p.off_tsR2),
+                         c->at<int32_t>(p.off_tsS2), c->at<int32_t>(p.off_tsk2),
+                         c->at<double>(p.off_tsP2), s))
+    return fail(SPID_EHIP, "two-stage: stage-2 coefficients");
+  st = hip_check("two-stage stage-2 coefficients launch");
+  if (st != SPID_OK) return st;
+  hipLaunchKernelGGL(ts_combine_kernel, dim3(nb), dim3(256), 0, s, c->at<BlkInfo>(p.off_blk), win,
+                     blk2, nw, k1, d.k_max, c->at<int32_t>(p.off_tsS1),
+                     c->at<int32_t>(p.off_tsk1), c->at<int32_t>(p.off_tsst1),
+                     c->at<double>(p.off_tsP1), c->at<int32_t>(p.off_tsS2),
+                     c->at<int32_t>(p.off_tsk2), c->at<int32_t>(p.off_tsst2),
+                     c->at<double>(p.off_tsP2), d_P, c->at<int32_t>(p.off_S),
+                     c->at<int32_t>(p.off_k), c->at<int32_t>(p.off_st));
+  return hip_check("two-stage combine launch");
+}
+
+}  // namespace
+
+extern "C" spid_status spid_select_two_stage(spid_ctx* c, int32_t* d_k, int32_t* d_S,
+                                             int32_t* d_status, double* d_P, void* stream) {
+  if (!c || !d_P) return fail(SPID_EINVAL, "NULL argument to spid_select_two_stage");
+  if (c->plan.ts_nwin < 1)
+    return fail(SPID_EINVAL, "spid_select_two_stage: the descriptor has no ts_windows");
+  for (int j = 0; j < c->plan.max_n; ++j)
+    if (!c->covered[j])
+      return fail(SPID_ESTATE, "spid_select_two_stage: sketch column %d has not been computed", j);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  spid_status st = c->plan.ydt == 0 ? two_stage_t<double>(c, d_P, s) : two_stage_t<float>(c, d_P, s);
+  if (st != SPID_OK) return st;
+  if (d_k || d_S || d_status) {
+    const int64_t tot = std::max<int64_t>((int64_t)c->desc.nblocks * c->desc.k_max,
+                                          c->desc.nblocks);
+    hipLaunchKernelGGL(select_export_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       c->desc.nblocks, c->desc.k_max, c->at<int32_t>(c->plan.off_S),
+                       c->at<int32_t>(c->plan.off_k), c->at<int32_t>(c->plan.off_st), d_k, d_S,
+                       d_status);
+    st = hip_check("select export launch");
+    if (st != SPID_OK) return st;
+  }
+  // the final selection and coefficients are in place: the error pass may follow
+  c->selected = true;
+  c->coeffs_done = true;
+  return SPID_OK;
+}
 
 extern "C" spid_status spid_reconstruct_interp(spid_ctx* c, const double* d_P, double* d_err2,
                                                double* d_nrm2, void* d_coarse_skeleton,

@@ -172,3 +172,18 @@ def test_coarse_grid_descriptor_validation():
     assert sp.spid_workspace_bytes(tall) >= 2 * 648 * 64 * 8
     gauss = sp.make_desc([12288], [64], 648, 8)
     assert sp.spid_workspace_bytes(gauss) == 0
+
+
+def test_two_stage_descriptor_validation():
+    import paper_2103_01380_amd as sp
+    ok = sp.make_desc([3000], [64], 24, 16, tol=1e-5, ts_windows=4, ts_k1=8)
+    assert sp.spid_workspace_bytes(ok) > sp.spid_workspace_bytes(sp.make_desc([3000], [64], 24, 16, tol=1e-5))
+    too_many = sp.make_desc([3000], [64], 24, 16, tol=1e-5, ts_windows=65, ts_k1=1)
+    assert sp.spid_workspace_bytes(too_many) == 0 and "windows exceed" in sp.spid_last_error()
+    wide = sp.make_desc([3000], [1024], 24, 16, tol=1e-5, ts_windows=64, ts_k1=32)
+    assert sp.spid_workspace_bytes(wide) == 0 and "1024" in sp.spid_last_error()
+    no_k1 = sp.make_desc([3000], [64], 24, 16, tol=1e-5, ts_windows=4, ts_k1=0)
+    assert sp.spid_workspace_bytes(no_k1) == 0 and "ts_k1" in sp.spid_last_error()
+    mixed = sp.make_desc([3000], [64], 24, 16, tol=1e-5, a_dtype=sp.A_F32, prec=sp.SK_BF16,
+                         ts_windows=4, ts_k1=8)
+    assert sp.spid_workspace_bytes(mixed) == 0 and "split-bfloat16" in sp.spid_last_error()

@@ -1,0 +1,138 @@
+"""GPU parity of the modified two-stage ID (Section 3.4.2) against the oracle,
+through the C ABI: stage-1 rank-k1 IDs of temporal windows, stage-2 tolerance
+ID of the concatenated skeletons (sketch gathered on the GPU), final pivots
+I_U(I_1) and coefficients C^1 C^{0'}, then the error pass.
+
+Pivots follow the gap rule on the stage-2 gaps (FP64, 1e-10); coefficients
+and errors match to FP64 rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _harness import matched_prefix
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _blocks(shapes, seed, rank=10, decay=0.25, noise=1e-8):
+    rng = np.random.default_rng(seed)
+    out = []
+    for m, n in shapes:
+        t = np.linspace(0.0, 1.0, n)
+        U = rng.standard_normal((m, rank))
+        V = np.stack([np.cos((q + 1) * 3.0 * t + q) * 10.0 ** (-decay * q) for q in range(rank)])
+        out.append(np.asfortranarray(U @ V + noise * rng.standard_normal((m, n))))
+    return out
+
+
+def _gpu_two_stage(blocks, l, k_max, seed, nwin, k1, tol, grids=None):
+    import paper_2103_01380_amd as sp
+    m = np.array([b.shape[0] for b in blocks], dtype=np.int64)
+    n = np.array([b.shape[1] for b in blocks], dtype=np.int32)
+    off = np.zeros(len(blocks), dtype=np.int64)
+    off[1:] = np.cumsum((m * n)[:-1])
+    flat = np.concatenate([b.T.ravel() for b in blocks])
+    A = torch.from_numpy(flat).cuda()
+    ctx = sp.SPID(m, n, l, k_max, tol=tol, seed=seed, prec="subsample" if grids else "f64",
+                  grids=grids, ts_windows=nwin, ts_k1=k1)
+    ctx.bind(A, offsets=off)
+    ctx.sketch_update()
+    ctx.select_two_stage()
+    ctx.reconstruct()
+    torch.cuda.synchronize()
+    out = dict(S=ctx.S.cpu().numpy(), k=ctx.k.cpu().numpy(), st=ctx.status.cpu().numpy(),
+               P=[ctx.block_P(b) for b in range(len(blocks))], err2=ctx.err2.cpu().numpy(),
+               nrm2=ctx.nrm2.cpu().numpy())
+    ctx.close()
+    return out
+
+
+def _oracle_two_stage(blocks, l, k_max, seed, nwin, k1, tol, grids=None):
+    res = []
+    for b, A in enumerate(blocks):
+        Y = oracle.subsample(A, grids[b]) if grids else oracle.sketch(A, l, seed)
+        ts = oracle.two_stage(Y, nwin, k1, k_max, tol)
+        e2, a2 = oracle.reconstruct(A, ts.S, ts.k, ts.P)
+        res.append((ts, e2, a2))
+    return res
+
+
+def _compare(g, o):
+    full = 0
+    for b, (ts, e2, a2) in enumerate(o):
+        s_star, ok = matched_prefix(g["S"][b], ts.S, ts.gaps, g["k"][b], ts.k, 1e-10)
+        assert ok, (b, g["S"][b][:s_star], ts.S[:s_star])
+        kg = int(g["k"][b])
+        assert np.array_equal(g["P"][b][:kg][:, g["S"][b][:kg]], np.eye(kg)), b
+        assert np.all(g["P"][b][kg:] == 0.0)
+        if s_star == ts.k and kg == ts.k:
+            full += 1
+            assert g["st"][b] == ts.status
+            Pg, Po = g["P"][b][:kg], ts.P[:kg]
+            assert np.abs(Pg - Po).max() <= 1e-9 * max(1.0, np.abs(Po).max()), b
+        eg = math.sqrt(g["err2"][b] / g["nrm2"][b])
+        eo = math.sqrt(e2 / a2)
+        assert abs(eg - eo) <= 1e-12 + 1e-9 * eo, (b, eg, eo)
+        assert abs(g["nrm2"][b] - a2) <= 1e-13 * a2
+    return full
+
+
+@pytest.mark.parametrize("nwin,k1", [(4, 8), (1, 12), (8, 4)])
+def test_two_stage_gaussian_f64(nwin, k1):
+    shapes = [(3000, 64)] * 6 + [(1500, 96)] * 2
+    blocks = _blocks(shapes, 1)
+    print("case: two-stage", nwin, k1, flush=True)
+    g = _gpu_two_stage(blocks, 24, 16, 7, nwin, k1, 1e-5)
+    o = _oracle_two_stage(blocks, 24, 16, 7, nwin, k1, 1e-5)
+    assert _compare(g, o) >= 1
+
+
+def test_two_stage_uneven_windows_and_fixed_stage2_rank():
+    shapes = [(2000, 37), (900, 53), (1200, 40)]
+    blocks = _blocks(shapes, 2, rank=8)
+    print("case: two-stage uneven", flush=True)
+    g = _gpu_two_stage(blocks, 20, 6, 3, 5, 4, 0.0)
+    o = _oracle_two_stage(blocks, 20, 6, 3, 5, 4, 0.0)
+    _compare(g, o)
+    assert np.all(g["k"] == 6)
+
+
+def test_two_stage_on_a_tall_coarse_grid():
+    grids = [(16, 16, 16, 3, 3, 3, 3)] * 3          # 648 coarse rows: global-memory selection
+    rng = np.random.default_rng(4)
+    blocks = []
+    for g in grids:
+        m = 16 ** 3 * 3
+        t = np.linspace(0.0, 1.0, 120)
+        U = np.stack([np.sin((q + 1) * np.linspace(0, 3, m) + q) for q in range(6)], axis=1)
+        V = np.stack([np.exp(-(q + 1) * t) * 0.5 ** q for q in range(6)])
+        blocks.append(np.asfortranarray(U @ V + 1e-9 * rng.standard_normal((m, 120))))
+    print("case: two-stage coarse", flush=True)
+    g = _gpu_two_stage(blocks, 648, 12, 0, 6, 5, 1e-7, grids=grids)
+    o = _oracle_two_stage(blocks, 648, 12, 0, 6, 5, 1e-7, grids=grids)
+    _compare(g, o)
+
+
+def test_two_stage_state_and_argument_errors():
+    import paper_2103_01380_amd as sp
+    ctx = sp.SPID([100], [10], 4, 2)
+    P = torch.zeros(20, dtype=torch.float64, device="cuda")
+    with pytest.raises(sp.SpidError) as e:
+        sp.spid_select_two_stage(ctx.ctx, P)
+    assert e.value.status == sp.SPID_EINVAL
+    ctx.close()
+    ctx = sp.SPID([100], [10], 4, 2, ts_windows=2, ts_k1=2)
+    with pytest.raises(sp.SpidError) as e:
+        ctx.select_two_stage()
+    assert e.value.status == sp.SPID_ESTATE
+    ctx.close()
