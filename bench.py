@@ -78,7 +78,7 @@ def main():
     stream = torch.cuda.current_stream()
     tuning = None
     coarse = w.subsample > 0
-    if not args.no_autotune and not coarse:
+    if not args.no_autotune and not coarse and not w.ts_windows:
         from paper_2103_01380_amd import autotune as at
         t0 = time.time()
         tuning = at.autotune(A, m, n, w.l, w.k_max, offsets=off, tol=w.tol, seed=w.omega_seed,
@@ -88,7 +88,7 @@ def main():
         log(args, f"launch shapes {tuning} ({time.time() - t0:.1f}s)")
     ctx = sp.SPID(m, n, w.l, w.k_max, tol=w.tol, seed=w.omega_seed,
                   a_dtype=w.a_dtype, prec=w.prec, lp_terms=w.lp_terms, device=dev, tuning=tuning,
-                  grids=w.grids() if coarse else None)
+                  grids=w.grids() if coarse else None, ts_windows=w.ts_windows, ts_k1=w.ts_k1)
     ctx.bind(A, offsets=off)
     ms_step, stage, wall = time_steps(args, ctx, w, stream)
     graph_ms = None
@@ -163,7 +163,9 @@ def main():
                    "tol": w.tol, "sketch_update": "one snapshot per call" if w.stream
                    else "all snapshots in one call",
                    "sketch": (f"coarse grid, every {w.subsample}th point; error of M B(:,S) C"
-                              if coarse else "Gaussian, " + w.prec)},
+                              if coarse else "Gaussian, " + w.prec),
+                   "two_stage": ({"windows": w.ts_windows, "k1": w.ts_k1}
+                                 if w.ts_windows else None)},
         "rel_error": rel_err,
         "error_gate_1e-3": bool(rel_err <= 1e-3),
         "compression_factor": round(cf, 3),
@@ -202,10 +204,15 @@ def time_steps(args, ctx, w, stream):
             ctx.sketch_update(stream=stream)
         if ev is not None:
             ev[1].record(stream)
-        ctx.select(stream)
+        if w.ts_windows:
+            # both stages, pivots and coefficients in one call (reported as "select")
+            ctx.select_two_stage(stream)
+        else:
+            ctx.select(stream)
         if ev is not None:
             ev[2].record(stream)
-        ctx.coeffs(stream)
+        if not w.ts_windows:
+            ctx.coeffs(stream)
         if ev is not None:
             ev[3].record(stream)
         if w.subsample:
@@ -255,6 +262,14 @@ def stage_work(w, m, n, kk, nbytes, ctx=None):
     sk_flops = 2.0 * w.l * float((m * n64).sum())
     sel_flops = float((4.0 * w.l * k64 * (n64 - (k64 - 1) / 2.0)).sum())
     co_flops = float((k64 * k64 * (n64 - k64)).sum())
+    if w.ts_windows:
+        # stage 1 on every window at rank k1, stage 2 on nwin * k1 columns, and C^1 C^{0'}
+        nw, k1 = w.ts_windows, w.ts_k1
+        n2 = nw * k1
+        sel_flops = float((nw * 4.0 * w.l * k1 * (n64 / nw - (k1 - 1) / 2.0)
+                           + 4.0 * w.l * k64 * (n2 - (k64 - 1) / 2.0)).sum())
+        co_flops = float((nw * k1 * k1 * (n64 / nw - k1) + k64 * k64 * (n2 - k64)
+                          + 2.0 * k64 * k1 * n64).sum())
     rc_flops = 2.0 * float((m * (n64 - k64) * k64).sum())
     sk_peak = PEAK_TFLOPS["f64" if w.prec == "f64" else w.prec]
     rc_peak = PEAK_TFLOPS["f64" if (w.a_dtype == "f64" or w.prec == "f64") else "bf16"]
@@ -388,12 +403,32 @@ def cpu_baseline(args, w, A, m, n, off, ctx):
             "subsample": oracle.OMEGA_F64}
     grids = w.grids() if w.subsample else None
 
+    def two_stage_batch(blocks):
+        # sketch, both stages and the error per block, one block per thread
+        from concurrent.futures import ThreadPoolExecutor
+
+        def one(Ab):
+            Y = oracle.sketch(Ab, w.l, w.omega_seed, prec=prec[w.prec])
+            ts = oracle.two_stage(Y, w.ts_windows, w.ts_k1, w.k_max, w.tol)
+            e2, a2 = oracle.reconstruct(Ab, ts.S, ts.k, ts.P)
+            return Y, ts, e2, a2
+        with ThreadPoolExecutor(threads) as ex:
+            out = list(ex.map(one, blocks))
+        return oracle.BatchResult([o[0] for o in out], np.stack([o[1].S for o in out]),
+                                  np.array([o[1].k for o in out]),
+                                  np.array([o[1].status for o in out]),
+                                  [o[1].P for o in out], np.stack([o[1].gaps for o in out]),
+                                  np.array([o[2] for o in out]), np.array([o[3] for o in out]))
+
     def run(idx):
         blocks = [si.block_view(A, m, n, off, int(b)) for b in idx]
         t0 = time.perf_counter()
-        res = oracle.run_batch(blocks, l=w.l, k_max=w.k_max, seed=w.omega_seed, tol=w.tol,
-                               prec=prec[w.prec], nthreads=threads,
-                               grids=None if grids is None else grids[idx])
+        if w.ts_windows:
+            res = two_stage_batch(blocks)
+        else:
+            res = oracle.run_batch(blocks, l=w.l, k_max=w.k_max, seed=w.omega_seed, tol=w.tol,
+                                   prec=prec[w.prec], nthreads=threads,
+                                   grids=None if grids is None else grids[idx])
         dt = time.perf_counter() - t0
         return dt, int(sum(b.shape[0] * b.shape[1] for b in blocks)) * w.elem_bytes, res
 

@@ -54,6 +54,8 @@ class Workload:
     omega_seed: int = 0
     nblocks_uneven: int = 0       # lowrank
     subsample: int = 0            # > 0: coarse-grid sketch, every s-th point per direction
+    ts_windows: int = 0           # > 0: modified two-stage ID with this many temporal windows
+    ts_k1: int = 0                # two-stage: stage-1 rank per window
     extra: dict = field(default_factory=dict)
 
     @property
@@ -143,6 +145,15 @@ WORKLOADS = {
                     "every 3rd point (648 rows), tolerance 1e-8 with k<=32, single-pass error",
         kind="tgv", N=128, B=8, n=256, fields=3, nu=0.005, T=10.0, noise=1e-6, a_dtype="f64",
         l=648, k_max=32, tol=1e-8, prec="subsample", subsample=3, data_seed=2002),
+    # the 512-block TGV data compressed by the modified two-stage ID (Section 3.4.2):
+    # 8 windows of 32 snapshots at rank 16, then a tolerance ID of the 128 window skeletons
+    "tgv128_b512_f64_2stage": Workload(
+        name="tgv128_b512_f64_2stage",
+        description="as tgv128_b512_f64, modified two-stage ID: 8 temporal windows of 32 "
+                    "snapshots at rank 16, stage 2 with tolerance 1e-8 and k<=32, l=42",
+        kind="tgv", N=128, B=8, n=256, fields=3, nu=0.005, T=10.0, noise=1e-6, a_dtype="f64",
+        l=42, k_max=32, tol=1e-8, prec="f64", data_seed=2002, omega_seed=1002,
+        ts_windows=8, ts_k1=16),
     "tgv128_b512_sub7": Workload(
         name="tgv128_b512_sub7",
         description="as tgv128_b512_sub3 with every 7th point (3*3^3=81 coarse rows)",
