@@ -45,6 +45,11 @@ def parse():
                     help="JSON table of tuned shapes (default: the package's table)")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip timing the plain FP64 path on a mixed-precision workload")
+    ap.add_argument("--insitu", action="store_true",
+                    help="measure the in-situ overhead instead: a stand-in solver produces the "
+                         "snapshots on one stream, the sketch updates run on another")
+    ap.add_argument("--solver-substeps", type=int, default=1,
+                    help="--insitu: solver steps per stored snapshot")
     return ap.parse_args()
 
 
@@ -66,6 +71,9 @@ def main():
 
     w = si.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
+    if args.insitu:
+        insitu(args, w, dev)
+        return
     t0 = time.time()
     def progress(f, j):
         if j == 0 or j == w.n - 1:
@@ -185,6 +193,116 @@ def main():
 
 
 STAGES = ("sketch", "select", "coeffs", "reconstruct")
+
+
+def insitu(args, w, dev):
+    """In-situ compression (Sections 3.3-3.4, Algorithms 4-5): a stand-in solver
+    advances the velocity field one step at a time and stores each snapshot into
+    the resident data matrix (the store task); the sketch update of that snapshot
+    runs on a second stream behind an event, so it overlaps the next solver step.
+    The overhead is the extra wall time over the solver alone; the selection,
+    coefficients and error pass run once after the last step.
+
+    Stand-in solver: linear advection-diffusion of the three velocity components
+    of the Taylor-Green field on the periodic N^3 grid, second-order central
+    differences, explicit Euler (torch element-wise operations: the application,
+    not the compression path)."""
+    import torch
+    import paper_2103_01380_amd as sp
+    assert w.kind == "tgv" and not w.subsample and not w.ts_windows
+    N, B = w.N, w.B
+    E = N // B
+    nb = B ** 3
+    h = 2.0 * math.pi / N
+    g = torch.arange(N, device=dev, dtype=torch.float64) * h
+    Z, Yc, X = torch.meshgrid(g, g, g, indexing="ij")            # [z, y, x], x fastest
+    F0 = torch.stack([torch.sin(X) * torch.cos(Yc) * torch.cos(Z),
+                      -torch.cos(X) * torch.sin(Yc) * torch.cos(Z),
+                      torch.zeros_like(X)])
+    vel = (1.0, 0.5, 0.25)                                      # advecting velocity (x, y, z)
+    dt = 0.2 * h
+    nu = w.nu
+
+    def solver_step(F):
+        lap = -6.0 * F
+        adv = torch.zeros_like(F)
+        for d, c in zip((3, 2, 1), vel):                         # x, y, z axes of [f, z, y, x]
+            fp = torch.roll(F, -1, d)
+            fm = torch.roll(F, 1, d)
+            lap += fp + fm
+            adv += (c / (2.0 * h)) * (fp - fm)
+        F += dt * (nu / (h * h) * lap - adv)
+
+    A = torch.empty((nb, w.n, 3 * E ** 3), dtype=torch.float64, device=dev)
+
+    def store(F, j):
+        V = F.reshape(3, B, E, B, E, B, E).permute(1, 3, 5, 0, 2, 4, 6)   # bz, by, bx, f, z, y, x
+        A[:, j, :] = V.reshape(nb, 3 * E ** 3)
+
+    m = np.full(nb, 3 * E ** 3, dtype=np.int64)
+    n = np.full(nb, w.n, dtype=np.int32)
+    ctx = sp.SPID(m, n, w.l, w.k_max, tol=w.tol, seed=w.omega_seed, device=dev)
+    ctx.bind(A)
+    prod = torch.cuda.current_stream()
+    sk = torch.cuda.Stream()
+
+    def run(mode):
+        F = F0.clone()
+        evs = [torch.cuda.Event() for _ in range(w.n)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(w.n):
+            for _ in range(args.solver_substeps):
+                solver_step(F)
+            store(F, j)
+            if mode == "overlap":
+                evs[j].record(prod)
+                sk.wait_event(evs[j])
+                ctx.sketch_update(j, 1, stream=sk)
+            elif mode == "serial":
+                ctx.sketch_update(j, 1, stream=prod)
+        torch.cuda.synchronize()
+        t_loop = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        if mode != "solver":
+            s = sk if mode == "overlap" else prod
+            ctx.select(s)
+            ctx.coeffs(s)
+            ctx.reconstruct(stream=s)
+            torch.cuda.synchronize()
+        return t_loop, time.perf_counter() - t1
+
+    run("overlap")                                               # warm-up (compiles, caches)
+    reps = max(1, args.steps // 5)
+    t = {}
+    for mode in ("solver", "overlap", "serial"):
+        best = None
+        for _ in range(reps):
+            r = run(mode)
+            best = r if best is None or r[0] < best[0] else best
+        t[mode] = best
+        log(args, f"in-situ {mode}: loop {best[0] * 1e3:.2f} ms, after-loop {best[1] * 1e3:.2f} ms")
+    over = (t["overlap"][0] / t["solver"][0] - 1.0) * 100.0
+    rel = ctx.rel_error()
+    kk = ctx.k.cpu().numpy()
+    out = {
+        "metric": "in-situ overhead of the per-snapshot sketch updates over the stand-in solver",
+        "value": round(over, 2), "unit": "%", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name + "_insitu", "snapshots": w.n, "nblocks": nb,
+                   "solver": f"advection-diffusion, {N}^3 x 3 fields, central differences, "
+                             f"explicit Euler, {args.solver_substeps} step(s) per snapshot",
+                   "l": w.l, "k_max": w.k_max, "tol": w.tol},
+        "solver_ms": round(t["solver"][0] * 1e3, 3),
+        "solver_plus_sketch_overlapped_ms": round(t["overlap"][0] * 1e3, 3),
+        "solver_plus_sketch_serial_ms": round(t["serial"][0] * 1e3, 3),
+        "serial_overhead_pct": round((t["serial"][0] / t["solver"][0] - 1.0) * 100.0, 2),
+        "after_last_step_ms": round(t["overlap"][1] * 1e3, 3),
+        "rel_error": rel, "k_mean": float(kk.mean()),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def time_steps(args, ctx, w, stream):
