@@ -1165,7 +1165,7 @@ extern "C" spid_status spid_reconstruct(spid_ctx* c, const double* d_P, double* 
   if (!ok) return fail(SPID_EHIP, "reconstruct: cannot reserve the coefficient LDS");
   spid_status st = hip_check("reconstruct kernel launch");
   if (st != SPID_OK) return st;
-  hipLaunchKernelGGL(recon_reduce_kernel, dim3((c->desc.nblocks + 255) / 256), dim3(256), 0, s,
+  hipLaunchKernelGGL(recon_reduce_kernel, dim3(c->desc.nblocks), dim3(kWave), 0, s,
                      c->desc.nblocks, c->at<int64_t>(p.off_rcfirst), c->at<double>(p.off_rcpart),
                      d_err2, d_nrm2);
   return hip_check("reconstruct reduce launch");
@@ -1343,7 +1343,7 @@ extern "C" spid_status spid_reconstruct_interp(spid_ctx* c, const double* d_P, d
   if (!ok) return fail(SPID_EHIP, "reconstruct_interp: cannot reserve the coefficient LDS");
   spid_status st = hip_check("interpolated error kernel launch");
   if (st != SPID_OK) return st;
-  hipLaunchKernelGGL(recon_reduce_kernel, dim3((c->desc.nblocks + 255) / 256), dim3(256), 0, s,
+  hipLaunchKernelGGL(recon_reduce_kernel, dim3(c->desc.nblocks), dim3(kWave), 0, s,
                      c->desc.nblocks, c->at<int64_t>(p.off_rcfirst), c->at<double>(p.off_rcpart),
                      d_err2, d_nrm2);
   return hip_check("interpolated error reduce launch");

@@ -1784,19 +1784,25 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
 }
 
 // Per-block sums of the row-tile partials, items of block b are the
-// contiguous range [first[b], first[b+1]).
-__global__ void recon_reduce_kernel(int nblocks, const int64_t* __restrict__ first,
-                                    const double* __restrict__ part, double* __restrict__ err2,
-                                    double* __restrict__ nrm2) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// contiguous range [first[b], first[b+1]).  One wave per block: lane t sums
+// items first + t, first + t + 64, ... in order, then a butterfly over the
+// lanes; the order is fixed, so repeated runs give identical bits.
+__global__ __launch_bounds__(kWave) void recon_reduce_kernel(
+    int nblocks, const int64_t* __restrict__ first, const double* __restrict__ part,
+    double* __restrict__ err2, double* __restrict__ nrm2) {
+  const int b = blockIdx.x;
   if (b >= nblocks) return;
   double e = 0.0, a = 0.0;
-  for (int64_t x = first[b]; x < first[b + 1]; ++x) {
+  for (int64_t x = first[b] + threadIdx.x; x < first[b + 1]; x += kWave) {
     e += part[2 * x];
     a += part[2 * x + 1];
   }
-  err2[b] = e;
-  nrm2[b] = a;
+  e = wave_sum(e);
+  a = wave_sum(a);
+  if (threadIdx.x == 0) {
+    err2[b] = e;
+    nrm2[b] = a;
+  }
 }
 
 // Widen the sketch to FP64 (diagnostics).
