@@ -43,6 +43,14 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // Sketch-matrix entries Omega(2q, i) and Omega(2q+1, i): one Philox block at
 // counter (i, q, block key, stream 0) under the 64-bit seed, two 53-bit
 // uniforms (u1 in (0,1], u2 in [0,1)), Box-Muller in double precision.
+// A pointer into global memory (address space 1).  Data pointers that reach a
+// kernel through a table in memory are otherwise generic, and the compiler
+// then emits flat loads, whose completion shares the counter of LDS
+// accesses: every wait for LDS data would also wait for the A loads in
+// flight.  Global loads also take the scalar-base addressing form.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+
 __device__ __forceinline__ void omega_words(uint64_t seed, uint32_t bkey, uint32_t i, uint32_t q,
                                             uint64_t& a, uint64_t& b) {
   const uint4 x = philox4x32_10(make_uint4(i, q, bkey, 0u), (uint32_t)seed,

@@ -71,28 +71,28 @@ constexpr int kOmStride = kKC + 2;  // LDS row stride (doubles) of the Omega til
 // one contiguous run of 4 W elements per column.  VEC: aligned column starts
 // (16 bytes) and W-aligned rows, so the pieces are 8- or 16-byte vectors.
 template <typename TA, int NP, int W, int STEP, bool VEC, typename TO>
-__device__ __forceinline__ void load_pieces_full(const TA* __restrict__ cb, int64_t row, bool ok,
+__device__ __forceinline__ void load_pieces_full(gptr<TA> __restrict__ cb, int64_t row, bool ok,
                                                  TO out[NP * W]) {
   constexpr int kBytes = W * (int)sizeof(TA);
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc) {
-    const TA* p = cb + row + pc * STEP;
+    gptr<TA> p = cb + row + pc * STEP;
     if constexpr (VEC && kBytes % 16 == 0 && sizeof(TA) == 8) {
 #pragma unroll
       for (int h = 0; h < W / 2; ++h) {
-        const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p) + h);
+        const f64x2 v = __builtin_nontemporal_load((gptr<f64x2>)p + h);
         out[W * pc + 2 * h] = ok ? (TO)v[0] : (TO)0;
         out[W * pc + 2 * h + 1] = ok ? (TO)v[1] : (TO)0;
       }
     } else if constexpr (VEC && kBytes % 16 == 0 && sizeof(TA) == 4) {
 #pragma unroll
       for (int h = 0; h < W / 4; ++h) {
-        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p) + h);
+        const f32x4 v = __builtin_nontemporal_load((gptr<f32x4>)p + h);
 #pragma unroll
         for (int e = 0; e < 4; ++e) out[W * pc + 4 * h + e] = ok ? (TO)v[e] : (TO)0;
       }
     } else if constexpr (VEC && kBytes == 8 && sizeof(TA) == 4) {
-      const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+      const f32x2 v = __builtin_nontemporal_load((gptr<f32x2>)p);
       out[2 * pc] = ok ? (TO)v[0] : (TO)0;
       out[2 * pc + 1] = ok ? (TO)v[1] : (TO)0;
     } else {
@@ -107,7 +107,7 @@ __device__ __forceinline__ void load_pieces_full(const TA* __restrict__ cb, int6
 
 // The same for a ragged chunk: rows at or past `rend` read as zero.
 template <typename TA, int NP, int W, int STEP, typename TO>
-__device__ __forceinline__ void load_pieces_tail(const TA* __restrict__ cb, int64_t row,
+__device__ __forceinline__ void load_pieces_tail(gptr<TA> __restrict__ cb, int64_t row,
                                                  int64_t rend, bool ok, TO out[NP * W]) {
 #pragma unroll
   for (int pc = 0; pc < NP; ++pc)
@@ -155,7 +155,7 @@ __device__ __forceinline__ void gen_omega_chunk(TO* __restrict__ om, int l, uint
 // ---------------------------------------------------------------------------
 template <typename TA, int TN>
 struct SkLane {
-  const TA* cb[TN];   // column starts (clamped)
+  gptr<TA> cb[TN];    // column starts (clamped)
   bool ok[TN];        // column inside the block and inside [j0, j1)
   int col[TN];
 };
@@ -165,7 +165,7 @@ __device__ __forceinline__ bool sk_setup(const BlkInfo& bi, const SkItem& it, in
                                          int span, int j0, int j1, SkLane<TA, TN>& ln) {
   const int clo = max(j0, 0), chi = min(j1, bi.n);
   if (it.c0 >= chi || it.c0 + span <= clo) return false;   // whole tile outside (uniform)
-  const TA* A = static_cast<const TA*>(bi.A);
+  gptr<TA> A = (gptr<TA>)bi.A;
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
     const int col = cwave + 16 * u + r16;
@@ -195,7 +195,7 @@ __device__ __forceinline__ void sk_setup_stream(const BlkInfo* __restrict__ blks
     const bool ok = valid && j < bb.n;
     ln.col[u] = local;
     ln.ok[u] = ok;
-    ln.cb[u] = static_cast<const TA*>(bb.A) + (int64_t)(ok ? j : 0) * bb.lda;
+    ln.cb[u] = (gptr<TA>)bb.A + (int64_t)(ok ? j : 0) * bb.lda;
   }
 }
 
@@ -1489,20 +1489,20 @@ __device__ __forceinline__ int rc_compact_columns(int n, int k, const int32_t* _
 // block, so one vector load from a clamped address plus a selection covers
 // both; otherwise four clamped scalar loads.  Branch-free either way.
 template <typename TA, bool VEC>
-__device__ __forceinline__ void rc_load4(const TA* __restrict__ colp, int64_t i0, int64_t m,
+__device__ __forceinline__ void rc_load4(gptr<TA> __restrict__ colp, int64_t i0, int64_t m,
                                          bool ok, double out[4]) {
   if constexpr (VEC) {
     const bool in = ok && i0 < m;
-    const TA* src = colp + (in ? i0 : 0);
+    gptr<TA> src = colp + (in ? i0 : 0);
     if constexpr (sizeof(TA) == 8) {
-      const f64x2 x0 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src));
-      const f64x2 x1 = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(src) + 1);
+      const f64x2 x0 = __builtin_nontemporal_load((gptr<f64x2>)src);
+      const f64x2 x1 = __builtin_nontemporal_load((gptr<f64x2>)src + 1);
       out[0] = in ? x0[0] : 0.0;
       out[1] = in ? x0[1] : 0.0;
       out[2] = in ? x1[0] : 0.0;
       out[3] = in ? x1[1] : 0.0;
     } else {
-      const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
+      const f32x4 x = __builtin_nontemporal_load((gptr<f32x4>)src);
 #pragma unroll
       for (int v = 0; v < 4; ++v) out[v] = in ? (double)x[v] : 0.0;
     }
@@ -1550,7 +1550,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
   const int n = bi.n;
   const int k = k_ws[it.blk];
   const int32_t* S = S_ws + (int64_t)it.blk * k_max;
-  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
+  gptr<TA> __restrict__ A = (gptr<TA>)bi.A;
   const double* __restrict__ Pb = P + bi.p_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c16 = lane & 15;
@@ -1593,7 +1593,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
       for (int tq = 0; tq < ntile; ++tq) {
         const int q = 16 * tq + c16;
         const bool cok = q < cc;
-        const TA* colp = A + (int64_t)cols[c0 + (cok ? q : cc - 1)] * bi.lda;
+        gptr<TA> colp = A + (int64_t)cols[c0 + (cok ? q : cc - 1)] * bi.lda;
         double av[MTR][4];
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt)
@@ -1668,7 +1668,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
   const BlkInfo bi = blks[it.blk];
   const int k = k_ws[it.blk];
   const int32_t* S = S_ws + (int64_t)it.blk * k_max;
-  const float* __restrict__ A = static_cast<const float*>(bi.A);
+  gptr<float> __restrict__ A = (gptr<float>)bi.A;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const int64_t col_off = bi.y_off / l;
@@ -1728,9 +1728,9 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt) {
           const int64_t i0 = rbase + 16 * mt + 4 * g;
-          const float* src = A + j * bi.lda + i0;
+          gptr<float> src = A + j * bi.lda + i0;
           if (VEC && cok && i0 + 4 <= bi.m) {
-            const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src));
+            const f32x4 x = __builtin_nontemporal_load((gptr<f32x4>)src);
 #pragma unroll
             for (int v = 0; v < 4; ++v) av[mt][v] = x[v];
           } else {

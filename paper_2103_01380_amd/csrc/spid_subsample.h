@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void subsample_kernel(const BlkInfo* __restric
     if (je <= j0) continue;
     const int64_t lda = blks[b].lda;
     const int64_t y_off = blks[b].y_off;
-    const TA* __restrict__ A = static_cast<const TA*>(blks[b].A);
+    gptr<TA> __restrict__ A = (gptr<TA>)blks[b].A;
     const GridInfo g = grids[b];
     const int64_t total = (int64_t)l * (je - j0);
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kRcThreads) void interp_mfma_kernel(
   const int n = bi.n;
   const int k = k_ws[it.blk];
   const int32_t* __restrict__ S = S_ws + (int64_t)it.blk * k_max;
-  const TA* __restrict__ A = static_cast<const TA*>(bi.A);
+  gptr<TA> __restrict__ A = (gptr<TA>)bi.A;
   const double* __restrict__ Pb = P + bi.p_off;
   const double* __restrict__ Yb = Y + bi.y_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kRcThreads) void interp_mfma_kernel(
       for (int tq = 0; tq < ntile; ++tq) {
         const int q = 16 * tq + c16;
         const bool cok = q < cc;
-        const TA* colp = A + (int64_t)(c0 + (cok ? q : cc - 1)) * bi.lda;
+        gptr<TA> colp = A + (int64_t)(c0 + (cok ? q : cc - 1)) * bi.lda;
         double av[MTR][4];
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt)
