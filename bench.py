@@ -509,7 +509,9 @@ def oracle_agreement(w, A, m, n, off, ctx, idx, res):
         extra = {"gpu_rel_interp_error": float(np.sqrt(i2g[idx].sum() / n2g[idx].sum())),
                  "oracle_rel_interp_error": res.rel_interp_error}
     return {"blocks": int(len(idx)), **extra,
-            "gpu_rel_error": float(np.sqrt(e2g[idx].sum() / n2g[idx].sum())),
+            # the coarse-grid step measures the single-pass error only (no SubID pass)
+            "gpu_rel_error": (None if w.subsample else
+                              float(np.sqrt(e2g[idx].sum() / n2g[idx].sum()))),
             "oracle_rel_error": res.rel_error,
             "R2": float(np.sqrt(num / den)) if den > 0 else 0.0,
             "gap_gamma": gamma,

@@ -218,7 +218,8 @@ spid_status spid_select_two_stage(spid_ctx* ctx, int32_t* d_k, int32_t* d_S, int
  * d_P holds every block's k_max x n_b column-major matrix (leading dimension
  * k_max) at element offset k_max * sum_{c<b} n_c; P_b(:, S[t]) = e_t exactly,
  * other columns solve R11 x = R12(:, j) by back-substitution, rows >= k_b are
- * zero.  ESTATE before spid_select. */
+ * zero.  ESTATE before spid_select, and after spid_select_two_stage (which
+ * writes the coefficients itself). */
 spid_status spid_coeffs(spid_ctx* ctx, double* d_P, void* stream);
 
 /* Reconstruction error (Section 5.1) against the stored A:

@@ -149,6 +149,11 @@ struct Plan {
   bool coarse = false;
   std::vector<GridInfo> grid;
   int64_t sum_mc = 0;
+  // a few very tall coarse sketches: selection with the rows split over workgroups
+  bool split = false;
+  int split_nch = 0;
+  std::vector<int64_t> split_off;   // per block: offset of its chunk partials (nch * n_b)
+  int64_t split_elems = 0;
   // modified two-stage ID: window table (nblocks * nwin), stage-2 table (nblocks)
   int ts_nwin = 0, ts_k1 = 0, ts_kmax1 = 8;
   SelShape ts_sel1, ts_sel2;
@@ -158,7 +163,8 @@ struct Plan {
   int max_n = 0, max_split_n = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
       off_st, off_rcpart, off_perm, off_sitems, off_sheads, off_ritems, off_pt, off_cols, off_ncols,
-      off_grid, off_W, off_tswin, off_tsblk2, off_tsR1, off_tsP1, off_tsS1, off_tsk1, off_tsst1,
+      off_grid, off_W, off_spoff, off_spnorm, off_spdot, off_spused, off_spstate, off_spbad,
+      off_tswin, off_tsblk2, off_tsR1, off_tsP1, off_tsS1, off_tsk1, off_tsst1,
       off_tsY2, off_tsW2, off_tsR2, off_tsP2, off_tsS2, off_tsk2, off_tsst2, total;
 };
 
@@ -412,6 +418,19 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     }
   }
 
+  // too few blocks to fill the chip with one workgroup each: split their rows
+  if (p.coarse && sh.sel.sel_tall && nb < 128 && d->l > 4 * kSplitRows) {
+    p.split = true;
+    p.split_nch = (d->l + kSplitRows - 1) / kSplitRows;
+    p.split_off.resize(nb);
+    int64_t o = 0;
+    for (int b = 0; b < nb; ++b) {
+      p.split_off[b] = o;
+      o += (int64_t)p.split_nch * d->h_n[b];
+    }
+    p.split_elems = o;
+  }
+
   if (d->ts_windows > 0) {
     const int nw = d->ts_windows, k1 = d->ts_k1;
     p.ts_nwin = nw;
@@ -561,6 +580,12 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_grid = take(sizeof(GridInfo) * std::max<size_t>(1, p.grid.size()));
   p.off_W = take((sh.sel.sel_tall || p.ts_sel1.sel_tall) ? sizeof(double) * (size_t)d->l * p.sum_n
                                                          : 256);
+  p.off_spoff = take(sizeof(int64_t) * std::max<size_t>(1, p.split_off.size()));
+  p.off_spnorm = take(sizeof(double) * (size_t)std::max<int64_t>(1, p.split_elems));
+  p.off_spdot = take(sizeof(double) * (size_t)std::max<int64_t>(1, p.split_elems));
+  p.off_spused = take(p.split ? (size_t)nb * kTallMaxN : 256);
+  p.off_spstate = take(sizeof(SplitState) * (p.split ? (size_t)nb : 1));
+  p.off_spbad = take(sizeof(int32_t) * (p.split ? (size_t)nb : 1));
   {
     const bool ts = p.ts_nwin > 0;
     const size_t nwt = ts ? p.ts_win.size() : 1;
@@ -595,6 +620,7 @@ struct spid_ctx {
   bool bound = false;
   bool selected = false;
   bool coeffs_done = false;        // spid_coeffs ran after the last selection
+  bool two_stage = false;          // the last selection was spid_select_two_stage
   bool all_vec = false;            // every block's column starts are 16-byte aligned
   bool all_vec4 = false;           // ... and every m is a multiple of 4
   std::vector<uint8_t> covered;   // per column index: sketched since bind
@@ -805,9 +831,48 @@ bool launch_select_job(const SelJob<TY>& j, hipStream_t s) {
   return true;
 }
 
+// Row-split selection of a few very tall coarse sketches: init, then three launches per
+// step and a final pivot launch (blocks that stopped return at once).
+bool launch_select_split(spid_ctx* c, hipStream_t s) {
+  const Plan& p = c->plan;
+  const spid_desc& d = c->desc;
+  const int nb = d.nblocks;
+  const BlkInfo* blks = c->at<BlkInfo>(p.off_blk);
+  const int64_t* poff = c->at<int64_t>(p.off_spoff);
+  double* pnorm = c->at<double>(p.off_spnorm);
+  double* pdot = c->at<double>(p.off_spdot);
+  unsigned char* used = c->at<unsigned char>(p.off_spused);
+  SplitState* st = c->at<SplitState>(p.off_spstate);
+  int32_t* bad = c->at<int32_t>(p.off_spbad);
+  double* W = c->at<double>(p.off_W);
+  double* R = c->at<double>(p.off_R);
+  int32_t* S = c->at<int32_t>(p.off_S);
+  int32_t* k = c->at<int32_t>(p.off_k);
+  int32_t* sts = c->at<int32_t>(p.off_st);
+  const dim3 g2((unsigned)p.split_nch, (unsigned)nb);
+  hipLaunchKernelGGL(split_clear_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, nb, bad);
+  hipLaunchKernelGGL(split_init_kernel, g2, dim3(kSplitThreads), 0, s, blks, d.l,
+                     c->at<double>(p.off_Y), W, poff, pnorm, bad);
+  const int kcap = std::min(d.k_max, std::min(d.l, p.max_n));
+  for (int step = 0; step <= kcap; ++step) {
+    hipLaunchKernelGGL(split_pivot_kernel, dim3(nb), dim3(kSplitThreads), 0, s, blks, d.l,
+                       d.k_max, d.tol, d.rank_floor, step, poff, pnorm, used, st, bad, R, S, k,
+                       sts);
+    if (step == kcap) break;
+    hipLaunchKernelGGL(split_dot_kernel, g2, dim3(kSplitThreads), 0, s, blks, d.l, poff, st,
+                       used, W, pdot);
+    hipLaunchKernelGGL(split_update_kernel, g2, dim3(kSplitThreads), 0, s, blks, d.l, step, poff,
+                       st, used, pdot, W, pnorm, R);
+  }
+  return true;
+}
+
 template <typename TY>
 bool launch_select_ctx(spid_ctx* c, hipStream_t s) {
   const Plan& p = c->plan;
+  if constexpr (std::is_same<TY, double>::value) {
+    if (p.split) return launch_select_split(c, s);
+  }
   SelJob<TY> j{c->at<BlkInfo>(p.off_blk), c->desc.nblocks, c->desc.l, c->desc.k_max,
                c->desc.tol, c->desc.rank_floor, c->at<TY>(p.off_Y), c->at<double>(p.off_W),
                c->at<double>(p.off_R), c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
@@ -975,6 +1040,9 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
   if (e == hipSuccess && p.coarse)
     e = hipMemcpy(c->ws + p.off_grid, p.grid.data(), sizeof(GridInfo) * p.grid.size(),
                   hipMemcpyHostToDevice);
+  if (e == hipSuccess && p.split)
+    e = hipMemcpy(c->ws + p.off_spoff, p.split_off.data(), sizeof(int64_t) * p.split_off.size(),
+                  hipMemcpyHostToDevice);
   if (e == hipSuccess && p.ts_nwin > 0)
     e = hipMemcpy(c->ws + p.off_tswin, p.ts_win.data(), sizeof(BlkInfo) * p.ts_win.size(),
                   hipMemcpyHostToDevice);
@@ -1132,12 +1200,16 @@ extern "C" spid_status spid_select(spid_ctx* c, int32_t* d_k, int32_t* d_S, int3
   }
   c->selected = true;
   c->coeffs_done = false;
+  c->two_stage = false;
   return SPID_OK;
 }
 
 extern "C" spid_status spid_coeffs(spid_ctx* c, double* d_P, void* stream) {
   if (!c || !d_P) return fail(SPID_EINVAL, "NULL argument to spid_coeffs");
   if (!c->selected) return fail(SPID_ESTATE, "spid_coeffs before spid_select");
+  if (c->two_stage)
+    return fail(SPID_ESTATE,
+                "spid_coeffs after spid_select_two_stage (which writes the coefficients)");
   hipStream_t s = static_cast<hipStream_t>(stream);
   bool ok = false;
   switch (c->plan.sh.KMAX) {
@@ -1323,6 +1395,7 @@ extern "C" spid_status spid_select_two_stage(spid_ctx* c, int32_t* d_k, int32_t*
   // the final selection and coefficients are in place: the error pass may follow
   c->selected = true;
   c->coeffs_done = true;
+  c->two_stage = true;
   return SPID_OK;
 }
 

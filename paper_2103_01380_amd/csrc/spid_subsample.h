@@ -331,6 +331,249 @@ __global__ __launch_bounds__(kTallThreads) void select_tall_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Column selection of a few very tall sketches (the single-partition case):
+// the same mgsqr steps as select_tall_kernel, with every block's rows split
+// into chunks of kSplitRows so that many workgroups share one block.  One
+// step is three launches: the pivot (one workgroup per block: fixed-order
+// sums of the chunk partial norms, stopping rules, argmax), the dot products
+// (per chunk: that chunk's rows of q = W(:,p)/r_pp are formed in place, then
+// partial q.W(:,j)), and the update (per chunk: fixed-order sum of the
+// partial dots, W(:,j) -= d_j q, partial norms).  A block that has stopped
+// makes the later launches return at once; the host launches k steps plus
+// one final pivot launch (which applies the last tolerance test).
+// State per block (SplitState) and partial sums live in the workspace.
+// ---------------------------------------------------------------------------
+constexpr int kSplitRows = 256;
+constexpr int kSplitThreads = 256;
+
+struct SplitState {
+  double F2, nu0max, rss;
+  int32_t p, done, k, status;
+};
+
+// clears the per-block non-finite flags before split_init_kernel
+__global__ void split_clear_kernel(int nblocks, int32_t* __restrict__ bad) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nblocks) bad[b] = 0;
+}
+
+// copy of the sketch, non-finite check, partial column norms of each chunk
+__global__ __launch_bounds__(kSplitThreads) void split_init_kernel(
+    const BlkInfo* __restrict__ blks, int l, const double* __restrict__ Y, double* __restrict__ W,
+    const int64_t* __restrict__ poff, double* __restrict__ pnorm, int32_t* __restrict__ bad) {
+  const int b = blockIdx.y, c = blockIdx.x;
+  const int nch = (l + kSplitRows - 1) / kSplitRows;
+  if (c >= nch) return;
+  const BlkInfo bi = blks[b];
+  const int n = bi.n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = c * kSplitRows, r1 = min(l, r0 + kSplitRows);
+  int nonfinite = 0;
+  for (int j = wave; j < n; j += kSplitThreads / kWave) {
+    double acc = 0.0;
+    for (int r = r0 + lane; r < r1; r += kWave) {
+      const double v = Y[bi.y_off + (int64_t)j * l + r];
+      W[bi.y_off + (int64_t)j * l + r] = v;
+      if (!isfinite(v)) nonfinite = 1;
+      acc += v * v;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) pnorm[poff[b] + (int64_t)c * n + j] = acc;
+  }
+  if (__any(nonfinite) && lane == 0) bad[b] = 1;   // only ever set: no ordering needed
+}
+
+// pivot of step s (s == kcap_b: the final tolerance test only)
+__global__ __launch_bounds__(kSplitThreads) void split_pivot_kernel(
+    const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor, int s,
+    const int64_t* __restrict__ poff, const double* __restrict__ pnorm,
+    unsigned char* __restrict__ used, SplitState* __restrict__ st, const int32_t* __restrict__ bad,
+    double* __restrict__ R, int32_t* __restrict__ S_ws, int32_t* __restrict__ k_ws,
+    int32_t* __restrict__ st_ws) {
+  __shared__ double nu[kTallMaxN];
+  __shared__ double red_v[kSplitThreads / kWave];
+  __shared__ int red_i[kSplitThreads / kWave];
+  constexpr int NWV = kSplitThreads / kWave;
+  const int b = blockIdx.x;
+  const BlkInfo bi = blks[b];
+  const int n = bi.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  SplitState& S = st[b];
+  if (s > 0 && S.done) return;                          // uniform
+  unsigned char* __restrict__ ub = used + (int64_t)b * kTallMaxN;
+  const int nch = (l + kSplitRows - 1) / kSplitRows;
+  int kcap = k_max;
+  if (kcap > l) kcap = l;
+  if (kcap > n) kcap = n;
+  auto finish = [&](int k, int status) {
+    if (tid == 0) {
+      S.done = 1;
+      S.k = k;
+      S.status = status;
+      k_ws[b] = k;
+      st_ws[b] = status;
+    }
+    for (int t = k + tid; t < k_max; t += kSplitThreads) S_ws[(int64_t)b * k_max + t] = -1;
+  };
+  if (s == 0) {
+    if (tid == 0) S.done = 0;
+    for (int j = tid; j < n; j += kSplitThreads) ub[j] = 0;
+    if (bad[b]) {
+      finish(0, 2);
+      return;
+    }
+  }
+  // nu_j of the live columns: fixed-order sums of the chunk partials
+  for (int j = tid; j < n; j += kSplitThreads) {
+    double v = 0.0;
+    if (s == 0 || !ub[j])
+      for (int c = 0; c < nch; ++c) v += pnorm[poff[b] + (int64_t)c * n + j];
+    nu[j] = v;
+  }
+  __syncthreads();
+  double fs = 0.0, fm = 0.0;
+  for (int j = tid; j < n; j += kSplitThreads) {
+    fs += nu[j];
+    fm = fmax(fm, nu[j]);
+  }
+  fs = wave_sum(fs);
+  fm = wave_max(fm);
+  if (lane == 0) red_v[wave] = fs;
+  __syncthreads();
+  double tot = 0.0;
+  for (int v = 0; v < NWV; ++v) tot += red_v[v];
+  __syncthreads();
+  if (lane == 0) red_v[wave] = fm;
+  __syncthreads();
+  double mx = 0.0;
+  for (int v = 0; v < NWV; ++v) mx = fmax(mx, red_v[v]);
+  __syncthreads();
+  double F2, nu0max;
+  if (s == 0) {
+    F2 = tot;
+    nu0max = mx;
+    if (tid == 0) {
+      S.F2 = tot;
+      S.nu0max = mx;
+    }
+  } else {
+    F2 = S.F2;
+    nu0max = S.nu0max;
+    if (tol > 0.0 && sqrt(tot) <= tol * sqrt(F2)) {   // after the previous step's update
+      finish(s, 0);
+      return;
+    }
+  }
+  if (s >= kcap) {
+    finish(kcap, tol > 0.0 ? 3 : 0);
+    return;
+  }
+  double bv = -1.0;
+  int bj = 0x7fffffff;
+  for (int j = tid; j < n; j += kSplitThreads)
+    if (!ub[j] && nu[j] > bv) {   // ascending j: ties keep the lowest index
+      bv = nu[j];
+      bj = j;
+    }
+  wave_argmax(bv, bj);
+  if (lane == 0) {
+    red_v[wave] = bv;
+    red_i[wave] = bj;
+  }
+  __syncthreads();
+  double best = red_v[0];
+  int p = red_i[0];
+  for (int x = 1; x < NWV; ++x)
+    if (red_v[x] > best || (red_v[x] == best && red_i[x] < p)) {
+      best = red_v[x];
+      p = red_i[x];
+    }
+  if (!(best > 0.0) || (rank_floor > 0.0 && best <= rank_floor * rank_floor * nu0max)) {
+    finish(s, 1);
+    return;
+  }
+  if (tid == 0) {
+    const double rss = sqrt(best);
+    S.p = p;
+    S.rss = rss;
+    R[bi.r_off + (int64_t)s * n + p] = rss;
+    S_ws[(int64_t)b * k_max + s] = p;
+    ub[p] = 1;
+  }
+}
+
+// dot products of step s: chunk rows of q formed in place, partial q.W(:,j)
+__global__ __launch_bounds__(kSplitThreads) void split_dot_kernel(
+    const BlkInfo* __restrict__ blks, int l, const int64_t* __restrict__ poff,
+    const SplitState* __restrict__ st, const unsigned char* __restrict__ used,
+    double* __restrict__ W, double* __restrict__ pdot) {
+  const int b = blockIdx.y, c = blockIdx.x;
+  const int nch = (l + kSplitRows - 1) / kSplitRows;
+  if (c >= nch || st[b].done) return;
+  const BlkInfo bi = blks[b];
+  const int n = bi.n;
+  const int p = st[b].p;
+  const double rss = st[b].rss;
+  const unsigned char* __restrict__ ub = used + (int64_t)b * kTallMaxN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = c * kSplitRows, r1 = min(l, r0 + kSplitRows);
+  double* __restrict__ q = W + bi.y_off + (int64_t)p * l;
+  __shared__ double qs[kSplitRows];
+  for (int r = r0 + threadIdx.x; r < r1; r += kSplitThreads) {
+    const double v = q[r] / rss;
+    q[r] = v;
+    qs[r - r0] = v;
+  }
+  __syncthreads();
+  for (int j = wave; j < n; j += kSplitThreads / kWave) {
+    if (ub[j]) continue;   // the pivot and earlier pivots (uniform over the wave)
+    double d = 0.0;
+    for (int r = r0 + lane; r < r1; r += kWave) d += qs[r - r0] * W[bi.y_off + (int64_t)j * l + r];
+    d = wave_sum(d);
+    if (lane == 0) pdot[poff[b] + (int64_t)c * n + j] = d;
+  }
+}
+
+// update of step s: d_j in a fixed order, W(:,j) -= d_j q on the chunk rows,
+// chunk partial norms; chunk 0 records R(s, j)
+__global__ __launch_bounds__(kSplitThreads) void split_update_kernel(
+    const BlkInfo* __restrict__ blks, int l, int s, const int64_t* __restrict__ poff,
+    const SplitState* __restrict__ st, const unsigned char* __restrict__ used,
+    const double* __restrict__ pdot, double* __restrict__ W, double* __restrict__ pnorm,
+    double* __restrict__ R) {
+  const int b = blockIdx.y, c = blockIdx.x;
+  const int nch = (l + kSplitRows - 1) / kSplitRows;
+  if (c >= nch || st[b].done) return;
+  const BlkInfo bi = blks[b];
+  const int n = bi.n;
+  const int p = st[b].p;
+  const unsigned char* __restrict__ ub = used + (int64_t)b * kTallMaxN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = c * kSplitRows, r1 = min(l, r0 + kSplitRows);
+  __shared__ double qs[kSplitRows];
+  for (int r = r0 + threadIdx.x; r < r1; r += kSplitThreads)
+    qs[r - r0] = W[bi.y_off + (int64_t)p * l + r];
+  __syncthreads();
+  for (int j = wave; j < n; j += kSplitThreads / kWave) {
+    if (ub[j]) continue;
+    double d = 0.0;
+    for (int x = 0; x < nch; ++x) d += pdot[poff[b] + (int64_t)x * n + j];
+    double a2 = 0.0;
+    for (int r = r0 + lane; r < r1; r += kWave) {
+      const int64_t e = bi.y_off + (int64_t)j * l + r;
+      const double v = W[e] - d * qs[r - r0];
+      W[e] = v;
+      a2 += v * v;
+    }
+    a2 = wave_sum(a2);
+    if (lane == 0) {
+      pnorm[poff[b] + (int64_t)c * n + j] = a2;
+      if (c == 0) R[bi.r_off + (int64_t)s * n + j] = d;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Single-pass error (equation (single_ID), Algorithm 3) on the FP64 matrix
 // cores: Ahat(rows, cols) = K(rows, :) P(:, cols) with the interpolated
 // skeleton K = M B(:,S) as the A operand of v_mfma_f64_16x16x4 (16 rows x 4

@@ -145,3 +145,18 @@ def test_tall_selection_row_caching_variants(grid):
     g = gpu_run(blocks, None, 24, 0, tol=1e-7, grids=grids)
     o = oracle_run(blocks, l, 24, 0, tol=1e-7, grids=grids)
     _check(g, o, blocks, grids)
+
+
+def test_tall_selection_one_workgroup_per_block_streaming_rows():
+    """128 blocks of 1440 coarse rows: the one-workgroup-per-block selection in its
+    streaming form (fewer blocks take the row-split selection)."""
+    grids = [(24, 20, 12, 2, 2, 2, 2)] * 128
+    blocks = _field_blocks(grids[:1], 32, 6, noise=1e-8) * 128
+    print("case: tall 128 blocks", flush=True)
+    g = gpu_run(blocks, None, 10, 0, tol=1e-6, grids=grids)
+    o = oracle_run(blocks[:2], 1440, 10, 0, tol=1e-6, grids=grids[:2])
+    for b in range(128):                    # identical blocks: identical results
+        assert np.array_equal(g.S[b], g.S[0]) and g.err2[b] == g.err2[0]
+    sub = type(g)(g.Y[:2], g.S[:2], g.k[:2], g.status[:2], g.P[:2], g.err2[:2], g.nrm2[:2],
+                  None, g.ierr2[:2], g.cskel[:2])
+    _check(sub, o, blocks[:2], grids[:2])

@@ -135,4 +135,15 @@ def test_two_stage_state_and_argument_errors():
     with pytest.raises(sp.SpidError) as e:
         ctx.select_two_stage()
     assert e.value.status == sp.SPID_ESTATE
+    A = torch.randn(1, 10, 100, dtype=torch.float64, device="cuda")
+    ctx.bind(A)
+    ctx.sketch_update()
+    ctx.select_two_stage()
+    with pytest.raises(sp.SpidError) as e:       # the two-stage call wrote P itself
+        ctx.coeffs()
+    assert e.value.status == sp.SPID_ESTATE
+    ctx.reconstruct()
+    ctx.select()                                  # a plain selection re-enables coeffs
+    ctx.coeffs()
+    torch.cuda.synchronize()
     ctx.close()
