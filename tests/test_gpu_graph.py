@@ -51,3 +51,73 @@ def test_graph_replays_equal_eager(prec, dtype):
         for a, b in zip((ctx.S, ctx.k, ctx.P, ctx.err2, ctx.nrm2), ref):
             assert torch.equal(a, b), rep
     ctx.close()
+
+
+def _capture_and_check(ctx, step, outs):
+    step()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in outs]
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            step(s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for t in outs:
+            t.fill_(7)                      # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), rep
+
+
+@pytest.mark.parametrize("nblocks,interval", [(24, 2), (2, 1)])
+def test_graph_coarse_grid_single_pass(nblocks, interval):
+    """Coarse-grid sketch, selection (one workgroup per block, or the row-split
+    form for two tall blocks), coefficients and the single-pass error in one graph."""
+    import paper_2103_01380_amd as sp
+    g = torch.Generator(device="cuda")
+    g.manual_seed(6)
+    grid = (20, 16, 12, 2, interval, interval, interval)
+    m, n = 20 * 16 * 12 * 2, 64
+    U = torch.randn((nblocks, 5, m), generator=g, device="cuda", dtype=torch.float64)
+    C = torch.randn((nblocks, n, 5), generator=g, device="cuda", dtype=torch.float64)
+    A = torch.bmm(C, U) + 1e-6 * torch.randn((nblocks, n, m), generator=g, device="cuda",
+                                             dtype=torch.float64)
+    ctx = sp.SPID(np.full(nblocks, m), np.full(nblocks, n), None, 8, tol=1e-4, prec="subsample",
+                  grids=[grid] * nblocks)
+    ctx.bind(A)
+
+    def step(stream=None):
+        ctx.sketch_update(stream=stream)
+        ctx.select(stream)
+        ctx.coeffs(stream)
+        ctx.reconstruct_interp(stream=stream)
+
+    _capture_and_check(ctx, step, (ctx.S, ctx.k, ctx.P, ctx.err2_interp, ctx.nrm2))
+    ctx.close()
+
+
+def test_graph_two_stage():
+    import paper_2103_01380_amd as sp
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    nb, n, m = 16, 120, 2000
+    U = torch.randn((nb, 7, m), generator=g, device="cuda", dtype=torch.float64)
+    C = torch.randn((nb, n, 7), generator=g, device="cuda", dtype=torch.float64)
+    A = torch.bmm(C, U) + 1e-7 * torch.randn((nb, n, m), generator=g, device="cuda",
+                                             dtype=torch.float64)
+    ctx = sp.SPID(np.full(nb, m), np.full(nb, n), 20, 12, tol=1e-5, seed=4, ts_windows=6,
+                  ts_k1=5)
+    ctx.bind(A)
+
+    def step(stream=None):
+        ctx.sketch_update(stream=stream)
+        ctx.select_two_stage(stream)
+        ctx.reconstruct(stream=stream)
+
+    _capture_and_check(ctx, step, (ctx.S, ctx.k, ctx.P, ctx.err2, ctx.nrm2))
+    ctx.close()

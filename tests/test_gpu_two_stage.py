@@ -147,3 +147,36 @@ def test_two_stage_state_and_argument_errors():
     ctx.coeffs()
     torch.cuda.synchronize()
     ctx.close()
+
+
+def test_two_stage_single_precision_sketch():
+    """BF16 sketch of FP64 data: the sketch (and the gathered stage-2 sketch) are
+    single precision; pivots follow the gap rule at 1e-3 against the oracle's
+    bfloat16-rounded sketch matrix."""
+    import paper_2103_01380_amd as sp
+    shapes = [(4096, 96)] * 6
+    blocks = _blocks(shapes, 8, rank=8, decay=0.3, noise=1e-9)
+    m = np.array([b.shape[0] for b in blocks], dtype=np.int64)
+    n = np.array([b.shape[1] for b in blocks], dtype=np.int32)
+    A = torch.from_numpy(np.concatenate([b.T.ravel() for b in blocks])).cuda()
+    off = np.arange(len(blocks), dtype=np.int64) * 4096 * 96
+    ctx = sp.SPID(m, n, 24, 10, tol=1e-4, seed=5, prec="bf16", lp_terms=2, ts_windows=4,
+                  ts_k1=6)
+    ctx.bind(A, offsets=off)
+    ctx.sketch_update()
+    ctx.select_two_stage()
+    ctx.reconstruct()
+    torch.cuda.synchronize()
+    S, k = ctx.S.cpu().numpy(), ctx.k.cpu().numpy()
+    for b, Ab in enumerate(blocks):
+        Y = oracle.sketch(Ab, 24, 5, prec=oracle.OMEGA_BF16)
+        ts = oracle.two_stage(Y, 4, 6, 10, 1e-4)
+        s_star, ok = matched_prefix(S[b], ts.S, ts.gaps, k[b], ts.k, 1e-3)
+        assert ok and s_star >= 1, (b, S[b][:s_star], ts.S[:s_star])
+        kg = int(k[b])
+        Pb = ctx.block_P(b)
+        assert np.array_equal(Pb[:kg][:, S[b][:kg]], np.eye(kg))
+    e_gpu = ctx.rel_error()
+    print(f"two-stage bf16 rel err {e_gpu:.3e}")
+    assert e_gpu < 1e-3
+    ctx.close()
