@@ -802,9 +802,7 @@ __global__ __launch_bounds__(512) void select_kernel(
   __shared__ double q_lds[LMAX];
   __shared__ double red_v[16];
   __shared__ int red_i[16];
-  __shared__ double bc_v;
   __shared__ double bc_rss;
-  __shared__ int bc_i;
   const int b = blockIdx.x;
   const BlkInfo bi = blks[b];
   const int n = bi.n;
@@ -883,20 +881,11 @@ __global__ __launch_bounds__(512) void select_kernel(
         red_i[wave] = bj;
       }
       __syncthreads();
-      if (tid == 0) {
-        double v = red_v[0];
-        int i = red_i[0];
-        for (int x = 1; x < nwaves; ++x)
-          if (red_v[x] > v || (red_v[x] == v && red_i[x] < i)) {
-            v = red_v[x];
-            i = red_i[x];
-          }
-        bc_v = v;
-        bc_i = i;
-      }
-      __syncthreads();
-      const double best = bc_v;
-      const int p = bc_i;
+      // every wave reduces the per-wave winners itself (ties to the lowest index); the
+      // next write of red_v comes after the pivot barrier below
+      double best = lane < nwaves ? red_v[lane] : -1.0;
+      int p = lane < nwaves ? red_i[lane] : 0x7fffffff;
+      wave_argmax(best, p);
       if (!(best > 0.0)) {
         status = 1;   // SPID_BLOCK_RANK_DEFICIENT
         break;
@@ -1000,9 +989,7 @@ __global__ __launch_bounds__(768) void select_pair_kernel(
   __shared__ double q_lds[2 * RPT];
   __shared__ double red_v[16];
   __shared__ int red_i[16];
-  __shared__ double bc_v;
   __shared__ double bc_rss;
-  __shared__ int bc_i;
   const int b = blockIdx.x;
   const BlkInfo bi = blks[b];
   const int n = bi.n;
@@ -1062,20 +1049,11 @@ __global__ __launch_bounds__(768) void select_pair_kernel(
         red_i[wave] = bj;
       }
       __syncthreads();
-      if (tid == 0) {
-        double v = red_v[0];
-        int i = red_i[0];
-        for (int x = 1; x < nwaves; ++x)
-          if (red_v[x] > v || (red_v[x] == v && red_i[x] < i)) {
-            v = red_v[x];
-            i = red_i[x];
-          }
-        bc_v = v;
-        bc_i = i;
-      }
-      __syncthreads();
-      const double best = bc_v;
-      const int p = bc_i;
+      // every wave reduces the per-wave winners itself (ties to the lowest index); the
+      // next write of red_v comes after the pivot barrier below
+      double best = lane < nwaves ? red_v[lane] : -1.0;
+      int p = lane < nwaves ? red_i[lane] : 0x7fffffff;
+      wave_argmax(best, p);
       if (!(best > 0.0)) {
         status = 1;   // SPID_BLOCK_RANK_DEFICIENT
         break;
@@ -1169,8 +1147,7 @@ __global__ __launch_bounds__(MAXTHR) void select_hybrid_kernel(
   __shared__ double q_lds[128];
   __shared__ double red_v[16];
   __shared__ int red_i[16];
-  __shared__ double bc_v, bc_rss;
-  __shared__ int bc_i;
+  __shared__ double bc_rss;
   const int b = blockIdx.x;
   const BlkInfo bi = blks[b];
   const int n = bi.n;
@@ -1234,20 +1211,11 @@ __global__ __launch_bounds__(MAXTHR) void select_hybrid_kernel(
         red_i[wave] = bj;
       }
       __syncthreads();
-      if (tid == 0) {
-        double v = red_v[0];
-        int i = red_i[0];
-        for (int x = 1; x < nwaves; ++x)
-          if (red_v[x] > v || (red_v[x] == v && red_i[x] < i)) {
-            v = red_v[x];
-            i = red_i[x];
-          }
-        bc_v = v;
-        bc_i = i;
-      }
-      __syncthreads();
-      const double best = bc_v;
-      const int p = bc_i;
+      // every wave reduces the per-wave winners itself (ties to the lowest index); the
+      // next write of red_v comes after the pivot barrier below
+      double best = lane < nwaves ? red_v[lane] : -1.0;
+      int p = lane < nwaves ? red_i[lane] : 0x7fffffff;
+      wave_argmax(best, p);
       if (!(best > 0.0)) {
         status = 1;
         break;
