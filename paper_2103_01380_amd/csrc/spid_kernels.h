@@ -1391,29 +1391,48 @@ __global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
       }
     }
     double* pc = Pb + (int64_t)j * k_max;
+    if ((k_max & 1) == 0) {
+      // 16-byte stores (an even k_max keeps every column start 16-byte aligned)
 #pragma unroll
-    for (int t = 0; t < KMAX; ++t)
-      if (t < k_max) pc[t] = (t < k) ? x[t] : 0.0;
+      for (int t0 = 0; t0 < KMAX; t0 += 2)
+        if (t0 < k_max)
+          *reinterpret_cast<f64x2*>(pc + t0) =
+              f64x2{t0 < k ? x[t0] : 0.0, t0 + 1 < k ? x[t0 + 1] : 0.0};
+    } else {
+#pragma unroll
+      for (int t = 0; t < KMAX; ++t)
+        if (t < k_max) pc[t] = (t < k) ? x[t] : 0.0;
+    }
     if (pt) {
       cols_out[col_off + q] = j;
+      // three bfloat16 terms, eight at a time (16-byte stores: KP is a multiple of 32)
       __bf16* o = pt + (col_off + q) * 3 * KP;
 #pragma unroll
-      for (int t = 0; t < KMAX; ++t) {
-        if (t < KP) {
-          const double pv = (t < k) ? x[t] : 0.0;
-          const __bf16 h = to_bf16((float)pv);
-          const double r1 = pv - (double)(float)h;
-          const __bf16 md = to_bf16((float)r1);
-          const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
-          o[t] = h;
-          o[KP + t] = md;
-          o[2 * KP + t] = lo;
+      for (int t0 = 0; t0 < KMAX; t0 += 8) {
+        if (t0 < KP) {
+          bf16x8 vh, vm, vl;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int t = t0 + e;
+            const double pv = (t < k) ? x[t] : 0.0;
+            const __bf16 h = to_bf16((float)pv);
+            const double r1 = pv - (double)(float)h;
+            const __bf16 md = to_bf16((float)r1);
+            const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
+            vh[e] = h;
+            vm[e] = md;
+            vl[e] = lo;
+          }
+          *reinterpret_cast<bf16x8*>(o + t0) = vh;
+          *reinterpret_cast<bf16x8*>(o + KP + t0) = vm;
+          *reinterpret_cast<bf16x8*>(o + 2 * KP + t0) = vl;
         }
       }
-      for (int t = KMAX; t < KP; ++t) {
-        o[t] = to_bf16(0.0f);
-        o[KP + t] = to_bf16(0.0f);
-        o[2 * KP + t] = to_bf16(0.0f);
+      const bf16x8 zero8 = {};
+      for (int t0 = KMAX; t0 < KP; t0 += 8) {
+        *reinterpret_cast<bf16x8*>(o + t0) = zero8;
+        *reinterpret_cast<bf16x8*>(o + KP + t0) = zero8;
+        *reinterpret_cast<bf16x8*>(o + 2 * KP + t0) = zero8;
       }
     }
   }
