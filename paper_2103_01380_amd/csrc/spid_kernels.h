@@ -1591,6 +1591,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
         for (int mt = 0; mt < MTR; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
+          if (4 * s >= k) break;    // uniform: k-steps past the selected columns are zero
           const double pv = pc[4 * s];
 #pragma unroll
           for (int mt = 0; mt < MTR; ++mt) acc[mt] = mfma_f64(as[mt][s], pv, acc[mt]);
@@ -1660,10 +1661,12 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
   const int g = lane >> 4, c16 = lane & 15;
   const int64_t col_off = bi.y_off / l;
   const int ncols = ncols_g[it.blk];
+  const int ksn = (k + 31) >> 5;   // k-steps holding selected columns (the rest are zero)
   const __bf16* __restrict__ ptb = pt_g + col_off * 3 * KP;
   const int32_t* __restrict__ colb = cols_g + col_off;
 
-  // A operand: tile row c16, selected columns 32 ks + 8 g + v, three terms
+  // A operand: tile row c16, selected columns 32 ks + 8 g + v, three terms (k-steps past
+  // ksn are never read)
   bf16x8 at[kRcBfSubs][MTR][KS32][3];
   double a2 = 0.0, e2 = 0.0;
 #pragma unroll
@@ -1673,6 +1676,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
       const int64_t i = it.i0 + (int64_t)sb * kSub + wave * 16 * MTR + 16 * mt + c16;
 #pragma unroll
       for (int ks = 0; ks < KS32; ++ks) {
+        if (ks >= ksn) break;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
           const int t = 32 * ks + 8 * g + v;
@@ -1698,6 +1702,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
     constexpr int kVec = kRcBfCols * 3 * KP / 8;   // 16-byte pieces of the chunk
     for (int e = tid; e < kVec; e += kRcThreads) {
       const int q = e / (3 * KP / 8);
+      if (8 * (e % (KP / 8)) >= 32 * ksn) continue;   // terms of k-steps that are skipped
       bf16x8 v = bf16x8{};
       if (q < cc) v = *reinterpret_cast<const bf16x8*>(ptb + (int64_t)c0 * 3 * KP + (int64_t)e * 8);
       *reinterpret_cast<bf16x8*>(&pt[0][0][0] + (int64_t)e * 8) = v;
@@ -1730,6 +1735,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
         for (int mt = 0; mt < MTR; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < KS32; ++ks) {
+          if (ks >= ksn) break;     // uniform: zero terms add nothing
           const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(&pt[q0 + c16][0][32 * ks + 8 * g]);
           const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(&pt[q0 + c16][1][32 * ks + 8 * g]);
           const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(&pt[q0 + c16][2][32 * ks + 8 * g]);

@@ -677,6 +677,7 @@ __global__ __launch_bounds__(kRcThreads) void interp_mfma_kernel(
         for (int mt = 0; mt < MTR; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
+          if (4 * s >= k) break;    // uniform: k-steps past the selected columns are zero
           const double pv = pc[4 * s];
 #pragma unroll
           for (int mt = 0; mt < MTR; ++mt) acc[mt] = mfma_f64(as[mt][s], pv, acc[mt]);
