@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kTallThreads) void select_tall_kernel(
 // State per block (SplitState) and partial sums live in the workspace.
 // ---------------------------------------------------------------------------
 constexpr int kSplitRows = 256;
-constexpr int kSplitThreads = 256;
+constexpr int kSplitThreads = 1024;  // 16 waves: columns of a chunk in flight at once
 
 struct SplitState {
   double F2, nu0max, rss;
