@@ -128,6 +128,17 @@ WORKLOADS = {
                     "8^3 (m_b=2560), k=64, l=96, FP8-e4m3 sketch, one snapshot per update",
         kind="turbulence", N=256, B=32, n=384, fields=5, dt=0.02, a_dtype="f32",
         l=96, k_max=64, prec="fp8", lp_terms=3, stream=True, data_seed=2005, omega_seed=1005),
+    # counter runs of the BF16 sketch at the BF16 turbulence workload's block shape
+    # (20480 x 512, l = 48, k = 32) on 512 synthetic low-rank blocks (21.5 GB)
+    "lowrank_b512_bf16": Workload(
+        name="lowrank_b512_bf16",
+        description="512 blocks of 20480 x 512 (5 fields x 16^3, the BF16 turbulence block "
+                    "shape), rank 40 with Gaussian factors, sigma_i=10^(-i/4), FP32; k=32, "
+                    "l=48, BF16 sketch",
+        kind="lowrank", fields=5, a_dtype="f32", l=48, k_max=32, prec="bf16", lp_terms=2,
+        nblocks_uneven=512, data_seed=2007, omega_seed=1007,
+        extra={"shape": {"edge_range": (16, 16), "n_range": (512, 512), "rank_range": (40, 40)},
+               "orthonormal": False}),
     # the paper's own sketch (Section 2, Algorithms 2-3; Section 5.2.3's 64^3 single
     # partition at interval 3): coarse-grid subsample, trilinear single-pass error
     "tgv64_single_sub3": Workload(
@@ -412,13 +423,14 @@ def lowrank_shapes(w: Workload, nblocks: int | None = None, edge_range=(4, 32),
 
 
 def lowrank_blocks(w: Workload, shapes: UnevenBatch, device="cpu", out_dtype=torch.float32,
-                   decay=0.25) -> torch.Tensor:
+                   decay=0.25, orthonormal=True) -> torch.Tensor:
     """Flat buffer of the uneven low-rank batch.
 
     A_b = U_b diag(sigma) V_b^T with U_b (m_b x r_b) and V_b (n_b x r_b)
     orthonormal (QR of Gaussian matrices, double precision) and
     sigma_i = 10^(-decay * i), i = 0..r_b-1.  Block b is column-major
-    m_b x n_b at ``shapes.offsets[b]``.
+    m_b x n_b at ``shapes.offsets[b]``.  ``orthonormal=False`` uses the
+    Gaussian factors scaled by 1/sqrt(rows) instead (nearly orthonormal, no QR).
     """
     dev = torch.device(device)
     out = torch.empty(shapes.total, device=dev, dtype=out_dtype)
@@ -426,8 +438,12 @@ def lowrank_blocks(w: Workload, shapes: UnevenBatch, device="cpu", out_dtype=tor
     gen.manual_seed(w.data_seed)
     for b in range(len(shapes.m)):
         m, n, r = int(shapes.m[b]), int(shapes.n[b]), int(shapes.rank[b])
-        U = torch.linalg.qr(torch.randn((m, r), generator=gen, device=dev, dtype=torch.float64))[0]
-        V = torch.linalg.qr(torch.randn((n, r), generator=gen, device=dev, dtype=torch.float64))[0]
+        U = torch.randn((m, r), generator=gen, device=dev, dtype=torch.float64)
+        V = torch.randn((n, r), generator=gen, device=dev, dtype=torch.float64)
+        if orthonormal:
+            U, V = torch.linalg.qr(U)[0], torch.linalg.qr(V)[0]
+        else:
+            U, V = U / math.sqrt(m), V / math.sqrt(n)
         sig = 10.0 ** (-decay * torch.arange(r, device=dev, dtype=torch.float64))
         Ab = (U * sig[None, :]) @ V.T                            # m x n
         o = int(shapes.offsets[b])
@@ -445,9 +461,10 @@ def generate(w: Workload, device="cpu", progress=None):
         A = turbulence_blocks(w, device=device, progress=progress,
                               out_dtype=torch.float32 if w.a_dtype == "f32" else torch.float64)
     elif w.kind == "lowrank":
-        sh = lowrank_shapes(w)
+        sh = lowrank_shapes(w, **w.extra.get("shape", {}))
         A = lowrank_blocks(w, sh, device=device,
-                           out_dtype=torch.float32 if w.a_dtype == "f32" else torch.float64)
+                           out_dtype=torch.float32 if w.a_dtype == "f32" else torch.float64,
+                           orthonormal=w.extra.get("orthonormal", True))
         return A, sh.m, sh.n, sh.offsets
     else:
         raise ValueError(w.kind)
