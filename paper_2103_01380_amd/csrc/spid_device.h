@@ -198,6 +198,16 @@ __device__ __forceinline__ void omega_pair_rounded(uint64_t seed, uint32_t bkey,
 // float already has 8 significant bits).
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 
+// Two floats rounded to nearest-even bfloat16, packed: x0 in bits 0-15, x1 in
+// bits 16-31 (one v_cvt_pk_bf16_f32).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float x0, float x1) {
+  bf16x2 p;
+  p[0] = (__bf16)x0;
+  p[1] = (__bf16)x1;
+  return __builtin_bit_cast(uint32_t, p);
+}
+
 // e4m3 byte of a float (hardware conversion, round to nearest even).
 __device__ __forceinline__ uint32_t to_e4m3_byte(float x) {
   return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xffu;

@@ -375,6 +375,36 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
     for (int u = 0; u < TN; ++u)
       load_pieces_full<TA, 2, 4, 16, VEC>(ln.cb[u], k0 + 4 * g, ln.ok[u], a[u]);
   };
+  // A split into `terms` (1..3) bfloat16 terms and the MFMAs of every term.
+  // Each pair of values is rounded by one packed conversion; the terms'
+  // values are read back from its halves by shifts, and the last term forms
+  // no remainder (uniform branches on the term count).
+  auto split_mfma = [&](const bf16x8 (&oa)[MT], float (&a)[TN][8]) {
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      float rem[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rem[e] = a[u][e];
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        if (h >= terms) break;
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = pack_bf16x2(rem[2 * e], rem[2 * e + 1]);
+        if (h + 1 < terms) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            rem[2 * e] -= __uint_as_float(w[e] << 16);
+            rem[2 * e + 1] -= __uint_as_float(w[e] & 0xffff0000u);
+          }
+        }
+        const bf16x8 bt = __builtin_bit_cast(bf16x8, i32x4{(int)w[0], (int)w[1], (int)w[2],
+                                                            (int)w[3]});
+#pragma unroll
+        for (int t = 0; t < MT; ++t) acc[t][u] = mfma_bf16(oa[t], bt, acc[t][u]);
+      }
+    }
+  };
   auto mfma_chunk = [&](const __bf16* __restrict__ omb, float (&a)[TN][8]) {
     bf16x8 oa[MT];
 #pragma unroll
@@ -384,23 +414,7 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
       const bf16x4 hi = *reinterpret_cast<const bf16x4*>(orow + 16);
       oa[t] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     }
-#pragma unroll
-    for (int u = 0; u < TN; ++u) {
-      float rem[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) rem[e] = a[u][e];
-      for (int h = 0; h < terms; ++h) {
-        bf16x8 bt;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const __bf16 x = to_bf16(rem[e]);
-          bt[e] = x;
-          rem[e] = rem[e] - (float)x;
-        }
-#pragma unroll
-        for (int t = 0; t < MT; ++t) acc[t][u] = mfma_bf16(oa[t], bt, acc[t][u]);
-      }
-    }
+    split_mfma(oa, a);
   };
 
   const int64_t nfull = (it.r1 - it.r0) / kKC;
