@@ -515,7 +515,8 @@ __device__ __forceinline__ int fp8_block_exp(float amax) {
 // 32-row K block): e4m3 bytes packed 4 per int with each half scaled by its
 // block's power of two, the residual left for the next term, and the E8M0
 // scale byte of K block g that this lane supplies to the MFMA.
-__device__ __forceinline__ i32x8 fp8_term(float res[32], int g, int& scale_byte) {
+__device__ __forceinline__ i32x8 fp8_term(float res[32], int g, int& scale_byte,
+                                          bool rem_needed) {
   float h0 = 0.0f, h1 = 0.0f;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -538,20 +539,32 @@ __device__ __forceinline__ i32x8 fp8_term(float res[32], int g, int& scale_byte)
   i32x8 out;
 #pragma unroll
   for (int hh = 0; hh < 2; ++hh) {
-    const int ex = hh ? e_second : e_first;
-    const float down = ldexpf(1.0f, -ex), up = ldexpf(1.0f, ex);
+    const float down = ldexpf(1.0f, -(hh ? e_second : e_first));
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      uint32_t word = 0;
+      const int e = 16 * hh + 4 * w;
+      const int p0 = __builtin_amdgcn_cvt_pk_fp8_f32(res[e] * down, res[e + 1] * down, 0, false);
+      const int p1 =
+          __builtin_amdgcn_cvt_pk_fp8_f32(res[e + 2] * down, res[e + 3] * down, 0, false);
+      out[4 * hh + w] = (int)(((uint32_t)p0 & 0xffffu) | ((uint32_t)p1 << 16));
+    }
+  }
+  // what the term represents is taken off the residual (not after the last
+  // term): bytes 0-1 and 2-3 of each word back to single precision in pairs
+  if (rem_needed) {
 #pragma unroll
-      for (int b = 0; b < 4; b += 2) {
-        const int e = 16 * hh + 4 * w + b;
-        const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(res[e] * down, res[e + 1] * down, 0, false);
-        res[e] -= __builtin_amdgcn_cvt_f32_fp8(pk, 0) * up;
-        res[e + 1] -= __builtin_amdgcn_cvt_f32_fp8(pk, 1) * up;
-        word |= ((uint32_t)pk & 0xffffu) << (8 * b);
+    for (int hh = 0; hh < 2; ++hh) {
+      const float up = ldexpf(1.0f, hh ? e_second : e_first);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int e = 16 * hh + 4 * w;
+        const f32x2 q0 = __builtin_amdgcn_cvt_pk_f32_fp8(out[4 * hh + w], false);
+        const f32x2 q1 = __builtin_amdgcn_cvt_pk_f32_fp8(out[4 * hh + w], true);
+        res[e] -= q0[0] * up;
+        res[e + 1] -= q0[1] * up;
+        res[e + 2] -= q1[0] * up;
+        res[e + 3] -= q1[1] * up;
       }
-      out[4 * hh + w] = (int)word;
     }
   }
   return out;
@@ -606,7 +619,7 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
     for (int u = 0; u < TN; ++u) {
       for (int h = 0; h < terms; ++h) {
         int sb;
-        const i32x8 bt = fp8_term(a[u], g, sb);
+        const i32x8 bt = fp8_term(a[u], g, sb, h + 1 < terms);
 #pragma unroll
         for (int t = 0; t < MT; ++t) acc[t][u] = mfma_fp8_scaled(oa[t], bt, acc[t][u], 127, sb);
       }
@@ -718,7 +731,7 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_resident_kernel(
       }
       for (int h = 0; h < terms; ++h) {
         int sb;
-        const i32x8 bt = fp8_term(a, g, sb);
+        const i32x8 bt = fp8_term(a, g, sb, h + 1 < terms);
 #pragma unroll
         for (int t = 0; t < MT; ++t) acc[t] = mfma_fp8_scaled(oa[t], bt, acc[t], 127, sb);
       }
