@@ -8,6 +8,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "spid.hip")
 OUT = os.path.join(HERE, "libspid.so")
+# stand-alone attainable-rate probe (MFMA, HBM, sketch-matrix generation)
+PROBE_SRC = os.path.join(HERE, "csrc", "rate_probe.hip")
+PROBE_OUT = os.path.join(HERE, "rate_probe")
 ARCH = "gfx950"
 
 FLAGS = [
@@ -25,15 +28,21 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = OUT + ".tmp"
-    cmd = [hipcc(), *FLAGS, SRC, "-o", tmp]
+def _compile(flags, src, out, verbose):
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *flags, src, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stderr[-8000:])
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    _compile(FLAGS, SRC, OUT, verbose)
+    exe_flags = [f for f in FLAGS if f not in ("-shared", "-fPIC")]
+    _compile(exe_flags, PROBE_SRC, PROBE_OUT, verbose)
     return OUT
 
 
