@@ -1,6 +1,6 @@
-// Attainable-rate probe for MI355X (gfx950): the ceilings against which the
-// library's kernels are judged, measured with the library's own device
-// helpers.  Not part of the library; a stand-alone program:
+// Attainable-rate probe for MI355X (gfx950): the ceilings to compare the
+// library's kernels with, measured with the library's own device helpers.
+// Not part of the library; a stand-alone program:
 //
 //   paper_2103_01380_amd/rate_probe
 //
