@@ -5,8 +5,10 @@ update over every column, column selection, coefficients and the
 reconstruction-error pass.  The timed region starts with the snapshot matrices
 already in HBM.  Prints one JSON line (rank 0).
 
-Default workload: analytic TGV 128^3 + 1e-6 noise, 512 blocks of 16^3
-(m_b = 12288 FP64), 256 snapshots, tolerance 1e-8 with k <= 32, l = 42.
+Default workload: the turbulence-like 256^3 field (rho, u, v, w, p; FP32),
+4096 blocks of 16^3 (m_b = 20480), 512 snapshots, k = 32, l = 48, bfloat16
+sketch with FP32 accumulation and FP64 selection / coefficients, timed beside
+the plain FP64 method on the same resident data.
 """
 from __future__ import annotations
 
@@ -32,7 +34,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="tgv128_b512_f64")
+    ap.add_argument("--workload", default="turb256_b4096_bf16")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-max-blocks", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -50,7 +52,33 @@ def parse():
                          "snapshots on one stream, the sketch updates run on another")
     ap.add_argument("--solver-substeps", type=int, default=1,
                     help="--insitu: solver steps per stored snapshot")
+    ap.add_argument("--profile-region", action="store_true",
+                    help="mark only the timed steps for rocprofv3 --selected-regions "
+                         "(roctxProfilerResume / roctxProfilerPause): data generation, tuning, "
+                         "the oracle and the FP64 comparison are left out of the profile")
     return ap.parse_args()
+
+
+class ProfileRegion:
+    """roctxProfilerResume(0) / roctxProfilerPause(0) around the timed steps when
+    --profile-region is given (no-op otherwise)."""
+
+    def __init__(self, on: bool):
+        self.lib = None
+        if on:
+            import ctypes
+            self.lib = ctypes.CDLL(os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib",
+                                                "librocprofiler-sdk-roctx.so"))
+            self.lib.roctxProfilerResume.argtypes = [ctypes.c_uint64]
+            self.lib.roctxProfilerPause.argtypes = [ctypes.c_uint64]
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(0)
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(0)
 
 
 def log(args, *a):
@@ -98,7 +126,11 @@ def main():
                   a_dtype=w.a_dtype, prec=w.prec, lp_terms=w.lp_terms, device=dev, tuning=tuning,
                   grids=w.grids() if coarse else None, ts_windows=w.ts_windows, ts_k1=w.ts_k1)
     ctx.bind(A, offsets=off)
+    region = ProfileRegion(args.profile_region)
+    region.resume()
     ms_step, stage, wall = time_steps(args, ctx, w, stream)
+    torch.cuda.synchronize()
+    region.pause()
     graph_ms = None
     if args.graph:
         # one step captured into a HIP graph, replayed for the same number of steps
@@ -127,6 +159,9 @@ def main():
         rel_err = ctx.rel_error()
         ms_rows = m
     cf = float((m * n.astype(np.int64)).sum() / max(1, (kk * (ms_rows + n)).sum()))
+    # bytes-CF: the stored skeleton in the data's type, the coefficients in FP64
+    cf_bytes = float(nbytes / max(1, (kk * (ms_rows * w.elem_bytes + n.astype(np.int64) * 8)).sum()))
+    blocks_err = per_block_errors(ctx, coarse)
     log(args, f"stage ms: sketch {stage[0]:.3f} select {stage[1]:.3f} coeffs {stage[2]:.3f} "
               f"recon {stage[3]:.3f}; step {ms_step:.3f} ms; rel err {rel_err:.3e}")
 
@@ -177,7 +212,10 @@ def main():
         "rel_error": rel_err,
         "error_gate_1e-3": bool(rel_err <= 1e-3),
         "compression_factor": round(cf, 3),
+        "compression_factor_bytes": round(cf_bytes, 3),
         "k_mean": float(kk.mean()),
+        "k_histogram": k_histogram(kk),
+        "block_rel_error": blocks_err,
         "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 4),
         "stage_ms": {k: round(v, 4) for k, v in zip(STAGES, stage)},
         "launch_shapes": ctx.tuning,
@@ -193,6 +231,24 @@ def main():
 
 
 STAGES = ("sketch", "select", "coeffs", "reconstruct")
+
+
+def per_block_errors(ctx, coarse):
+    """Distribution of the per-block relative errors sqrt(err2_b / nrm2_b) (the gate
+    uses the global error; Section 5.1 reports field-level errors)."""
+    e2 = (ctx.err2_interp if coarse else ctx.err2).cpu().numpy()
+    n2 = ctx.nrm2.cpu().numpy()
+    e = np.sqrt(e2 / np.where(n2 > 0, n2, 1.0))
+    q = np.quantile(e, [0.5, 0.9, 0.99])
+    return {"max": float(e.max()), "argmax_block": int(e.argmax()), "p50": float(q[0]),
+            "p90": float(q[1]), "p99": float(q[2]), "mean": float(e.mean()),
+            "blocks_over_1e-3": int((e > 1e-3).sum())}
+
+
+def k_histogram(kk):
+    """Selected ranks: {k: number of blocks}."""
+    vals, cnt = np.unique(kk, return_counts=True)
+    return {str(int(v)): int(c) for v, c in zip(vals, cnt)}
 
 
 def insitu(args, w, dev):
@@ -574,12 +630,32 @@ def cpu_baseline(args, w, A, m, n, off, ctx):
               f"rel err {res.rel_error:.3e}")
     agree = oracle_agreement(w, A, m, n, off, ctx, idx, res)
     log(args, f"oracle agreement: {agree}")
+    total_bytes = int((m * n.astype(np.int64)).sum()) * w.elem_bytes
+    # one core: the first blocks of the sample, about a tenth of the multi-thread time
+    one = None
+    if not w.ts_windows:
+        n1 = int(max(1, min(len(idx), round(0.1 * args.cpu_seconds / max(per_block * threads,
+                                                                           1e-9)))))
+        sel1 = idx[:n1]
+        blocks1 = [si.block_view(A, m, n, off, int(b)) for b in sel1]
+        t0 = time.perf_counter()
+        oracle.run_batch(blocks1, l=w.l, k_max=w.k_max, seed=w.omega_seed, tol=w.tol,
+                         prec=prec[w.prec], nthreads=1,
+                         grids=None if grids is None else grids[sel1])
+        dt1c = time.perf_counter() - t0
+        b1c = int(sum(b.shape[0] * b.shape[1] for b in blocks1)) * w.elem_bytes
+        one = {"value": round(b1c / dt1c / 1e9, 5), "unit": "GB/s", "cores": 1,
+               "blocks": int(n1), "seconds": round(dt1c, 2),
+               "full_config_s_extrapolated": round(total_bytes / (b1c / dt1c), 1)}
+        log(args, f"cpu oracle, one core: {n1} blocks in {dt1c:.1f}s")
     return {"value": round(sbytes / dt / 1e9, 5), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{len(idx)} of {nb} blocks (seeded choice), whole method per block "
                       f"(sketch, select, coefficients, error), {dt:.1f} s wall on {threads} "
                       f"threads" + ("; the oracle also forms the SubID error (a second pass "
-                                    "over A)" if w.subsample else "")}, agree
+                                    "over A)" if w.subsample else ""),
+            "full_config_s_extrapolated": round(total_bytes / (sbytes / dt), 1),
+            "one_core": one}, agree
 
 
 if __name__ == "__main__":

@@ -1,20 +1,25 @@
-"""Build ``libspid.so`` for gfx950 with hipcc (in-tree, no JIT cache)."""
+"""Build ``libspid.so`` for gfx950 with hipcc (in-tree, no JIT cache).
+
+The library's kernels are instantiated in several translation units (one per
+stage, the sketch one per arithmetic) that compile in parallel and link into
+one shared object."""
 from __future__ import annotations
 
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "spid.hip")
+CSRC = os.path.join(HERE, "csrc")
+SOURCES = ["spid.hip", "spid_sketch_f64.hip", "spid_sketch_bf16.hip", "spid_sketch_fp8.hip",
+           "spid_select.hip", "spid_recon.hip"]
 OUT = os.path.join(HERE, "libspid.so")
-# stand-alone attainable-rate probe (MFMA, HBM, sketch-matrix generation)
-PROBE_SRC = os.path.join(HERE, "csrc", "rate_probe.hip")
-PROBE_OUT = os.path.join(HERE, "rate_probe")
+OBJ_DIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # keep hipcc from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
@@ -28,21 +33,25 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(flags, src, out, verbose):
-    tmp = out + ".tmp"
-    cmd = [hipcc(), *flags, src, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + r.stderr[-8000:])
-    os.replace(tmp, out)
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + r.stderr[-8000:])
 
 
-def build(verbose: bool = False) -> str:
-    _compile(FLAGS, SRC, OUT, verbose)
-    exe_flags = [f for f in FLAGS if f not in ("-shared", "-fPIC")]
-    _compile(exe_flags, PROBE_SRC, PROBE_OUT, verbose)
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs = [os.path.join(OBJ_DIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    cmds = [[hipcc(), *FLAGS, "-c", os.path.join(CSRC, s), "-o", o]
+            for s, o in zip(SOURCES, objs)]
+    jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    tmp = OUT + ".tmp"
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    os.replace(tmp, OUT)
     return OUT
 
 

@@ -2,27 +2,20 @@
 // validation, workspace planning, work-item tables and kernel dispatch for
 // gfx950.  Every compute entry point only enqueues kernels on the caller's
 // stream.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
-#include <string>
-#include <vector>
 
-#include "../../include/spid.h"
-#include "spid_kernels.h"
-#include "spid_subsample.h"
-#include "spid_two_stage.h"
+#include "spid_internal.h"
 
 using namespace spid;
 
-namespace {
+namespace spid_host {
 
+namespace {
 thread_local std::string g_err;
+}
 
 spid_status fail(spid_status st, const char* fmt, ...) {
   char buf[512];
@@ -34,139 +27,19 @@ spid_status fail(spid_status st, const char* fmt, ...) {
   return st;
 }
 
-constexpr int kMaxL = 128;
-constexpr int kMaxLCoarse = 1 << 22;               // coarse-grid sketch rows
-constexpr int kMaxK = 96;
-constexpr int kMaxN = 1024;
-constexpr int kStreamNW = 8;                       // waves of a one-snapshot sketch workgroup
-constexpr int kStreamGroup = 16 * kStreamNW;       // blocks per group (one 16-column tile per wave)
-constexpr int kStreamMaxW = 4;                     // updates of up to this many snapshots use it
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// Selection kernel choice for a sketch height l and widest block max_n.
-struct SelShape {
-  int LMAX = 16, CPT = 1, sel_thr = 64, sel_rr = 0, sel_pair = 0, sel_tall = 0;
-  size_t sel_lds = 0;
-};
-
-// tile/template choices for a descriptor
-struct Shape {
-  int MT;        // 16-row MFMA tiles covering l
-  int TN;        // 16-column tiles per wave in the sketch
-  int NW;        // waves per sketch workgroup (columns per workgroup = 16 * NW * TN)
-  SelShape sel;  // selection kernel
-  int KMAX;      // register skeleton width in the error pass
-  int KS;        // k-steps of 4 selected columns in the matrix-core error pass
-  int MTR;       // 16-row MFMA tiles per wave in the error pass
-  int RC_SUB;    // rows of an error-pass sub-tile (4 waves x 16 * MTR)
-  int RPI;       // sub-tiles per error-pass work item
-  int PCAP;      // non-skeleton columns whose coefficients are staged in LDS at once
-  int rc_bf16;   // 1: split-bfloat16 error pass (FP32 data, low-precision sketch)
-  int KS32;      // k-steps of 32 selected columns in the split-bfloat16 error pass
-  int sk_items;  // target number of sketch work items
-};
-
-int pick_mt(int l) {
-  const int t = (l + 15) / 16;
-  if (t <= 4) return t;
-  if (t <= 6) return 6;
-  return 8;
+spid_status hip_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SPID_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return SPID_OK;
 }
 
-int pick_lmax(int l) {
-  const int opts[] = {16, 32, 48, 56, 64, 96, 128};
-  for (int o : opts)
-    if (l <= o) return o;
-  return 128;
+bool allow_lds(const void* kernel, size_t bytes) {
+  if (bytes <= 65536) return true;
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+         hipSuccess;
 }
 
-int pick_kmax(int k) {
-  const int opts[] = {8, 16, 32, 48, 64, 96};
-  for (int o : opts)
-    if (k <= o) return o;
-  return 96;
-}
-
-// false: no register/LDS kernel fits and the global-memory kernel is not allowed
-bool pick_sel(int l, int max_n, bool allow_tall, SelShape& sh) {
-  sh = SelShape{};
-  sh.LMAX = pick_lmax(l);
-  sh.sel_tall = (allow_tall && l > kMaxL) ? 1 : 0;
-  sh.CPT = (max_n > 512) ? 2 : 1;
-  {
-    int need = (max_n + sh.CPT - 1) / sh.CPT;
-    sh.sel_thr = std::max(64, (need + 63) / 64 * 64);
-  }
-  if (sh.sel_tall) {
-    // coarse sketch taller than the register/LDS kernels take: global memory
-  } else if (sh.LMAX > 56 && max_n <= 384) {
-    // two lanes per column, every row in registers
-    sh.sel_pair = l <= 64 ? 32 : (l <= 96 ? 48 : 64);
-    sh.sel_thr = std::max(64, (2 * max_n + 63) / 64 * 64);
-  } else if (sh.LMAX > 56 || max_n > 512) {
-    // hybrid: one column per thread, RR rows in registers, the rest in LDS
-    sh.CPT = 1;
-    sh.sel_thr = std::max(64, (max_n + 63) / 64 * 64);
-    const int rr_opts[] = {48, 32, 16};
-    for (int rr : rr_opts) {
-      if (sh.sel_thr > 512 && rr > 32) continue;   // 1024 threads: 128 registers per lane
-      const size_t lds = sizeof(double) * (size_t)std::max(0, l - rr) * sh.sel_thr;
-      if (lds <= 150 * 1024) {
-        sh.sel_rr = rr;
-        sh.sel_lds = lds;
-        break;
-      }
-    }
-    if (sh.sel_rr == 0) {
-      if (!allow_tall) return false;
-      sh.sel_tall = 1;
-    }
-  }
-  return true;
-}
-
-// Workspace plan (sizes in bytes, offsets from the workspace base)
-struct Plan {
-  Shape sh;
-  int ydt;                       // 0: Y in FP64, 1: Y in FP32
-  std::vector<BlkInfo> blk;
-  std::vector<SkItem> items;
-  std::vector<int32_t> split_blocks;
-  std::vector<RcItem> rc;
-  std::vector<int64_t> rc_first;
-  // one-snapshot updates: blocks ordered by m (perm), groups of kStreamGroup
-  // equal-m blocks x K ranges (sitems), heads of groups with several K ranges
-  bool st_ok = false;
-  std::vector<int32_t> perm;
-  std::vector<SkItem> sitems;
-  std::vector<int32_t> sheads;
-  std::vector<int32_t> ritems;   // FP8 resident-Omega items: (first stream item, count, stride)
-  int64_t st_part_elems = 0;
-  // coarse-grid sketch: block grids (the single-pass error uses the error-pass items)
-  bool coarse = false;
-  std::vector<GridInfo> grid;
-  int64_t sum_mc = 0;
-  // a few very tall coarse sketches: selection with the rows split over workgroups
-  bool split = false;
-  int split_nch = 0;
-  std::vector<int64_t> split_off;   // per block: offset of its chunk partials (nch * n_b)
-  int64_t split_elems = 0;
-  // modified two-stage ID: window table (nblocks * nwin), stage-2 table (nblocks)
-  int ts_nwin = 0, ts_k1 = 0, ts_kmax1 = 8;
-  SelShape ts_sel1, ts_sel2;
-  std::vector<BlkInfo> ts_win, ts_blk2;
-  int64_t ts_n2sum = 0;
-  int64_t sum_n = 0, sum_m = 0, part_elems = 0;
-  int max_n = 0, max_split_n = 0;
-  size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
-      off_st, off_rcpart, off_perm, off_sitems, off_sheads, off_ritems, off_pt, off_cols, off_ncols,
-      off_grid, off_W, off_spoff, off_spnorm, off_spdot, off_spused, off_spstate, off_spbad,
-      off_tswin, off_tsblk2, off_tsR1, off_tsP1, off_tsS1, off_tsk1, off_tsst1,
-      off_tsY2, off_tsW2, off_tsR2, off_tsP2, off_tsS2, off_tsk2, off_tsst2, total;
-};
+namespace {
 
 spid_status validate(const spid_desc* d) {
   if (!d) return fail(SPID_EINVAL, "descriptor is NULL");
@@ -612,348 +485,22 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
 }
 
 }  // namespace
+}  // namespace spid_host
 
-struct spid_ctx {
-  spid_desc desc;
-  std::vector<int64_t> m;
-  std::vector<int32_t> n;
-  Plan plan;
-  char* ws = nullptr;
-  bool bound = false;
-  bool selected = false;
-  bool coeffs_done = false;        // spid_coeffs ran after the last selection
-  bool two_stage = false;          // the last selection was spid_select_two_stage
-  bool all_vec = false;            // every block's column starts are 16-byte aligned
-  bool all_vec4 = false;           // ... and every m is a multiple of 4
-  std::vector<uint8_t> covered;   // per column index: sketched since bind
-  template <typename T>
-  T* at(size_t off) const {
-    return reinterpret_cast<T*>(ws + off);
-  }
-};
+using namespace spid_host;
 
 namespace {
 
-spid_status hip_check(const char* what) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(SPID_EHIP, "%s: %s", what, hipGetErrorString(e));
-  return SPID_OK;
+void sketch_batch_prec(spid_ctx* c, int j0, int j1, hipStream_t s) {
+  if (c->plan.ydt == 0) sketch_batch_f64(c, j0, j1, s);
+  else if (c->desc.prec == SPID_SK_FP8E4M3) sketch_batch_fp8(c, j0, j1, s);
+  else sketch_batch_bf16(c, j0, j1, s);
 }
 
-// Kernels whose dynamic LDS exceeds 64 KiB must opt in before every launch
-// (cheap host call, no stream work, safe under graph capture).
-bool allow_lds(const void* kernel, size_t bytes) {
-  if (bytes <= 65536) return true;
-  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
-         hipSuccess;
-}
-
-// ---- sketch dispatch
-// ST: one-snapshot update of snapshot jst over the block groups
-template <typename TA, int MT, int TN, int NW, bool VEC, bool ST>
-void launch_sketch_k(spid_ctx* c, int j0, int j1, int jst, hipStream_t s) {
-  const Plan& p = c->plan;
-  const size_t nitems = ST ? p.sitems.size() : p.items.size();
-  const SkItem* items = c->at<SkItem>(ST ? p.off_sitems : p.off_items);
-  const int32_t* perm = c->at<int32_t>(p.off_perm);
-  dim3 grid((unsigned)nitems), block(64 * NW);
-  // shapes the planner can choose (others are not instantiated): FP64 TN <= 2
-  // (2 only for MT <= 4), FP8 TN = 1, BF16 TN = 4 only for MT < 6
-  constexpr bool kF64 = TN == 1 || (TN == 2 && MT <= 4);
-  constexpr bool kFP8 = TN == 1;
-  constexpr bool kBF16 = TN <= 2 || MT < 6;
-  if (p.ydt == 0) {
-    if constexpr (kF64)
-    hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN, NW, VEC, ST>), grid, block, 0, s,
-                       c->at<BlkInfo>(p.off_blk), items, c->desc.l, c->desc.seed,
-                       c->desc.omega_per_block, j0, j1, perm, jst, c->at<double>(p.off_Y),
-                       c->at<double>(p.off_part));
-  } else if (c->desc.prec == SPID_SK_FP8E4M3) {
-    if constexpr (kFP8)
-    hipLaunchKernelGGL((sketch_fp8_kernel<TA, MT, TN, NW, VEC, ST>), grid, block, 0, s,
-                       c->at<BlkInfo>(p.off_blk), items, c->desc.l, c->desc.seed,
-                       c->desc.omega_per_block, j0, j1, perm, jst, c->desc.lp_terms,
-                       c->at<float>(p.off_Y), c->at<float>(p.off_part));
-  } else {
-    if constexpr (kBF16)
-    hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, NW, VEC, ST>), grid, block, 0, s,
-                       c->at<BlkInfo>(p.off_blk), items, c->desc.l, c->desc.seed,
-                       c->desc.omega_per_block, j0, j1, perm, jst, c->desc.lp_terms,
-                       c->at<float>(p.off_Y), c->at<float>(p.off_part));
-  }
-}
-
-// instantiated (TN, NW) pairs: FP64 path 8 waves x 1-2 tiles or 4 waves x 1
-// tile; low-precision paths 8 waves x 1-4 tiles or 4 waves x 1 tile
-template <typename TA, int MT, int TN>
-void launch_sketch_t(spid_ctx* c, int j0, int j1, hipStream_t s) {
-  const bool vec = c->all_vec;
-  if (c->plan.sh.NW == 8) {
-    if (vec) launch_sketch_k<TA, MT, TN, 8, true, false>(c, j0, j1, 0, s);
-    else launch_sketch_k<TA, MT, TN, 8, false, false>(c, j0, j1, 0, s);
-  } else {
-    if constexpr (TN == 1) {
-      if (vec) launch_sketch_k<TA, MT, 1, 4, true, false>(c, j0, j1, 0, s);
-      else launch_sketch_k<TA, MT, 1, 4, false, false>(c, j0, j1, 0, s);
-    }
-  }
-}
-
-template <typename TA, int MT>
-void launch_sketch_mt(spid_ctx* c, int j0, int j1, hipStream_t s) {
-  switch (c->plan.sh.TN) {
-    case 1: launch_sketch_t<TA, MT, 1>(c, j0, j1, s); break;
-    case 2: launch_sketch_t<TA, MT, 2>(c, j0, j1, s); break;
-    default: launch_sketch_t<TA, MT, 4>(c, j0, j1, s); break;
-  }
-}
-
-template <typename TA, int MT, bool VEC>
-bool launch_fp8_resident(spid_ctx* c, int j, hipStream_t s) {
-  const Plan& p = c->plan;
-  const size_t lds = (size_t)kResChunks * MT * 16 * kOm8Stride;
-  auto kern = sketch_fp8_resident_kernel<TA, MT, kStreamNW, VEC>;
-  if (!allow_lds((const void*)kern, lds)) return false;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(p.ritems.size() / 3)), dim3(64 * kStreamNW), lds, s,
-                     c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_sitems),
-                     c->at<int32_t>(p.off_ritems), c->desc.l, c->desc.seed,
-                     c->at<int32_t>(p.off_perm), j, c->desc.lp_terms, c->at<float>(p.off_Y),
-                     c->at<float>(p.off_part));
-  return true;
-}
-
-template <typename TA, int MT>
-bool launch_sketch_stream_mt(spid_ctx* c, int j, hipStream_t s) {
-  if (c->desc.prec == SPID_SK_FP8E4M3 && !c->plan.ritems.empty())
-    return c->all_vec ? launch_fp8_resident<TA, MT, true>(c, j, s)
-                      : launch_fp8_resident<TA, MT, false>(c, j, s);
-  if (c->all_vec) launch_sketch_k<TA, MT, 1, kStreamNW, true, true>(c, 0, 0, j, s);
-  else launch_sketch_k<TA, MT, 1, kStreamNW, false, true>(c, 0, 0, j, s);
-  return true;
-}
-
-template <typename TA>
-void launch_sketch_a(spid_ctx* c, int j0, int j1, hipStream_t s) {
-  switch (c->plan.sh.MT) {
-    case 1: launch_sketch_mt<TA, 1>(c, j0, j1, s); break;
-    case 2: launch_sketch_mt<TA, 2>(c, j0, j1, s); break;
-    case 3: launch_sketch_mt<TA, 3>(c, j0, j1, s); break;
-    case 4: launch_sketch_mt<TA, 4>(c, j0, j1, s); break;
-    case 6: launch_sketch_mt<TA, 6>(c, j0, j1, s); break;
-    default: launch_sketch_mt<TA, 8>(c, j0, j1, s); break;
-  }
-}
-
-template <typename TA>
-bool launch_sketch_stream_a(spid_ctx* c, int j, hipStream_t s) {
-  switch (c->plan.sh.MT) {
-    case 1: return launch_sketch_stream_mt<TA, 1>(c, j, s);
-    case 2: return launch_sketch_stream_mt<TA, 2>(c, j, s);
-    case 3: return launch_sketch_stream_mt<TA, 3>(c, j, s);
-    case 4: return launch_sketch_stream_mt<TA, 4>(c, j, s);
-    case 6: return launch_sketch_stream_mt<TA, 6>(c, j, s);
-    default: return launch_sketch_stream_mt<TA, 8>(c, j, s);
-  }
-}
-
-// ---- selection dispatch
-// One selection launch: a block table (blocks, or temporal windows of blocks),
-// the sketch it points into and where R, S, k and the status go.
-template <typename TY>
-struct SelJob {
-  const BlkInfo* blks;
-  int nblocks, l, k_max;
-  double tol, rank_floor;
-  const TY* Y;
-  double* W;           // working copy of the global-memory kernel (same offsets as Y)
-  double* R;
-  int32_t *S, *k, *st;
-  SelShape sh;
-};
-
-template <typename TY, int LMAX>
-void launch_select_l(const SelJob<TY>& j, hipStream_t s) {
-  hipLaunchKernelGGL((select_kernel<TY, LMAX, 1>), dim3(j.nblocks), dim3(j.sh.sel_thr), 0, s,
-                     j.blks, j.l, j.k_max, j.tol, j.rank_floor, j.Y, j.R, j.S, j.k, j.st);
-}
-
-template <typename TY, int RR, int MAXTHR>
-bool launch_select_hybrid_t(const SelJob<TY>& j, hipStream_t s) {
-  auto kern = select_hybrid_kernel<TY, RR, MAXTHR>;
-  if (!allow_lds((const void*)kern, j.sh.sel_lds)) return false;
-  hipLaunchKernelGGL(kern, dim3(j.nblocks), dim3(j.sh.sel_thr), j.sh.sel_lds, s, j.blks, j.l,
-                     j.k_max, j.tol, j.rank_floor, j.Y, j.R, j.S, j.k, j.st);
-  return true;
-}
-
-template <typename TY, int RPT>
-void launch_select_pair_t(const SelJob<TY>& j, hipStream_t s) {
-  hipLaunchKernelGGL((select_pair_kernel<TY, RPT>), dim3(j.nblocks), dim3(j.sh.sel_thr), 0, s,
-                     j.blks, j.l, j.k_max, j.tol, j.rank_floor, j.Y, j.R, j.S, j.k, j.st);
-}
-
-template <typename TY>
-bool launch_select_job(const SelJob<TY>& j, hipStream_t s) {
-  const SelShape& sh = j.sh;
-  if (sh.sel_tall) {
-    if constexpr (std::is_same<TY, double>::value) {
-      auto launch = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(j.nblocks), dim3(kTallThreads), 0, s, j.blks, j.l,
-                           j.k_max, j.tol, j.rank_floor, j.Y, j.W, j.R, j.S, j.k, j.st);
-      };
-      if (j.l <= 4 * kWave) launch(select_tall_kernel<4>);
-      else if (j.l <= 8 * kWave) launch(select_tall_kernel<8>);
-      else if (j.l <= 16 * kWave) launch(select_tall_kernel<16>);
-      else launch(select_tall_kernel<0>);
-      return true;
-    }
-    return false;   // tall sketches are double precision
-  }
-  if (sh.sel_pair) {
-    if (sh.sel_pair == 32) launch_select_pair_t<TY, 32>(j, s);
-    else if (sh.sel_pair == 48) launch_select_pair_t<TY, 48>(j, s);
-    else launch_select_pair_t<TY, 64>(j, s);
-    return true;
-  }
-  if (sh.sel_rr) {
-    if (sh.sel_thr > 512) {
-      if (sh.sel_rr == 32) return launch_select_hybrid_t<TY, 32, 1024>(j, s);
-      return launch_select_hybrid_t<TY, 16, 1024>(j, s);
-    }
-    if (sh.sel_rr == 48) return launch_select_hybrid_t<TY, 48, 512>(j, s);
-    if (sh.sel_rr == 32) return launch_select_hybrid_t<TY, 32, 512>(j, s);
-    return launch_select_hybrid_t<TY, 16, 512>(j, s);
-  }
-  switch (sh.LMAX) {
-    case 16: launch_select_l<TY, 16>(j, s); break;
-    case 32: launch_select_l<TY, 32>(j, s); break;
-    case 48: launch_select_l<TY, 48>(j, s); break;
-    default: launch_select_l<TY, 56>(j, s); break;
-  }
-  return true;
-}
-
-// Row-split selection of a few very tall coarse sketches: init, then three launches per
-// step and a final pivot launch (blocks that stopped return at once).
-bool launch_select_split(spid_ctx* c, hipStream_t s) {
-  const Plan& p = c->plan;
-  const spid_desc& d = c->desc;
-  const int nb = d.nblocks;
-  const BlkInfo* blks = c->at<BlkInfo>(p.off_blk);
-  const int64_t* poff = c->at<int64_t>(p.off_spoff);
-  double* pnorm = c->at<double>(p.off_spnorm);
-  double* pdot = c->at<double>(p.off_spdot);
-  unsigned char* used = c->at<unsigned char>(p.off_spused);
-  SplitState* st = c->at<SplitState>(p.off_spstate);
-  int32_t* bad = c->at<int32_t>(p.off_spbad);
-  double* W = c->at<double>(p.off_W);
-  double* R = c->at<double>(p.off_R);
-  int32_t* S = c->at<int32_t>(p.off_S);
-  int32_t* k = c->at<int32_t>(p.off_k);
-  int32_t* sts = c->at<int32_t>(p.off_st);
-  const dim3 g2((unsigned)p.split_nch, (unsigned)nb);
-  hipLaunchKernelGGL(split_clear_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, nb, bad);
-  hipLaunchKernelGGL(split_init_kernel, g2, dim3(kSplitThreads), 0, s, blks, d.l,
-                     c->at<double>(p.off_Y), W, poff, pnorm, bad);
-  const int kcap = std::min(d.k_max, std::min(d.l, p.max_n));
-  for (int step = 0; step <= kcap; ++step) {
-    hipLaunchKernelGGL(split_pivot_kernel, dim3(nb), dim3(kSplitThreads), 0, s, blks, d.l,
-                       d.k_max, d.tol, d.rank_floor, step, poff, pnorm, used, st, bad, R, S, k,
-                       sts);
-    if (step == kcap) break;
-    hipLaunchKernelGGL(split_dot_kernel, g2, dim3(kSplitThreads), 0, s, blks, d.l, poff, st,
-                       used, W, pdot);
-    hipLaunchKernelGGL(split_update_kernel, g2, dim3(kSplitThreads), 0, s, blks, d.l, step, poff,
-                       st, used, pdot, W, pnorm, R);
-  }
-  return true;
-}
-
-template <typename TY>
-bool launch_select_ctx(spid_ctx* c, hipStream_t s) {
-  const Plan& p = c->plan;
-  if constexpr (std::is_same<TY, double>::value) {
-    if (p.split) return launch_select_split(c, s);
-  }
-  SelJob<TY> j{c->at<BlkInfo>(p.off_blk), c->desc.nblocks, c->desc.l, c->desc.k_max,
-               c->desc.tol, c->desc.rank_floor, c->at<TY>(p.off_Y), c->at<double>(p.off_W),
-               c->at<double>(p.off_R), c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
-               c->at<int32_t>(p.off_st), p.sh.sel};
-  return launch_select_job<TY>(j, s);
-}
-
-// ---- reconstruction dispatch (matrix-core kernels)
-// one attribute call per kernel instantiation for dynamic LDS above 64 KiB
-template <typename TA, int KS, int MTR>
-bool launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
-  const Plan& p = c->plan;
-  const size_t lds = sizeof(double) * p.sh.PCAP * 4 * KS;
-  auto launch = [&](auto kern) {
-    if (!allow_lds((const void*)kern, lds)) return false;
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), lds, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.k_max,
-                       p.sh.PCAP, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
-                       static_cast<TA*>(skel), c->at<double>(p.off_rcpart));
-    return true;
-  };
-  if (c->all_vec4) return launch(recon_mfma_kernel<TA, KS, MTR, true>);
-  return launch(recon_mfma_kernel<TA, KS, MTR, false>);
-}
-
-// single-precision data on the mixed path: split-bfloat16 error pass
-template <int KS32, int MTR>
-bool launch_recon_bf16_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
-  (void)P;   // the split coefficients written by spid_coeffs are used
-  const Plan& p = c->plan;
-  auto launch = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), 0, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.l,
-                       c->desc.k_max, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
-                       c->at<__bf16>(p.off_pt), c->at<int32_t>(p.off_cols),
-                       c->at<int32_t>(p.off_ncols), static_cast<float*>(skel),
-                       c->at<double>(p.off_rcpart));
-  };
-  if (c->all_vec4) launch(recon_bf16x3_kernel<KS32, MTR, true>);
-  else launch(recon_bf16x3_kernel<KS32, MTR, false>);
-  return true;
-}
-
-template <typename TA>
-bool launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
-  const Shape& sh = c->plan.sh;
-  if constexpr (sizeof(TA) == 4) {
-    if (sh.rc_bf16) {
-      switch (sh.KS32) {
-        case 1: return launch_recon_bf16_t<1, 2>(c, P, skel, s);
-        case 2: return launch_recon_bf16_t<2, 2>(c, P, skel, s);
-        default: return launch_recon_bf16_t<3, 2>(c, P, skel, s);
-      }
-    }
-  }
-  switch (sh.KS) {
-    case 1: return launch_recon_t<TA, 1, 4>(c, P, skel, s);
-    case 2: return launch_recon_t<TA, 2, 4>(c, P, skel, s);
-    case 4: return launch_recon_t<TA, 4, 4>(c, P, skel, s);
-    case 8: return launch_recon_t<TA, 8, 4>(c, P, skel, s);
-    case 12: return launch_recon_t<TA, 12, 2>(c, P, skel, s);
-    case 16: return launch_recon_t<TA, 16, 2>(c, P, skel, s);
-    default: return launch_recon_t<TA, 24, 2>(c, P, skel, s);
-  }
-}
-
-template <int KMAX>
-bool launch_coeffs_t(spid_ctx* c, double* P, hipStream_t s) {
-  const Plan& p = c->plan;
-  const size_t lds = sizeof(double) * (size_t)c->desc.k_max * c->desc.k_max;
-  if (!allow_lds((const void*)coeffs_kernel<KMAX>, lds)) return false;
-  const bool bf = p.sh.rc_bf16 != 0;
-  hipLaunchKernelGGL((coeffs_kernel<KMAX>), dim3(c->desc.nblocks), dim3(kCoThreads), lds, s,
-                     c->at<BlkInfo>(p.off_blk), c->desc.l, c->desc.k_max, c->at<double>(p.off_R),
-                     c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
-                     bf ? c->at<__bf16>(p.off_pt) : nullptr, 32 * p.sh.KS32,
-                     bf ? c->at<int32_t>(p.off_cols) : nullptr,
-                     bf ? c->at<int32_t>(p.off_ncols) : nullptr);
-  return true;
+bool sketch_stream_prec(spid_ctx* c, int j, hipStream_t s) {
+  if (c->plan.ydt == 0) return sketch_stream_f64(c, j, s);
+  if (c->desc.prec == SPID_SK_FP8E4M3) return sketch_stream_fp8(c, j, s);
+  return sketch_stream_bf16(c, j, s);
 }
 
 }  // namespace
@@ -1123,8 +670,7 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
   if (p.st_ok && j1 - j0 <= kStreamMaxW) {
     // a few snapshots: one launch per snapshot with the blocks as MFMA columns
     for (int j = j0; j < j1; ++j) {
-      const bool ok = c->desc.a_dtype == SPID_A_F64 ? launch_sketch_stream_a<double>(c, j, s)
-                                                    : launch_sketch_stream_a<float>(c, j, s);
+      const bool ok = sketch_stream_prec(c, j, s);
       if (!ok) return fail(SPID_EHIP, "stream sketch: cannot reserve the Omega LDS");
       spid_status st = hip_check("stream sketch kernel launch");
       if (st != SPID_OK) return st;
@@ -1152,10 +698,7 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
     c->coeffs_done = false;
     return SPID_OK;
   }
-  if (c->desc.a_dtype == SPID_A_F64)
-    launch_sketch_a<double>(c, j0, j1, s);
-  else
-    launch_sketch_a<float>(c, j0, j1, s);
+  sketch_batch_prec(c, j0, j1, s);
   spid_status st = hip_check("sketch kernel launch");
   if (st != SPID_OK) return st;
   if (!p.split_blocks.empty()) {
@@ -1185,8 +728,7 @@ extern "C" spid_status spid_select(spid_ctx* c, int32_t* d_k, int32_t* d_S, int3
     if (!c->covered[j])
       return fail(SPID_ESTATE, "spid_select: sketch column %d has not been computed", j);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool ok = c->plan.ydt == 0 ? launch_select_ctx<double>(c, s)
-                                    : launch_select_ctx<float>(c, s);
+  const bool ok = launch_select_ctx(c, s);
   if (!ok) return fail(SPID_EHIP, "select: cannot reserve the selection LDS");
   spid_status st = hip_check("select kernel launch");
   if (st != SPID_OK) return st;
@@ -1213,15 +755,7 @@ extern "C" spid_status spid_coeffs(spid_ctx* c, double* d_P, void* stream) {
     return fail(SPID_ESTATE,
                 "spid_coeffs after spid_select_two_stage (which writes the coefficients)");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  bool ok = false;
-  switch (c->plan.sh.KMAX) {
-    case 8: ok = launch_coeffs_t<8>(c, d_P, s); break;
-    case 16: ok = launch_coeffs_t<16>(c, d_P, s); break;
-    case 32: ok = launch_coeffs_t<32>(c, d_P, s); break;
-    case 48: ok = launch_coeffs_t<48>(c, d_P, s); break;
-    case 64: ok = launch_coeffs_t<64>(c, d_P, s); break;
-    default: ok = launch_coeffs_t<96>(c, d_P, s); break;
-  }
+  const bool ok = launch_coeffs_ctx(c, d_P, s);
   if (!ok) return fail(SPID_EHIP, "coeffs: cannot reserve the R11 LDS");
   c->coeffs_done = true;
   return hip_check("coeffs kernel launch");
@@ -1234,8 +768,7 @@ extern "C" spid_status spid_reconstruct(spid_ctx* c, const double* d_P, double* 
   if (!c->coeffs_done) return fail(SPID_ESTATE, "spid_reconstruct before spid_coeffs");
   const Plan& p = c->plan;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool ok = c->desc.a_dtype == SPID_A_F64 ? launch_recon_a<double>(c, d_P, d_skeleton, s)
-                                                 : launch_recon_a<float>(c, d_P, d_skeleton, s);
+  const bool ok = launch_recon_ctx(c, d_P, d_skeleton, s);
   if (!ok) return fail(SPID_EHIP, "reconstruct: cannot reserve the coefficient LDS");
   spid_status st = hip_check("reconstruct kernel launch");
   if (st != SPID_OK) return st;
@@ -1246,79 +779,6 @@ extern "C" spid_status spid_reconstruct(spid_ctx* c, const double* d_P, double* 
 }
 
 namespace {
-
-template <typename TA, int KS, int MTR>
-bool launch_interp_t(spid_ctx* c, const double* P, hipStream_t s) {
-  const Plan& p = c->plan;
-  const size_t lds = sizeof(double) * p.sh.PCAP * 4 * KS;
-  auto launch = [&](auto kern) {
-    if (!allow_lds((const void*)kern, lds)) return false;
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), lds, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<GridInfo>(p.off_grid),
-                       c->at<RcItem>(p.off_rc), c->desc.l, c->desc.k_max, p.sh.PCAP,
-                       c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
-                       c->at<double>(p.off_Y), P, c->at<double>(p.off_rcpart));
-    return true;
-  };
-  if (c->all_vec4) return launch(interp_mfma_kernel<TA, KS, MTR, true>);
-  return launch(interp_mfma_kernel<TA, KS, MTR, false>);
-}
-
-template <typename TA>
-bool launch_interp_a(spid_ctx* c, const double* P, void* cskel, hipStream_t s) {
-  bool ok;
-  switch (c->plan.sh.KS) {
-    case 1: ok = launch_interp_t<TA, 1, 4>(c, P, s); break;
-    case 2: ok = launch_interp_t<TA, 2, 4>(c, P, s); break;
-    case 4: ok = launch_interp_t<TA, 4, 4>(c, P, s); break;
-    case 8: ok = launch_interp_t<TA, 8, 4>(c, P, s); break;
-    case 12: ok = launch_interp_t<TA, 12, 2>(c, P, s); break;
-    case 16: ok = launch_interp_t<TA, 16, 2>(c, P, s); break;
-    default: ok = launch_interp_t<TA, 24, 2>(c, P, s); break;
-  }
-  if (!ok) return false;
-  if (cskel) {
-    const Plan& p = c->plan;
-    int mcmax = 1;
-    for (const GridInfo& g : p.grid) mcmax = std::max(mcmax, g.mc);
-    const int64_t per_blk = (int64_t)mcmax * c->desc.k_max;
-    dim3 grid((unsigned)std::min<int64_t>((per_blk + 255) / 256, 1 << 20),
-              (unsigned)std::min(c->desc.nblocks, 65535));
-    hipLaunchKernelGGL((coarse_skeleton_kernel<TA>), grid, dim3(256), 0, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<GridInfo>(p.off_grid), c->desc.nblocks,
-                       c->desc.l, c->desc.k_max, c->at<int32_t>(p.off_S),
-                       c->at<int32_t>(p.off_k), c->at<double>(p.off_Y), static_cast<TA*>(cskel));
-  }
-  return true;
-}
-
-}  // namespace
-
-namespace {
-
-template <int KMAX>
-bool launch_coeffs_job(const BlkInfo* blks, int nblocks, int l, int k_max, const double* R,
-                       const int32_t* S, const int32_t* k, double* P, hipStream_t s) {
-  const size_t lds = sizeof(double) * (size_t)k_max * k_max;
-  if (!allow_lds((const void*)coeffs_kernel<KMAX>, lds)) return false;
-  hipLaunchKernelGGL((coeffs_kernel<KMAX>), dim3(nblocks), dim3(kCoThreads), lds, s, blks, l,
-                     k_max, R, S, k, P, (__bf16*)nullptr, 32, (int32_t*)nullptr,
-                     (int32_t*)nullptr);
-  return true;
-}
-
-bool launch_coeffs_any(int kmax_t, const BlkInfo* blks, int nblocks, int l, int k_max,
-                       const double* R, const int32_t* S, const int32_t* k, double* P,
-                       hipStream_t s) {
-  switch (kmax_t) {
-    case 8: return launch_coeffs_job<8>(blks, nblocks, l, k_max, R, S, k, P, s);
-    case 16: return launch_coeffs_job<16>(blks, nblocks, l, k_max, R, S, k, P, s);
-    case 32: return launch_coeffs_job<32>(blks, nblocks, l, k_max, R, S, k, P, s);
-    case 48: return launch_coeffs_job<48>(blks, nblocks, l, k_max, R, S, k, P, s);
-    case 64: return launch_coeffs_job<64>(blks, nblocks, l, k_max, R, S, k, P, s);
-    default: return launch_coeffs_job<96>(blks, nblocks, l, k_max, R, S, k, P, s);
-  }
-}
 
 template <typename TY>
 spid_status two_stage_t(spid_ctx* c, double* d_P, hipStream_t s) {
@@ -1412,9 +872,7 @@ extern "C" spid_status spid_reconstruct_interp(spid_ctx* c, const double* d_P, d
   if (!c->coeffs_done) return fail(SPID_ESTATE, "spid_reconstruct_interp before spid_coeffs");
   const Plan& p = c->plan;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool ok = c->desc.a_dtype == SPID_A_F64
-                      ? launch_interp_a<double>(c, d_P, d_coarse_skeleton, s)
-                      : launch_interp_a<float>(c, d_P, d_coarse_skeleton, s);
+  const bool ok = launch_interp_ctx(c, d_P, d_coarse_skeleton, s);
   if (!ok) return fail(SPID_EHIP, "reconstruct_interp: cannot reserve the coefficient LDS");
   spid_status st = hip_check("interpolated error kernel launch");
   if (st != SPID_OK) return st;

@@ -1326,7 +1326,7 @@ __global__ __launch_bounds__(MAXTHR) void select_hybrid_kernel(
 }
 
 // Copy per-block selection results to the caller's arrays.
-__global__ void select_export_kernel(int nblocks, int k_max, const int32_t* __restrict__ S_ws,
+static __global__ void select_export_kernel(int nblocks, int k_max, const int32_t* __restrict__ S_ws,
                                      const int32_t* __restrict__ k_ws,
                                      const int32_t* __restrict__ st_ws, int32_t* d_k,
                                      int32_t* d_S, int32_t* d_status) {
@@ -1807,7 +1807,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
 // contiguous range [first[b], first[b+1]).  One wave per block: lane t sums
 // items first + t, first + t + 64, ... in order, then a butterfly over the
 // lanes; the order is fixed, so repeated runs give identical bits.
-__global__ __launch_bounds__(kWave) void recon_reduce_kernel(
+static __global__ __launch_bounds__(kWave) void recon_reduce_kernel(
     int nblocks, const int64_t* __restrict__ first, const double* __restrict__ part,
     double* __restrict__ err2, double* __restrict__ nrm2) {
   const int b = blockIdx.x;

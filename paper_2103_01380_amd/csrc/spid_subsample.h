@@ -352,13 +352,13 @@ struct SplitState {
 };
 
 // clears the per-block non-finite flags before split_init_kernel
-__global__ void split_clear_kernel(int nblocks, int32_t* __restrict__ bad) {
+static __global__ void split_clear_kernel(int nblocks, int32_t* __restrict__ bad) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < nblocks) bad[b] = 0;
 }
 
 // copy of the sketch, non-finite check, partial column norms of each chunk
-__global__ __launch_bounds__(kSplitThreads) void split_init_kernel(
+static __global__ __launch_bounds__(kSplitThreads) void split_init_kernel(
     const BlkInfo* __restrict__ blks, int l, const double* __restrict__ Y, double* __restrict__ W,
     const int64_t* __restrict__ poff, double* __restrict__ pnorm, int32_t* __restrict__ bad) {
   const int b = blockIdx.y, c = blockIdx.x;
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kSplitThreads) void split_init_kernel(
 }
 
 // pivot of step s (s == kcap_b: the final tolerance test only)
-__global__ __launch_bounds__(kSplitThreads) void split_pivot_kernel(
+static __global__ __launch_bounds__(kSplitThreads) void split_pivot_kernel(
     const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor, int s,
     const int64_t* __restrict__ poff, const double* __restrict__ pnorm,
     unsigned char* __restrict__ used, SplitState* __restrict__ st, const int32_t* __restrict__ bad,
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(kSplitThreads) void split_pivot_kernel(
 }
 
 // dot products of step s: chunk rows of q formed in place, partial q.W(:,j)
-__global__ __launch_bounds__(kSplitThreads) void split_dot_kernel(
+static __global__ __launch_bounds__(kSplitThreads) void split_dot_kernel(
     const BlkInfo* __restrict__ blks, int l, const int64_t* __restrict__ poff,
     const SplitState* __restrict__ st, const unsigned char* __restrict__ used,
     double* __restrict__ W, double* __restrict__ pdot) {
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(kSplitThreads) void split_dot_kernel(
 
 // update of step s: d_j in a fixed order, W(:,j) -= d_j q on the chunk rows,
 // chunk partial norms; chunk 0 records R(s, j)
-__global__ __launch_bounds__(kSplitThreads) void split_update_kernel(
+static __global__ __launch_bounds__(kSplitThreads) void split_update_kernel(
     const BlkInfo* __restrict__ blks, int l, int s, const int64_t* __restrict__ poff,
     const SplitState* __restrict__ st, const unsigned char* __restrict__ used,
     const double* __restrict__ pdot, double* __restrict__ W, double* __restrict__ pnorm,

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void ts_gather_kernel(
 // and P(:, j) = C^1(:, slots of window w) C_w(:, j - c_w) for column j of
 // window w; rows past k are zero.  A window with a non-finite sketch makes
 // the block NONFINITE with k = 0.  One workgroup per block.
-__global__ __launch_bounds__(256) void ts_combine_kernel(
+static __global__ __launch_bounds__(256) void ts_combine_kernel(
     const BlkInfo* __restrict__ blks, const BlkInfo* __restrict__ win,
     const BlkInfo* __restrict__ blk2, int nwin, int k1, int k_max,
     const int32_t* __restrict__ S1, const int32_t* __restrict__ k1w,
