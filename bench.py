@@ -259,41 +259,23 @@ def insitu(args, w, dev):
     The overhead is the extra wall time over the solver alone; the selection,
     coefficients and error pass run once after the last step.
 
-    Stand-in solver: linear advection-diffusion of the three velocity components
-    of the Taylor-Green field on the periodic N^3 grid, second-order central
-    differences, explicit Euler (torch element-wise operations: the application,
-    not the compression path)."""
+    Stand-in solver: ``spid_inputs.StandInSolver`` (linear advection-diffusion of
+    the three Taylor-Green velocity components, the application, not the
+    compression path)."""
     import torch
     import paper_2103_01380_amd as sp
     assert w.kind == "tgv" and not w.subsample and not w.ts_windows
+    import spid_inputs as si
     N, B = w.N, w.B
     E = N // B
     nb = B ** 3
-    h = 2.0 * math.pi / N
-    g = torch.arange(N, device=dev, dtype=torch.float64) * h
-    Z, Yc, X = torch.meshgrid(g, g, g, indexing="ij")            # [z, y, x], x fastest
-    F0 = torch.stack([torch.sin(X) * torch.cos(Yc) * torch.cos(Z),
-                      -torch.cos(X) * torch.sin(Yc) * torch.cos(Z),
-                      torch.zeros_like(X)])
-    vel = (1.0, 0.5, 0.25)                                      # advecting velocity (x, y, z)
-    dt = 0.2 * h
-    nu = w.nu
-
-    def solver_step(F):
-        lap = -6.0 * F
-        adv = torch.zeros_like(F)
-        for d, c in zip((3, 2, 1), vel):                         # x, y, z axes of [f, z, y, x]
-            fp = torch.roll(F, -1, d)
-            fm = torch.roll(F, 1, d)
-            lap += fp + fm
-            adv += (c / (2.0 * h)) * (fp - fm)
-        F += dt * (nu / (h * h) * lap - adv)
-
+    solver = si.StandInSolver(N, B, w.nu, dev)
+    F0 = solver.F0
+    solver_step = solver.step
     A = torch.empty((nb, w.n, 3 * E ** 3), dtype=torch.float64, device=dev)
 
     def store(F, j):
-        V = F.reshape(3, B, E, B, E, B, E).permute(1, 3, 5, 0, 2, 4, 6)   # bz, by, bx, f, z, y, x
-        A[:, j, :] = V.reshape(nb, 3 * E ** 3)
+        solver.store(F, A, j)
 
     m = np.full(nb, 3 * E ** 3, dtype=np.int64)
     n = np.full(nb, w.n, dtype=np.int32)

@@ -140,12 +140,16 @@ typedef struct {
  *   sk_items target number of sketch work items (64..65536): blocks are
  *            split along their rows (K) until about this many items exist
  *   rc_rpi   error-pass row sub-tiles per work item, 1..16 (double-precision
- *            error pass only; the split-bfloat16 pass uses one)            */
+ *            error pass only; the split-bfloat16 pass uses one)
+ *   st_groups one-snapshot FP8 updates: groups of 128 equal-m blocks that share
+ *            one resident sketch-matrix range per work item, 1..16 (default:
+ *            enough to leave about one work item per compute unit, at most 8) */
 typedef struct {
   int32_t sk_tn;
   int32_t sk_nw;
   int32_t sk_items;
   int32_t rc_rpi;
+  int32_t st_groups;
 } spid_tuning;
 
 /* Bytes of device workspace a descriptor needs (0 if the descriptor is

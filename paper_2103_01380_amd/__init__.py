@@ -71,6 +71,7 @@ class spid_tuning(ctypes.Structure):
         ("sk_nw", ctypes.c_int32),
         ("sk_items", ctypes.c_int32),
         ("rc_rpi", ctypes.c_int32),
+        ("st_groups", ctypes.c_int32),
     ]
 
     def as_dict(self):

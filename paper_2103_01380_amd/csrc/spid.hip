@@ -126,6 +126,8 @@ spid_status validate_tuning(const spid_desc* d, const spid_tuning* t, int mt) {
     return fail(SPID_EINVAL, "tuning: sk_items must be 0 or 64..65536 (got %d)", t->sk_items);
   if (t->rc_rpi < 0 || t->rc_rpi > 16)
     return fail(SPID_EINVAL, "tuning: rc_rpi must be 0..16 (got %d)", t->rc_rpi);
+  if (t->st_groups < 0 || t->st_groups > 16)
+    return fail(SPID_EINVAL, "tuning: st_groups must be 0..16 (got %d)", t->st_groups);
   return SPID_OK;
 }
 
@@ -397,7 +399,9 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
       // that about one item per compute unit (256) exists: more groups per item
       // amortise the Omega generation further (measured on 32768 blocks of 2560 rows:
       // 2 groups per item 87 ms per 384 snapshots, 4 groups 68 ms, 8 groups 95 ms)
-      const int64_t gw = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)p.sitems.size() / 256));
+      int64_t gw = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)p.sitems.size() / 256));
+      if (tune && tune->st_groups) gw = tune->st_groups;
+      sh.st_groups = (int)gw;
       size_t i = 0;
       while (i < p.sitems.size()) {
         // run of consecutive groups with the same m and K split
@@ -529,6 +533,7 @@ extern "C" spid_status spid_get_tuning(const spid_ctx* c, spid_tuning* out) {
   out->sk_nw = sh.NW;
   out->sk_items = sh.sk_items;
   out->rc_rpi = sh.rc_bf16 ? 1 : sh.RPI;
+  out->st_groups = sh.st_groups;
   return SPID_OK;
 }
 

@@ -58,6 +58,7 @@ struct Shape {
   int rc_bf16;   // 1: split-bfloat16 error pass (FP32 data, low-precision sketch)
   int KS32;      // k-steps of 32 selected columns in the split-bfloat16 error pass
   int sk_items;  // target number of sketch work items
+  int st_groups = 0;  // one-snapshot FP8 updates: block groups per resident-Omega item
 };
 
 inline int pick_mt(int l) {

@@ -52,7 +52,8 @@ __global__ __launch_bounds__(256) void ts_gather_kernel(
   }
 }
 
-// Final pivots S = I_U(I_1) (columns of A, stage-2 pivot order), k, status,
+// Final pivots S = I_U(I_1) (columns of A, stage-2 pivot order), k, status
+// (the stage-2 selection's, as on the compact union of the stage-1 pivots),
 // and P(:, j) = C^1(:, slots of window w) C_w(:, j - c_w) for column j of
 // window w; rows past k are zero.  A window with a non-finite sketch makes
 // the block NONFINITE with k = 0.  One workgroup per block.
@@ -64,15 +65,18 @@ static __global__ __launch_bounds__(256) void ts_combine_kernel(
     const int32_t* __restrict__ S2, const int32_t* __restrict__ k2,
     const int32_t* __restrict__ st2, const double* __restrict__ P2, double* __restrict__ P,
     int32_t* __restrict__ S_ws, int32_t* __restrict__ k_ws, int32_t* __restrict__ st_ws) {
-  __shared__ int bad_s;
+  __shared__ int bad_s, union_s;
   const int b = blockIdx.x;
   const BlkInfo bi = blks[b];
   const int n = bi.n;
   if (threadIdx.x == 0) {
-    int bad = 0;
-    for (int w = 0; w < nwin; ++w)
+    int bad = 0, nu = 0;
+    for (int w = 0; w < nwin; ++w) {
       if (st1[(int64_t)b * nwin + w] == 2) bad = 1;
+      nu += k1w[(int64_t)b * nwin + w];
+    }
     bad_s = bad;
+    union_s = nu;
   }
   __syncthreads();
   const int kk = bad_s ? 0 : k2[b];
@@ -87,7 +91,14 @@ static __global__ __launch_bounds__(256) void ts_combine_kernel(
   }
   if (threadIdx.x == 0) {
     k_ws[b] = kk;
-    st_ws[b] = bad_s ? 2 : st2[b];
+    // Stage 2 runs on nwin * k1 slots, the ones past a window's pivot count
+    // zero.  Having taken every stage-1 pivot, it meets a zero pivot and
+    // reports RANK_DEFICIENT; on the compact union of the stage-1 skeletons
+    // (whose size caps the selection) the same pivots end the selection with
+    // OK, and that is the status reported.
+    int st = bad_s ? 2 : st2[b];
+    if (st == 1 && kk > 0 && kk == union_s) st = 0;
+    st_ws[b] = st;
   }
   const double* __restrict__ P2b = P2 + blk2[b].p_off;
   for (int64_t e = threadIdx.x; e < (int64_t)n * k_max; e += 256) {

@@ -540,3 +540,41 @@ def turbulence_block_direct(w: Workload, b: int, modes: Modes | None = None,
         Gs = np.sin(th) @ ind
         out[f * E ** 3:(f + 1) * E ** 3] = offsets[f] + Gc @ Ct + Gs @ St
     return np.asfortranarray(out.astype(out_dtype))
+
+
+# ----------------------------------------------------------------------------- in-situ stand-in
+class StandInSolver:
+    """Stand-in for the paper's flow solver in the in-situ measurements: the three
+    Taylor-Green velocity components on the periodic N^3 grid advanced by linear
+    advection-diffusion (second-order central differences, explicit Euler) with
+    torch element-wise operations on the GPU.  ``store`` writes the current field
+    as snapshot column j of the block-major data matrix [B^3, n, 3 E^3] (the store
+    task that precedes a sketch update).  This is the application, not the
+    compression method."""
+
+    def __init__(self, N: int, B: int, nu: float, device, vel=(1.0, 0.5, 0.25), cfl=0.2):
+        self.N, self.B, self.E = N, B, N // B
+        self.h = 2.0 * math.pi / N
+        self.nu, self.vel = nu, vel
+        self.dt = cfl * self.h
+        g = torch.arange(N, device=device, dtype=torch.float64) * self.h
+        Z, Yc, X = torch.meshgrid(g, g, g, indexing="ij")        # [z, y, x], x fastest
+        self.F0 = torch.stack([torch.sin(X) * torch.cos(Yc) * torch.cos(Z),
+                               -torch.cos(X) * torch.sin(Yc) * torch.cos(Z),
+                               torch.zeros_like(X)])
+
+    def step(self, F):
+        h = self.h
+        lap = -6.0 * F
+        adv = torch.zeros_like(F)
+        for d, c in zip((3, 2, 1), self.vel):                     # x, y, z axes of [f, z, y, x]
+            fp = torch.roll(F, -1, d)
+            fm = torch.roll(F, 1, d)
+            lap += fp + fm
+            adv += (c / (2.0 * h)) * (fp - fm)
+        F += self.dt * (self.nu / (h * h) * lap - adv)
+
+    def store(self, F, A, j):
+        B, E = self.B, self.E
+        V = F.reshape(3, B, E, B, E, B, E).permute(1, 3, 5, 0, 2, 4, 6)   # bz, by, bx, f, z, y, x
+        A[:, j, :] = V.reshape(B ** 3, 3 * E ** 3)

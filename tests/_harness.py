@@ -25,6 +25,7 @@ class GpuResult:
     skel: list | None = None
     ierr2: np.ndarray | None = None      # single-pass (interpolated) error, coarse grids
     cskel: list | None = None            # coarse skeleton B(:,S), coarse grids
+    tuning: dict | None = None           # launch shapes in effect
 
     @property
     def rel_interp_error(self):
@@ -37,7 +38,7 @@ class GpuResult:
 
 def gpu_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=False,
             prec="f64", lp_terms=1, skeleton=False, stream_columns=False, lda_pad=0,
-            grids=None):
+            grids=None, tuning=None):
     """Run the four stages on the GPU for host column-major blocks.  ``grids``: the
     coarse-grid sketch (SubID) plus the single-pass error and coarse skeleton."""
     import paper_2103_01380_amd as sp
@@ -59,7 +60,7 @@ def gpu_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=Fal
         prec = "subsample"
     ctx = sp.SPID(m, n, l, k_max, tol=tol, rank_floor=rank_floor, seed=seed,
                   omega_per_block=omega_per_block, a_dtype=a_dtype, prec=prec,
-                  lp_terms=lp_terms, grids=grids)
+                  lp_terms=lp_terms, grids=grids, tuning=tuning)
     l = ctx.l
     ctx.bind(A, offsets=off, lda=lda)
     if stream_columns:
@@ -97,7 +98,8 @@ def gpu_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=Fal
         cskel = [cs[co[b]:co[b] + ctx.mc[b] * k_max].reshape(k_max, ctx.mc[b]).T
                  for b in range(len(blocks))]
     res = GpuResult(Ys, ctx.S.cpu().numpy(), ctx.k.cpu().numpy(), ctx.status.cpu().numpy(), Ps,
-                    ctx.err2.cpu().numpy(), ctx.nrm2.cpu().numpy(), skel, ierr2, cskel)
+                    ctx.err2.cpu().numpy(), ctx.nrm2.cpu().numpy(), skel, ierr2, cskel,
+                    dict(ctx.tuning))
     ctx.close()
     return res
 

@@ -99,6 +99,7 @@ def _tuned_bytes(tuning, **kw):
 @pytest.mark.parametrize("tuning", [
     None, {}, dict(sk_tn=1, sk_nw=4), dict(sk_tn=2, sk_nw=8, sk_items=1024),
     dict(sk_items=64), dict(sk_items=65536), dict(rc_rpi=1), dict(rc_rpi=16),
+    dict(st_groups=1), dict(st_groups=16),
 ])
 def test_valid_launch_shapes_are_accepted(tuning):
     nb, err = _tuned_bytes(tuning)
@@ -116,6 +117,8 @@ def test_valid_launch_shapes_are_accepted(tuning):
     (dict(sk_items=10), {}, "sk_items"),
     (dict(rc_rpi=17), {}, "rc_rpi"),
     (dict(rc_rpi=-1), {}, "rc_rpi"),
+    (dict(st_groups=17), {}, "st_groups"),
+    (dict(st_groups=-2), {}, "st_groups"),
 ])
 def test_invalid_launch_shapes_are_rejected(tuning, kw, msg):
     nb, err = _tuned_bytes(tuning, **kw)

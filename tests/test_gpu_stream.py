@@ -15,7 +15,7 @@ import torch
 
 import oracle
 import spid_inputs as si
-from _harness import compare, gpu_run, oracle_run
+from _harness import compare, gpu_run, matched_prefix, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -79,18 +79,64 @@ def test_stream_fp8_turbulence_8cubed_blocks():
     g = gpu_run(blocks, w.l, w.k_max, w.omega_seed, prec="fp8", lp_terms=w.lp_terms,
                 stream_columns=True)
     o = oracle_run(blocks, w.l, w.k_max, w.omega_seed, prec="fp8")
-    num = den = 0.0
+    e_gpu, r2, pre = _fp8_gates(blocks, g, o)
+    print(f"stream fp8 e_gpu={e_gpu:.3e} e_oracle={o.rel_error:.3e} R2={r2:.3e} "
+          f"min prefix={min(pre)}")
+    assert e_gpu <= 1e-3 and r2 <= 1e-3
+
+
+def _fp8_gates(blocks, g, o, gamma=1e-2, y_rtol=2e-4):
+    """FP8 sketch against the oracle (same e4m3 sketch matrix): sketch within the
+    split-term rounding, the pivots of every step whose oracle gap exceeds gamma,
+    the status where the whole selection is decided, and the error gates
+    (e_gpu = ||A - A(:,S~)P~|| / ||A||, R2 = ||A(:,S~)P~ - A(:,S)P|| / ||A||)."""
+    num = den = rd = 0.0
+    prefixes = []
     for b, A in enumerate(blocks):
         Ad = A.astype(np.float64)
         scale = np.linalg.norm(o.Y[b], axis=0).max()
-        assert np.abs(g.Y[b] - o.Y[b]).max() <= 1e-3 * scale, b
-        kg = int(g.k[b])
+        assert np.abs(g.Y[b] - o.Y[b]).max() <= y_rtol * scale, (b, np.abs(g.Y[b] - o.Y[b]).max() / scale)
+        s_star, ok = matched_prefix(g.S[b], o.S[b], o.gaps[b], g.k[b], o.k[b], gamma)
+        assert ok, (b, s_star, g.S[b][:s_star], o.S[b][:s_star])
+        prefixes.append(s_star)
+        kg, ko = int(g.k[b]), int(o.k[b])
+        if s_star == ko and kg == ko:
+            assert g.status[b] == o.status[b], (b, g.status[b], o.status[b])
+        assert np.array_equal(g.P[b][:kg][:, g.S[b][:kg]], np.eye(kg)), b
         ag = Ad[:, g.S[b][:kg]] @ g.P[b][:kg]
+        ao = Ad[:, o.S[b][:ko]] @ o.P[b][:ko]
         num += ((Ad - ag) ** 2).sum()
+        rd += ((ag - ao) ** 2).sum()
         den += (Ad ** 2).sum()
-    e_gpu = float(np.sqrt(num / den))
-    print(f"stream fp8 e_gpu={e_gpu:.3e} e_oracle={o.rel_error:.3e}")
-    assert e_gpu <= 1e-3
+    return float(np.sqrt(num / den)), float(np.sqrt(rd / den)), prefixes
+
+
+@pytest.mark.parametrize("groups", [2, 4, 0])
+def test_stream_fp8_resident_multi_group(groups):
+    """One-snapshot FP8 updates with several groups of 128 equal-m blocks sharing one
+    resident sketch-matrix range per work item (st_groups; 0 = the library's choice).
+    Three groups of 2560-row blocks (four K ranges each, reduced in a fixed order)
+    and a 128 + 2 block run of 1000-row blocks (two K ranges)."""
+    shapes = [(2560, 80)] * 384 + [(1000, 80)] * 130
+    rng = np.random.default_rng(41)
+    blocks = []
+    for m, n in shapes:
+        U = rng.standard_normal((m, 12))
+        V = rng.standard_normal((n, 12)) * 10.0 ** (-0.3 * np.arange(12))
+        # columns decaying in time keep the first pivots decidable at the FP8 gap
+        A = (U @ V.T + 1e-5 * rng.standard_normal((m, n))) * (0.85 ** np.arange(n))
+        blocks.append(np.asfortranarray(A.astype(np.float32)))
+    print(f"case: fp8 resident st_groups={groups}", flush=True)
+    g = gpu_run(blocks, 64, 40, 19, prec="fp8", lp_terms=3, stream_columns=True,
+                tuning={"st_groups": groups} if groups else None)
+    if groups:
+        assert g.tuning["st_groups"] == groups
+    o = oracle_run(blocks, 64, 40, 19, prec="fp8")
+    e_gpu, r2, pre = _fp8_gates(blocks, g, o)
+    print(f"fp8 resident groups={g.tuning['st_groups']} e_gpu={e_gpu:.3e} "
+          f"e_oracle={o.rel_error:.3e} R2={r2:.3e} min prefix={min(pre)}")
+    assert min(pre) >= 1 and np.mean(pre) >= 2
+    assert e_gpu <= 1e-3 and r2 <= 1e-3
 
 
 @pytest.mark.parametrize("prec,code", [("bf16", oracle.OMEGA_BF16), ("fp8", oracle.OMEGA_FP8E4M3)])

@@ -1,0 +1,166 @@
+"""Parity under the launch shapes the autotuner committed for the benchmark
+workloads, and a graph-captured ragged (uneven-batch) step.
+
+Launch shapes change only how the independent blocks of Section 3.2 map onto
+the GPU (column tiles per wave, waves per workgroup, how far blocks are split
+along their rows, error-pass rows per item, resident groups per item), never
+the method: every committed shape must meet the same parity rules against the
+oracle as the library's defaults.  Each table entry is run on a small batch with
+the entry's method parameters (sketch arithmetic, data type, l, k, tolerance,
+split terms, batch or one-snapshot updates) and blocks of several heights,
+some split along their rows.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from _harness import compare, gpu_run, matched_prefix, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TABLE = os.path.join(ROOT, "paper_2103_01380_amd", "tuned_shapes.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _entries():
+    with open(TABLE) as f:
+        table = json.load(f)
+    out = []
+    for key, ent in sorted(table.items()):
+        prec, a_dtype, l, k, tol, terms, _nb, mode, _h = key.split("|")
+        out.append(pytest.param(dict(prec=prec, a_dtype=a_dtype, l=int(l[1:]), k=int(k[1:]),
+                                     tol=float(tol[3:]), terms=int(terms[1:]),
+                                     stream=mode == "stream", tuning=ent["tuning"]),
+                                id=f"{prec}-{a_dtype}-l{l[1:]}-{mode}"))
+    return out
+
+
+def _lowrank(shapes, seed, dtype):
+    rng = np.random.default_rng(seed)
+    out = []
+    for m, n, r in shapes:
+        U = rng.standard_normal((m, r))
+        V = rng.standard_normal((n, r)) * 10.0 ** (-0.25 * np.arange(r))
+        A = (U @ V.T + 1e-6 * rng.standard_normal((m, n))) * (0.9 ** np.arange(n))
+        out.append(np.asfortranarray(A.astype(dtype)))
+    return out
+
+
+def _mixed_gates(blocks, g, o, gamma):
+    num = den = rd = 0.0
+    for b, A in enumerate(blocks):
+        Ad = A.astype(np.float64)
+        s_star, ok = matched_prefix(g.S[b], o.S[b], o.gaps[b], g.k[b], o.k[b], gamma)
+        assert ok, (b, s_star, g.S[b][:s_star], o.S[b][:s_star])
+        kg, ko = int(g.k[b]), int(o.k[b])
+        assert np.array_equal(g.P[b][:kg][:, g.S[b][:kg]], np.eye(kg)), b
+        ag = Ad[:, g.S[b][:kg]] @ g.P[b][:kg]
+        ao = Ad[:, o.S[b][:ko]] @ o.P[b][:ko]
+        num += ((Ad - ag) ** 2).sum()
+        rd += ((ag - ao) ** 2).sum()
+        den += (Ad ** 2).sum()
+        e_direct = ((Ad - ag) ** 2).sum()
+        a_norm = math.sqrt((Ad ** 2).sum())
+        assert abs(g.err2[b] - e_direct) <= 1e-6 * math.sqrt(e_direct) * a_norm + \
+            1e-13 * a_norm ** 2, b
+    return math.sqrt(num / den), math.sqrt(rd / den)
+
+
+@pytest.mark.parametrize("ent", _entries())
+def test_committed_tuned_shapes_keep_parity(ent):
+    l, k = ent["l"], ent["k"]
+    n = max(k + 8, 100)
+    dtype = np.float64 if ent["a_dtype"] == "f64" else np.float32
+    # heights: below one sketch chunk, a few chunks, and tall enough to be split
+    shapes = [(300, n, 6), (5000, n + 17, min(k, 20)), (20480, n, min(k, 24)),
+              (1337, n - 3, 8), (70000, n, 10)]
+    if ent["stream"]:
+        shapes = [(m, n, r) for m, _, r in shapes]      # one-snapshot updates: one n
+    blocks = _lowrank(shapes, 7 + l, dtype)
+    print(f"case: tuned {ent}", flush=True)
+    g = gpu_run(blocks, l, k, 29, tol=ent["tol"], prec=ent["prec"], lp_terms=ent["terms"],
+                stream_columns=ent["stream"], tuning=ent["tuning"])
+    for key, v in ent["tuning"].items():
+        assert g.tuning[key] == v, (key, g.tuning)
+    o = oracle_run(blocks, l, k, 29, tol=ent["tol"], prec=ent["prec"])
+    if ent["prec"] == "f64":
+        compare(g, o)
+    else:
+        e_gpu, r2 = _mixed_gates(blocks, g, o, 1e-3 if ent["prec"] == "bf16" else 1e-2)
+        print(f"tuned {ent['prec']}: e_gpu={e_gpu:.3e} e_oracle={o.rel_error:.3e} R2={r2:.3e}")
+        assert e_gpu <= 1e-3 and r2 <= 1e-3
+
+
+def test_graph_captured_ragged_batch():
+    """An uneven batch shaped like the 2000-block workload (m_b = 5 e^3 with e from 4 to
+    24, n_b from 128 to 700, tolerance 1e-4 with k <= 40, l = 50, BF16 sketch) under
+    that workload's tuned shapes: one step captured into a HIP graph and replayed with
+    eager work between the replays; every replay equals the eager step bitwise, and the
+    eager step passes the oracle gates."""
+    import paper_2103_01380_amd as sp
+    with open(TABLE) as f:
+        table = json.load(f)
+    tuning = next(v["tuning"] for key, v in table.items() if key.startswith("bf16|f32|l50|k40"))
+    rng = np.random.default_rng(33)
+    edges = [4, 24, 7, 16, 5, 11, 20, 9, 13, 6]
+    ns = [128, 700, 300, 451, 129, 640, 200, 333, 512, 160]
+    shapes = [(5 * e ** 3, nb, int(rng.integers(2, 41))) for e, nb in zip(edges, ns)]
+    shapes = [(m, nb, min(r, m, nb)) for m, nb, r in shapes]
+    blocks = []
+    for m, nb, r in shapes:
+        U = np.linalg.qr(rng.standard_normal((m, r)))[0]
+        V = np.linalg.qr(rng.standard_normal((nb, r)))[0]
+        blocks.append(np.asfortranarray(((U * 10.0 ** (-0.25 * np.arange(r))) @ V.T)
+                                        .astype(np.float32)))
+    m = np.array([b.shape[0] for b in blocks], dtype=np.int64)
+    n = np.array([b.shape[1] for b in blocks], dtype=np.int32)
+    off = np.zeros(len(blocks), dtype=np.int64)
+    off[1:] = np.cumsum((m * n)[:-1])
+    A = torch.from_numpy(np.concatenate([b.T.ravel() for b in blocks])).cuda()
+    ctx = sp.SPID(m, n, 50, 40, tol=1e-4, seed=31, a_dtype="f32", prec="bf16", lp_terms=2,
+                  tuning=tuning)
+    ctx.bind(A, offsets=off)
+    outs = (ctx.S, ctx.k, ctx.status, ctx.P, ctx.err2, ctx.nrm2)
+    print("case: graph ragged batch", flush=True)
+    ctx.run()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in outs]
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            ctx.run(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for t in outs:
+            t.fill_(7)                        # eager work between the replays
+        ctx.run()                             # and an eager step on the same context
+        torch.cuda.synchronize()
+        for t in outs:
+            t.fill_(5)
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), rep
+    from _harness import GpuResult
+    g = GpuResult(None, ctx.S.cpu().numpy(), ctx.k.cpu().numpy(), ctx.status.cpu().numpy(),
+                  [ctx.block_P(b) for b in range(len(blocks))], ctx.err2.cpu().numpy(),
+                  ctx.nrm2.cpu().numpy())
+    ctx.close()
+    o = oracle_run(blocks, 50, 40, 31, tol=1e-4, prec="bf16")
+    e_gpu, r2 = _mixed_gates(blocks, g, o, 1e-3)
+    print(f"graph ragged: e_gpu={e_gpu:.3e} e_oracle={o.rel_error:.3e} R2={r2:.3e} k={g.k}")
+    assert e_gpu <= 1e-3 and r2 <= 1e-3
+    assert np.all(np.abs(g.k - o.k) <= 1)

@@ -180,3 +180,27 @@ def test_two_stage_single_precision_sketch():
     print(f"two-stage bf16 rel err {e_gpu:.3e}")
     assert e_gpu < 1e-3
     ctx.close()
+
+
+def test_two_stage_stage2_takes_the_whole_union():
+    """Fixed stage-2 rank above the size of the stage-1 union: a window with two zero
+    columns takes two pivots, the union has 14 columns, k_max = 16.  Stage 2 takes
+    every union column, and the block's status is OK, as on the compact union of the
+    oracle (whose selection is capped by the union size)."""
+    rng = np.random.default_rng(12)
+    blocks = []
+    for m in (900, 700):
+        A = rng.standard_normal((m, 16)) * (0.8 ** np.arange(16))
+        A[:, [1, 2]] = 0.0                       # window 0 = columns 0..3
+        blocks.append(np.asfortranarray(A))
+    full = np.asfortranarray(rng.standard_normal((800, 16)) * (0.8 ** np.arange(16)))
+    blocks.append(full)                          # union of 16: stage 2 takes all, OK
+    print("case: two-stage union exhausted", flush=True)
+    g = _gpu_two_stage(blocks, 20, 16, 9, 4, 4, 0.0)
+    o = _oracle_two_stage(blocks, 20, 16, 9, 4, 4, 0.0)
+    for b, (ts, e2, a2) in enumerate(o):
+        assert g["k"][b] == ts.k, (b, g["k"][b], ts.k)
+        assert g["st"][b] == ts.status == 0, (b, g["st"][b], ts.status)
+        assert sorted(g["S"][b][:ts.k]) == sorted(ts.S[:ts.k]), b
+    assert list(g["k"]) == [14, 14, 16]
+    _compare(g, o)
