@@ -29,9 +29,11 @@ def _gates(blocks, g, o, gamma=1e-3, y_rtol=2e-6):
     sketch matrix, relative to the largest sketch column norm (two bfloat16 terms
     leave about 2e-7, three e4m3 terms about 6e-5; FP32 accumulation over the rows
     adds about 1e-6 at most).  The error pass is held to the rounding of its
-    split-bfloat16 product: the product A(:,S) P carries a relative error of about
-    1e-7, so |err2 - e_direct| <= 2 sqrt(e_direct) |delta| + |delta|^2 with
-    |delta| <= 5e-7 ||A||."""
+    split-bfloat16 product: with delta the error of the product A(:,S) P,
+    |err2 - e_direct| <= 2 |<r, delta>| + |delta|^2; the cross term is bounded by
+    2 sqrt(e_direct) |delta| (|delta| about 1e-7 ||A||) and in practice far smaller,
+    since the residual and the rounding are uncorrelated (measured at most 4.2e-9
+    sqrt(e_direct) ||A|| on these blocks), so the test holds it to 5e-8."""
     num = den = rdiff = 0.0
     worst = 0.0
     for b, A in enumerate(blocks):
@@ -51,7 +53,7 @@ def _gates(blocks, g, o, gamma=1e-3, y_rtol=2e-6):
         a_norm = math.sqrt((Ad ** 2).sum())
         gap = abs(g.err2[b] - e_direct)
         worst = max(worst, gap / (math.sqrt(e_direct) * a_norm + 1e-300))
-        assert gap <= 1e-6 * math.sqrt(e_direct) * a_norm + 1e-13 * a_norm ** 2, \
+        assert gap <= 5e-8 * math.sqrt(e_direct) * a_norm + 1e-13 * a_norm ** 2, \
             (b, g.err2[b], e_direct, gap / (math.sqrt(e_direct) * a_norm + 1e-300))
     e_gpu = math.sqrt(num / den)
     r2 = math.sqrt(rdiff / den)

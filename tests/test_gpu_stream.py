@@ -135,7 +135,8 @@ def test_stream_fp8_resident_multi_group(groups):
     e_gpu, r2, pre = _fp8_gates(blocks, g, o)
     print(f"fp8 resident groups={g.tuning['st_groups']} e_gpu={e_gpu:.3e} "
           f"e_oracle={o.rel_error:.3e} R2={r2:.3e} min prefix={min(pre)}")
-    assert min(pre) >= 1 and np.mean(pre) >= 2
+    # the oracle decides 3.6 pivots per block on average at the FP8 gap (0 to 7)
+    assert np.mean(pre) >= 3 and max(pre) >= 6
     assert e_gpu <= 1e-3 and r2 <= 1e-3
 
 
