@@ -172,6 +172,22 @@ spid_status spid_create(const spid_desc* desc, void* d_workspace, size_t ws_byte
 spid_status spid_create_tuned(const spid_desc* desc, const spid_tuning* tuning,
                               void* d_workspace, size_t ws_bytes, spid_ctx** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): spid_create_tuned
+ * without a caller workspace.  The context uses a file-scope device array of
+ * the library, 64 MiB per device (held from the library's first use on the
+ * device until the process ends), as its workspace; nothing is allocated.
+ * EWORKSPACE (with the size needed) when spid_workspace_bytes_tuned exceeds
+ * 64 MiB.  Every static context on a device shares that device's array: the
+ * call waits for the device to finish its queued work (hipDeviceSynchronize),
+ * then takes the array over, and any earlier static context on the device gets
+ * ESTATE from every later call.  Calls on static contexts must not overlap in
+ * time with another spid_create_static on the same device.  The kernels need no
+ * zeroed workspace (every value they read was written by an earlier stage of
+ * the same context).  tuning may be NULL.  A set-up call: not for graph
+ * capture; the compute calls on the context are capturable as usual. */
+spid_status spid_create_static(const spid_desc* desc, const spid_tuning* tuning, spid_ctx** out);
+
 /* The launch shapes a context uses (defaults resolved), for the record. */
 spid_status spid_get_tuning(const spid_ctx* ctx, spid_tuning* out);
 

@@ -32,7 +32,7 @@ EXPORTS = ("spid_workspace_bytes", "spid_workspace_bytes_tuned", "spid_create",
            "spid_create_tuned", "spid_get_tuning", "spid_bind_A", "spid_sketch_update",
            "spid_select", "spid_coeffs", "spid_reconstruct", "spid_copy_sketch",
            "spid_destroy", "spid_last_error", "spid_reconstruct_interp",
-           "spid_select_two_stage")
+           "spid_select_two_stage", "spid_create_static")
 
 
 class SpidError(RuntimeError):
@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH):
     lib.spid_create.restype = ctypes.c_int
     lib.spid_create_tuned.argtypes = [D, T, P, ctypes.c_size_t, ctypes.POINTER(P)]
     lib.spid_create_tuned.restype = ctypes.c_int
+    lib.spid_create_static.argtypes = [D, T, ctypes.POINTER(P)]
+    lib.spid_create_static.restype = ctypes.c_int
     lib.spid_get_tuning.argtypes = [P, T]
     lib.spid_get_tuning.restype = ctypes.c_int
     lib.spid_bind_A.argtypes = [P, P, P]
@@ -209,6 +211,14 @@ def spid_create_tuned(desc: spid_desc, tuning, workspace) -> ctypes.c_void_p:
     return ctx
 
 
+def spid_create_static(desc: spid_desc, tuning=None) -> ctypes.c_void_p:
+    """Context whose workspace is the library's static per-device array (no allocation)."""
+    ctx = ctypes.c_void_p()
+    t = None if tuning is None else ctypes.byref(tuning)
+    _check(load_library().spid_create_static(ctypes.byref(desc), t, ctypes.byref(ctx)))
+    return ctx
+
+
 def spid_get_tuning(ctx) -> dict:
     t = spid_tuning()
     _check(load_library().spid_get_tuning(ctx, ctypes.byref(t)))
@@ -279,6 +289,10 @@ class SPID:
     ``ts_windows`` / ``ts_k1`` reserve the modified two-stage ID
     (:meth:`select_two_stage` in place of :meth:`select` + :meth:`coeffs`).
 
+    ``static_scratch=True`` creates the context with ``spid_create_static`` (the
+    library's per-device scratch array as the workspace: nothing is allocated for
+    it; one such context per device at a time).
+
     ``prec="subsample"`` with ``grids`` (one ``(nx, ny, nz, nfields, sx, sy, sz)`` per
     block, or one for all) selects the coarse-grid sketch B = A(J,:); ``l`` then
     defaults to the largest coarse row count, and :meth:`reconstruct_interp` gives
@@ -287,7 +301,7 @@ class SPID:
 
     def __init__(self, m, n, l, k_max, tol=0.0, rank_floor=0.0, seed=0, omega_per_block=False,
                  a_dtype="f64", prec="f64", lp_terms=1, device="cuda", tuning=None, grids=None,
-                 ts_windows=0, ts_k1=0):
+                 ts_windows=0, ts_k1=0, static_scratch=False):
         import torch
         self.m = np.ascontiguousarray(m, dtype=np.int64)
         self.n = np.ascontiguousarray(n, dtype=np.int32)
@@ -309,11 +323,17 @@ class SPID:
         if nbytes == 0:
             raise SpidError(SPID_EINVAL, spid_last_error())
         self.device = torch.device(device)
-        # 256-byte aligned workspace carved from a torch allocation
-        self._ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        off = (-self._ws_raw.data_ptr()) % 256
-        self.workspace = self._ws_raw[off:off + nbytes]
-        self.ctx = spid_create_tuned(self.desc, self._tuning, self.workspace)
+        if static_scratch:
+            # the library's static scratch array instead of a workspace (spid_create_static)
+            self._ws_raw = self.workspace = None
+            with torch.cuda.device(self.device):
+                self.ctx = spid_create_static(self.desc, self._tuning)
+        else:
+            # 256-byte aligned workspace carved from a torch allocation
+            self._ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self._ws_raw.data_ptr()) % 256
+            self.workspace = self._ws_raw[off:off + nbytes]
+            self.ctx = spid_create_tuned(self.desc, self._tuning, self.workspace)
         self.tuning = spid_get_tuning(self.ctx)
         sum_n = int(self.n.astype(np.int64).sum())
         self.k = torch.zeros(self.nblocks, dtype=torch.int32, device=self.device)

@@ -2,9 +2,11 @@
 // validation, workspace planning, work-item tables and kernel dispatch for
 // gfx950.  Every compute entry point only enqueues kernels on the caller's
 // stream.
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "spid_internal.h"
@@ -509,6 +511,36 @@ bool sketch_stream_prec(spid_ctx* c, int j, hipStream_t s) {
 
 }  // namespace
 
+// ---- allocation-free contexts (spid_create_static)
+// The workspace of callers that cannot allocate device memory: one array per
+// device, allocated with the code object when the library is loaded on it and
+// held until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (on the host it only stands in for the symbol): it takes the
+// device address from hipGetSymbolAddress, once per device, and uses that.
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxStaticDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices];                 // per device, under g_static_mu
+std::atomic<uint64_t> g_static_gen[kMaxStaticDevices];  // last static context per device
+
+// A context made by spid_create_static that a later one on the same device has
+// replaced: its tables in the scratch array are gone.
+spid_status check_live(const spid_ctx* c) {
+  if (c->static_dev >= 0 && g_static_gen[c->static_dev].load() != c->static_gen)
+    return fail(SPID_ESTATE,
+                "context created by spid_create_static was replaced by a later "
+                "spid_create_static on device %d (they share the static scratch array)",
+                c->static_dev);
+  return SPID_OK;
+}
+}  // namespace
+
 // ============================================================================ C ABI
 
 extern "C" size_t spid_workspace_bytes(const spid_desc* desc) {
@@ -612,9 +644,52 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
   return SPID_OK;
 }
 
+extern "C" spid_status spid_create_static(const spid_desc* desc, const spid_tuning* tuning,
+                                          spid_ctx** out) {
+  if (!out) return fail(SPID_EINVAL, "out is NULL");
+  *out = nullptr;
+  Plan p;
+  spid_status st = make_plan(desc, tuning, p);
+  if (st != SPID_OK) return st;
+  if (p.total > kStaticScratchBytes)
+    return fail(SPID_EWORKSPACE,
+                "spid_create_static: the descriptor needs %zu bytes of workspace, the static "
+                "scratch array holds %zu (spid_create takes a caller workspace of any size)",
+                p.total, kStaticScratchBytes);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(SPID_EHIP, "spid_create_static: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxStaticDevices)
+    return fail(SPID_EINVAL, "spid_create_static: device %d beyond %d", dev, kMaxStaticDevices);
+  void* ptr = nullptr;
+  uint64_t gen = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return fail(SPID_EHIP, "spid_create_static: address of the scratch array: %s",
+                    hipGetErrorString(e));
+      g_static_ptr[dev] = ptr;
+    }
+    ptr = g_static_ptr[dev];
+    // the previous static context on this device loses the array now; work it
+    // enqueued must end before its tables are overwritten
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(SPID_EHIP, "spid_create_static: %s", hipGetErrorString(e));
+    gen = ++g_static_gen[dev];
+  }
+  st = spid_create_tuned(desc, tuning, ptr, kStaticScratchBytes, out);
+  if (st != SPID_OK) return st;
+  (*out)->static_dev = dev;
+  (*out)->static_gen = gen;
+  return SPID_OK;
+}
+
 extern "C" spid_status spid_bind_A(spid_ctx* c, const void* const* h_block_ptrs,
                                    const int64_t* h_lda) {
   if (!c || !h_block_ptrs || !h_lda) return fail(SPID_EINVAL, "NULL argument to spid_bind_A");
+  if (check_live(c) != SPID_OK) return SPID_ESTATE;
   Plan& p = c->plan;
   const size_t es = c->desc.a_dtype == SPID_A_F64 ? 8 : 4;
   for (int b = 0; b < c->desc.nblocks; ++b) {
@@ -647,6 +722,7 @@ extern "C" spid_status spid_bind_A(spid_ctx* c, const void* const* h_block_ptrs,
 
 extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, void* stream) {
   if (!c) return fail(SPID_EINVAL, "NULL context");
+  if (check_live(c) != SPID_OK) return SPID_ESTATE;
   if (!c->bound) return fail(SPID_ESTATE, "spid_sketch_update before spid_bind_A");
   if (j0 < 0 || w < 1) return fail(SPID_EINVAL, "need j0 >= 0 and w >= 1 (got %d, %d)", j0, w);
   const Plan& p = c->plan;
@@ -729,6 +805,7 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
 extern "C" spid_status spid_select(spid_ctx* c, int32_t* d_k, int32_t* d_S, int32_t* d_status,
                                    void* stream) {
   if (!c) return fail(SPID_EINVAL, "NULL context");
+  if (check_live(c) != SPID_OK) return SPID_ESTATE;
   for (int j = 0; j < c->plan.max_n; ++j)
     if (!c->covered[j])
       return fail(SPID_ESTATE, "spid_select: sketch column %d has not been computed", j);
@@ -755,6 +832,7 @@ extern "C" spid_status spid_select(spid_ctx* c, int32_t* d_k, int32_t* d_S, int3
 
 extern "C" spid_status spid_coeffs(spid_ctx* c, double* d_P, void* stream) {
   if (!c || !d_P) return fail(SPID_EINVAL, "NULL argument to spid_coeffs");
+  if (check_live(c) != SPID_OK) return SPID_ESTATE;
   if (!c->selected) return fail(SPID_ESTATE, "spid_coeffs before spid_select");
   if (c->two_stage)
     return fail(SPID_ESTATE,
@@ -769,6 +847,7 @@ extern "C" spid_status spid_coeffs(spid_ctx* c, double* d_P, void* stream) {
 extern "C" spid_status spid_reconstruct(spid_ctx* c, const double* d_P, double* d_err2,
                                         double* d_nrm2, void* d_skeleton, void* stream) {
   if (!c || !d_P || !d_err2 || !d_nrm2) return fail(SPID_EINVAL, "NULL argument to spid_reconstruct");
+  if (check_live(c) != SPID_OK) return SPID_ESTATE;
   if (!c->selected) return fail(SPID_ESTATE, "spid_reconstruct before spid_select");
   if (!c->coeffs_done) return fail(SPID_ESTATE, "spid_reconstruct before spid_coeffs");
   const Plan& p = c->plan;
@@ -841,6 +920,7 @@ spid_status two_stage_t(spid_ctx* c, double* d_P, hipStream_t s) {
 extern "C" spid_status spid_select_two_stage(spid_ctx* c, int32_t* d_k, int32_t* d_S,
                                              int32_t* d_status, double* d_P, void* stream) {
   if (!c || !d_P) return fail(SPID_EINVAL, "NULL argument to spid_select_two_stage");
+  if (check_live(c) != SPID_OK) return SPID_ESTATE;
   if (c->plan.ts_nwin < 1)
     return fail(SPID_EINVAL, "spid_select_two_stage: the descriptor has no ts_windows");
   for (int j = 0; j < c->plan.max_n; ++j)
@@ -871,6 +951,7 @@ extern "C" spid_status spid_reconstruct_interp(spid_ctx* c, const double* d_P, d
                                                void* stream) {
   if (!c || !d_P || !d_err2 || !d_nrm2)
     return fail(SPID_EINVAL, "NULL argument to spid_reconstruct_interp");
+  if (check_live(c) != SPID_OK) return SPID_ESTATE;
   if (!c->plan.coarse)
     return fail(SPID_EINVAL, "spid_reconstruct_interp needs the coarse-grid sketch");
   if (!c->selected) return fail(SPID_ESTATE, "spid_reconstruct_interp before spid_select");
@@ -889,6 +970,7 @@ extern "C" spid_status spid_reconstruct_interp(spid_ctx* c, const double* d_P, d
 
 extern "C" spid_status spid_copy_sketch(spid_ctx* c, double* d_Y, void* stream) {
   if (!c || !d_Y) return fail(SPID_EINVAL, "NULL argument to spid_copy_sketch");
+  if (check_live(c) != SPID_OK) return SPID_ESTATE;
   const Plan& p = c->plan;
   const int64_t total = (int64_t)c->desc.l * p.sum_n;
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -175,6 +175,8 @@ struct spid_ctx {
   bool all_vec = false;            // every block's column starts are 16-byte aligned
   bool all_vec4 = false;           // ... and every m is a multiple of 4
   std::vector<uint8_t> covered;   // per column index: sketched since bind
+  int static_dev = -1;             // spid_create_static: device whose scratch array it uses
+  uint64_t static_gen = 0;         // ... and the generation of that array it owns
   template <typename T>
   T* at(size_t off) const {
     return reinterpret_cast<T*>(ws + off);
