@@ -250,6 +250,39 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
   }
 }
 
+// The same argmax with the first four exchange levels by DPP lane moves within
+// each row of 16 lanes (quad permutations, then the half-row and row mirrors)
+// and the last two by lane shuffles.  The operation (max, lowest index on
+// equal values) is commutative, associative and idempotent, so every lane ends
+// with the argmax over the 64 lanes whatever the exchange pattern.
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp_level(double& v, int& idx) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  const int oi = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xf, 0xf, false);
+  const double ov = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                                     (unsigned)lo));
+  const bool take = (ov > v) | ((ov == v) & (oi < idx));
+  v = take ? ov : v;
+  idx = take ? oi : idx;
+}
+
+__device__ __forceinline__ void wave_argmax_dpp(double& v, int& idx) {
+  argmax_dpp_level<0xB1>(v, idx);    // quad_perm [1,0,3,2]
+  argmax_dpp_level<0x4E>(v, idx);    // quad_perm [2,3,0,1]
+  argmax_dpp_level<0x141>(v, idx);   // row_half_mirror (lane i <-> 7 - i)
+  argmax_dpp_level<0x140>(v, idx);   // row_mirror (lane i <-> 15 - i)
+#pragma unroll
+  for (int off = 16; off <= 32; off <<= 1) {
+    const double ov = __shfl_xor(v, off, kWave);
+    const int oi = __shfl_xor(idx, off, kWave);
+    const bool take = (ov > v) | ((ov == v) & (oi < idx));
+    v = take ? ov : v;
+    idx = take ? oi : idx;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // MFMA wrappers (gfx950).  Operand layouts (checked on the device):
 //   f64 16x16x4 : A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);

@@ -38,8 +38,13 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Selection kernel choice for a sketch height l and widest block max_n.
+//   register kernel (sel_lpc > 0): groups of sel_lpc lanes hold 4 columns,
+//     each lane sel_rpt rows (l <= 128, n <= 512; n <= 384 for l > 64);
+//   hybrid (sel_rr > 0): one column per thread, sel_rr rows in registers, the
+//     rest in LDS (wider blocks);
+//   tall (sel_tall): coarse sketches taller than 128 rows, in global memory.
 struct SelShape {
-  int LMAX = 16, CPT = 1, sel_thr = 64, sel_rr = 0, sel_pair = 0, sel_tall = 0;
+  int LMAX = 16, sel_thr = 64, sel_rr = 0, sel_lpc = 0, sel_rpt = 0, sel_tall = 0;
   size_t sel_lds = 0;
 };
 
@@ -87,36 +92,31 @@ inline bool pick_sel(int l, int max_n, bool allow_tall, SelShape& sh) {
   sh = SelShape{};
   sh.LMAX = pick_lmax(l);
   sh.sel_tall = (allow_tall && l > kMaxL) ? 1 : 0;
-  sh.CPT = (max_n > 512) ? 2 : 1;
+  if (sh.sel_tall) return true;   // coarse sketch taller than the register/LDS kernels take
   {
-    int need = (max_n + sh.CPT - 1) / sh.CPT;
-    sh.sel_thr = std::max(64, (need + 63) / 64 * 64);
-  }
-  if (sh.sel_tall) {
-    // coarse sketch taller than the register/LDS kernels take: global memory
-  } else if (sh.LMAX > 56 && max_n <= 384) {
-    // two lanes per column, every row in registers
-    sh.sel_pair = l <= 64 ? 32 : (l <= 96 ? 48 : 64);
-    sh.sel_thr = std::max(64, (2 * max_n + 63) / 64 * 64);
-  } else if (sh.LMAX > 56 || max_n > 512) {
-    // hybrid: one column per thread, RR rows in registers, the rest in LDS
-    sh.CPT = 1;
-    sh.sel_thr = std::max(64, (max_n + 63) / 64 * 64);
-    const int rr_opts[] = {48, 32, 16};
-    for (int rr : rr_opts) {
-      if (sh.sel_thr > 512 && rr > 32) continue;   // 1024 threads: 128 registers per lane
-      const size_t lds = sizeof(double) * (size_t)std::max(0, l - rr) * sh.sel_thr;
-      if (lds <= 150 * 1024) {
-        sh.sel_rr = rr;
-        sh.sel_lds = lds;
-        break;
-      }
-    }
-    if (sh.sel_rr == 0) {
-      if (!allow_tall) return false;
-      sh.sel_tall = 1;
+    const int lpc = l <= 32 ? 2 : (l <= 64 ? 4 : 8);
+    if (l <= kMaxL && max_n <= (lpc == 8 ? 384 : 512)) {
+      sh.sel_lpc = lpc;
+      sh.sel_rpt = std::max(4, ((l + lpc - 1) / lpc + 3) / 4 * 4);
+      const int groups = (max_n + 3) / 4;
+      sh.sel_thr = std::max(64, (groups * lpc + 63) / 64 * 64);
+      return true;
     }
   }
+  // hybrid: one column per thread, RR rows in registers, the rest in LDS
+  sh.sel_thr = std::max(64, (max_n + 63) / 64 * 64);
+  const int rr_opts[] = {48, 32, 16};
+  for (int rr : rr_opts) {
+    if (sh.sel_thr > 512 && rr > 32) continue;   // 1024 threads: 128 registers per lane
+    const size_t lds = sizeof(double) * (size_t)std::max(0, l - rr) * sh.sel_thr;
+    if (lds <= 150 * 1024) {
+      sh.sel_rr = rr;
+      sh.sel_lds = lds;
+      return true;
+    }
+  }
+  if (!allow_tall) return false;
+  sh.sel_tall = 1;
   return true;
 }
 

@@ -4,9 +4,9 @@
 //                     Omega regenerated per 32-row chunk into LDS.
 //   sketch_reduce     fixed-order sum of split-K partial sketches (per block,
 //                     or per group of blocks for one-snapshot updates).
-//   select_kernel     pivoted modified Gram-Schmidt on the sketch, one
-//                     workgroup per block, one sketch column per lane held in
-//                     registers, pivot search by wave + LDS reduction.
+//   select_step_kernel pivoted modified Gram-Schmidt on the sketch, one
+//                     workgroup per block, sketch columns in registers (groups
+//                     of lanes holding four columns), one barrier per step.
 //   coeffs_kernel     back-substitution R11 x = R12(:, j), identity columns
 //                     (and the split-bfloat16 coefficients of the mixed error pass).
 //   recon_mfma_kernel streaming residual ||A - A(:,S) P||^2 per row tile, the
@@ -813,274 +813,201 @@ __global__ __launch_bounds__(256) void sketch_stream_reduce_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Column selection: rank-k pivoted modified Gram-Schmidt on Y_b (l x n_b).
-// One workgroup per block; thread t owns columns t + c*blockDim (c < CPT),
-// each an LMAX-double register column (rows >= l are zero).  Per step:
-// block argmax of the residual norms (ties -> lowest index), the owner
-// writes q = w_p / ||w_p|| to LDS, every other column is orthogonalised and
-// its norm recomputed; optional tolerance stop on the residual Frobenius
-// norm.  Writes S, k, status, and R (row s = step s) for the coefficients.
+// Column selection with one barrier per step.  A group of LPC lanes holds CPL
+// sketch columns, each lane RPT consecutive rows of all of them (RPT * LPC >=
+// l, rows past l zero), so a lane reads only its RPT rows of the pivot column
+// and uses each of them on CPL columns; dot products and norms are summed over
+// the group's lanes by DPP moves.  In every step each wave finds its best live
+// column (largest residual norm^2, lowest index on ties) and that column's
+// lanes write its rows to the wave's slot in LDS beside the candidate; after
+// the barrier the per-wave candidates are reduced across lanes (entries of
+// absent waves never win) and every lane reads its rows of the pivot column
+// from the winning wave's slot.  Slots and candidates are double buffered by
+// step parity: the writes of step s + 1 go to the buffer last read in step
+// s - 1, which every lane finished before the barrier of step s, so one
+// barrier per step suffices.  The pivot column is used unscaled:
+// R(s, j) = <w_p, w_j> / r_ss and w_j -= (R(s, j) / r_ss) w_p, the modified
+// Gram-Schmidt step of Algorithm 1 with q = w_p / r_ss folded into two
+// products with 1 / r_ss (r_ss^2 is the pivot's residual norm^2, computed as
+// every norm).  Norms are recomputed after every update.  The tolerance test
+// after step s (Remark 2.1) runs at the start of step s + 1 on per-wave sums of
+// the live residual norms published with the candidates (after the last step,
+// in one more round), so it ends the selection at the same step.
 // ---------------------------------------------------------------------------
-template <typename TY, int LMAX, int CPT>
-__global__ __launch_bounds__(512) void select_kernel(
-    const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor,
-    const TY* __restrict__ Y, double* __restrict__ R, int32_t* __restrict__ S_ws,
-    int32_t* __restrict__ k_ws, int32_t* __restrict__ st_ws) {
-  __shared__ double q_lds[LMAX];
-  __shared__ double red_v[16];
-  __shared__ int red_i[16];
-  __shared__ double bc_rss;
-  const int b = blockIdx.x;
-  const BlkInfo bi = blks[b];
-  const int n = bi.n;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
-  const TY* __restrict__ Yb = Y + bi.y_off;
-  double* __restrict__ Rb = R + bi.r_off;
-
-  double w[CPT][LMAX];
-  double nu[CPT];
-  bool live[CPT];     // column exists and is not selected yet
-  int bad = 0;
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    const int j = tid + c * nthr;
-    live[c] = j < n;
-    double acc = 0.0;
-#pragma unroll
-    for (int r = 0; r < LMAX; ++r) {
-      double v = 0.0;
-      if (live[c] && r < l) v = (double)Yb[(int64_t)j * l + r];
-      if (!isfinite(v)) bad = 1;
-      w[c][r] = v;
-      acc += v * v;
-    }
-    nu[c] = live[c] ? acc : 0.0;
-  }
-  for (int e = tid; e < LMAX; e += nthr) q_lds[e] = 0.0;
-  const int any_bad = __syncthreads_or(bad);
-
-  // Frobenius norm^2 and largest column norm^2 of the sketch (fixed order)
-  double fs = 0.0, fm = 0.0;
-#pragma unroll
-  for (int c = 0; c < CPT; ++c) {
-    fs += nu[c];
-    fm = fmax(fm, nu[c]);
-  }
-  fs = wave_sum(fs);
-  fm = wave_max(fm);
-  if (lane == 0) {
-    red_v[wave] = fs;
-    red_i[wave] = 0;
-  }
-  __syncthreads();
-  double F2 = 0.0;
-  for (int v = 0; v < nwaves; ++v) F2 += red_v[v];
-  __syncthreads();
-  if (lane == 0) red_v[wave] = fm;
-  __syncthreads();
-  double nu0max = 0.0;
-  for (int v = 0; v < nwaves; ++v) nu0max = fmax(nu0max, red_v[v]);
-  __syncthreads();
-
-  int kcap = k_max;
-  if (kcap > l) kcap = l;
-  if (kcap > n) kcap = n;
-  int status = 0, taken = 0;
-  if (any_bad) {
-    status = 2;   // SPID_BLOCK_NONFINITE
-  } else {
-    for (int s = 0; s < kcap; ++s) {
-      // ---- pivot: argmax of live residual norms
-      double bv = -1.0;
-      int bj = 0x7fffffff;
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        const int j = tid + c * nthr;
-        if (live[c] && (nu[c] > bv || (nu[c] == bv && j < bj))) {
-          bv = nu[c];
-          bj = j;
-        }
-      }
-      wave_argmax(bv, bj);
-      if (lane == 0) {
-        red_v[wave] = bv;
-        red_i[wave] = bj;
-      }
-      __syncthreads();
-      // every wave reduces the per-wave winners itself (ties to the lowest index); the
-      // next write of red_v comes after the pivot barrier below
-      double best = lane < nwaves ? red_v[lane] : -1.0;
-      int p = lane < nwaves ? red_i[lane] : 0x7fffffff;
-      wave_argmax(best, p);
-      if (!(best > 0.0)) {
-        status = 1;   // SPID_BLOCK_RANK_DEFICIENT
-        break;
-      }
-      if (rank_floor > 0.0 && best <= rank_floor * rank_floor * nu0max) {
-        status = 1;
-        break;
-      }
-      // ---- the owner publishes its column and its norm; q = w_p / r_ss is
-      // then formed in LDS, one row per thread
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        if (tid + c * nthr == p) {
-          double pn = 0.0;
-#pragma unroll
-          for (int r = 0; r < LMAX; ++r) {
-            pn += w[c][r] * w[c][r];
-            q_lds[r] = w[c][r];
-          }
-          const double rss = sqrt(pn);
-          bc_rss = rss;
-          Rb[(int64_t)s * n + p] = rss;
-          live[c] = false;
-          nu[c] = 0.0;
-        }
-      }
-      if (tid == 0) S_ws[(int64_t)b * k_max + s] = p;
-      __syncthreads();
-      if (tid < LMAX) q_lds[tid] = q_lds[tid] / bc_rss;
-      __syncthreads();
-      taken = s + 1;
-      // ---- orthogonalise the live columns against q, recompute norms.  The
-      // update runs on every register column with d = 0 where the column is
-      // not live (w - 0*q = w exactly), so no predicated copy of w is needed.
-      double rest = 0.0;
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        const int j = tid + c * nthr;
-        // q is read from LDS 8 rows at a time (scheduling fences keep the
-        // compiler from holding all LMAX q values in registers)
-        double d = 0.0;
-#pragma unroll
-        for (int r0 = 0; r0 < LMAX; r0 += 8) {
-#pragma unroll
-          for (int r = r0; r < r0 + 8; ++r) d += q_lds[r] * w[c][r];
-          __builtin_amdgcn_sched_barrier(0);
-        }
-        if (live[c]) Rb[(int64_t)s * n + j] = d;
-        d = live[c] ? d : 0.0;
-        // second read of q: relaxed atomic LDS loads are not merged with the
-        // first ones, so q is never held whole in registers
-        double a2 = 0.0;
-#pragma unroll
-        for (int r0 = 0; r0 < LMAX; r0 += 8) {
-#pragma unroll
-          for (int r = r0; r < r0 + 8; ++r) {
-            const double qr =
-                __hip_atomic_load(q_lds + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            w[c][r] -= d * qr;
-            a2 += w[c][r] * w[c][r];
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
-        nu[c] = live[c] ? a2 : 0.0;
-        rest += nu[c];
-      }
-      if (tol > 0.0) {
-        rest = wave_sum(rest);
-        if (lane == 0) red_v[wave] = rest;
-        __syncthreads();
-        double tot = 0.0;
-        for (int v = 0; v < nwaves; ++v) tot += red_v[v];
-        if (sqrt(tot) <= tol * sqrt(F2)) {
-          __syncthreads();
-          break;
-        }
-        if (s == kcap - 1) status = 3;   // SPID_BLOCK_TOL_NOT_MET
-      }
-      __syncthreads();   // q_lds and red_v reused by the next step
-    }
-  }
-  if (tid == 0) {
-    k_ws[b] = taken;
-    st_ws[b] = status;
-  }
-  for (int s = taken + tid; s < k_max; s += nthr) S_ws[(int64_t)b * k_max + s] = -1;
+// sum over the LPC lanes of a group (LPC = 1, 2, 4, 8 or 16 consecutive lanes);
+// every lane of the group gets the same value (the pairings are symmetric and
+// addition is commutative)
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return v + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                              (unsigned)lo));
 }
 
-// ---------------------------------------------------------------------------
-// Column selection for tall sketches (l up to 2 RPT) on narrow blocks
-// (n <= 384): two lanes per sketch column, each holding RPT consecutive rows
-// in registers (rows >= l are zero), so the whole sketch stays in registers.
-// Dot products and norms add the two halves with one lane exchange; the
-// pivot search, publication of q and the updates follow select_kernel.
-// ---------------------------------------------------------------------------
-template <typename TY, int RPT>
-__global__ __launch_bounds__(768) void select_pair_kernel(
+template <int LPC>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (LPC >= 2) v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
+  if constexpr (LPC >= 4) v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
+  if constexpr (LPC >= 8) v = dpp_add<0x141>(v);   // row_half_mirror
+  if constexpr (LPC >= 16) v = dpp_add<0x140>(v);  // row_mirror
+  return v;
+}
+
+__device__ __forceinline__ double readfirstlane_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+
+template <typename TY, int RPT, int LPC, int CPL, int MAXTHR>
+__global__ __launch_bounds__(MAXTHR) void select_step_kernel(
     const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor,
     const TY* __restrict__ Y, double* __restrict__ R, int32_t* __restrict__ S_ws,
     int32_t* __restrict__ k_ws, int32_t* __restrict__ st_ws) {
-  __shared__ double q_lds[2 * RPT];
-  __shared__ double red_v[16];
-  __shared__ int red_i[16];
-  __shared__ double bc_rss;
+  static_assert(RPT % 2 == 0 && (LPC == 1 || LPC == 2 || LPC == 4 || LPC == 8), "shape");
+  constexpr int LCOL = RPT * LPC;
+  constexpr int NWMAX = MAXTHR / kWave;
+  __shared__ __attribute__((aligned(16))) double slot[2][NWMAX][LCOL];
+  __shared__ double cand_v[2][NWMAX];
+  __shared__ double cand_r[2][NWMAX];
+  __shared__ int cand_i[2][NWMAX];
   const int b = blockIdx.x;
   const BlkInfo bi = blks[b];
   const int n = bi.n;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
-  const int h = tid & 1;            // row half
-  const int j = tid >> 1;           // sketch column
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int h = tid % LPC;                 // row slice of the lane
+  const int j0 = (tid / LPC) * CPL;        // first column of the lane's group
   const int r0 = h * RPT;
   const TY* __restrict__ Yb = Y + bi.y_off;
   double* __restrict__ Rb = R + bi.r_off;
 
-  double w[RPT];
-  bool live = j < n;
+  double w[CPL][RPT];
+  double nu[CPL];
+  bool live[CPL];
   int bad = 0;
-  double part = 0.0;
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    double v = 0.0;
-    if (live && r0 + i < l) v = (double)Yb[(int64_t)j * l + r0 + i];
-    if (!isfinite(v)) bad = 1;
-    w[i] = v;
-    part += v * v;
+  for (int c = 0; c < CPL; ++c) {
+    const int j = j0 + c;
+    live[c] = j < n;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      double v = 0.0;
+      if (live[c] && r0 + i < l) v = (double)Yb[(int64_t)j * l + r0 + i];
+      if (!isfinite(v)) bad = 1;
+      w[c][i] = v;
+      if (i & 1) s1 += v * v;
+      else s0 += v * v;
+    }
+    nu[c] = group_sum<LPC>(s0 + s1);
+    nu[c] = live[c] ? nu[c] : 0.0;
   }
-  double nu = part + __shfl_xor(part, 1, kWave);
-  nu = live ? nu : 0.0;
-  for (int e = tid; e < 2 * RPT; e += nthr) q_lds[e] = 0.0;
+  // candidate entries of waves that do not exist never win and add nothing
+  for (int e = tid; e < 2 * NWMAX; e += blockDim.x) {
+    (&cand_v[0][0])[e] = -1.0;
+    (&cand_i[0][0])[e] = 0x7fffffff;
+    (&cand_r[0][0])[e] = 0.0;
+  }
   const int any_bad = __syncthreads_or(bad);
-
-  // Frobenius norm^2 and largest column norm^2 of the sketch (each column once)
-  double fs = h == 0 ? nu : 0.0, fm = nu;
-  fs = wave_sum(fs);
-  fm = wave_max(fm);
-  if (lane == 0) red_v[wave] = fs;
+  // Frobenius norm^2 and largest column norm^2 of the sketch (each column
+  // once), through buffer 1, which step 1 writes only after the barrier of step 0
+  {
+    double fs = 0.0, fm = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      fs += h == 0 ? nu[c] : 0.0;
+      fm = fmax(fm, nu[c]);
+    }
+    fs = wave_sum(fs);
+    fm = wave_max(fm);
+    if (lane == 0) {
+      cand_r[1][wave] = fs;
+      cand_v[1][wave] = fm;
+    }
+  }
   __syncthreads();
-  double F2 = 0.0;
-  for (int v = 0; v < nwaves; ++v) F2 += red_v[v];
-  __syncthreads();
-  if (lane == 0) red_v[wave] = fm;
-  __syncthreads();
-  double nu0max = 0.0;
-  for (int v = 0; v < nwaves; ++v) nu0max = fmax(nu0max, red_v[v]);
-  __syncthreads();
+  double F2 = 0.0, nu0max = 0.0;
+  for (int v = 0; v < nwaves; ++v) {
+    F2 += cand_r[1][v];
+    nu0max = fmax(nu0max, cand_v[1][v]);
+  }
 
   int kcap = k_max;
   if (kcap > l) kcap = l;
   if (kcap > n) kcap = n;
   int status = 0, taken = 0;
+  bool ran_out = false;   // the loop ended at kcap without a stop
+  auto live_sum = [&]() {  // sum of the live residual norms of the lane's group (once)
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) t += (h == 0 && live[c]) ? nu[c] : 0.0;
+    return wave_sum(t);
+  };
   if (any_bad) {
     status = 2;   // SPID_BLOCK_NONFINITE
   } else {
-    for (int s = 0; s < kcap; ++s) {
-      double bv = live ? nu : -1.0;
-      int bj = live ? j : 0x7fffffff;
-      wave_argmax(bv, bj);
-      if (lane == 0) {
-        red_v[wave] = bv;
-        red_i[wave] = bj;
+    int s = 0;
+    for (; s < kcap; ++s) {
+      const int buf = s & 1;
+      // the lane's best live column, then the wave's
+      double bv = -1.0;
+      int bj = 0x7fffffff, bc = 0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const bool take = live[c] & (nu[c] > bv);   // ties keep the lower column
+        bv = take ? nu[c] : bv;
+        bj = take ? j0 + c : bj;
+        bc = take ? c : bc;
       }
-      __syncthreads();
-      // every wave reduces the per-wave winners itself (ties to the lowest index); the
-      // next write of red_v comes after the pivot barrier below
-      double best = lane < nwaves ? red_v[lane] : -1.0;
-      int p = lane < nwaves ? red_i[lane] : 0x7fffffff;
-      wave_argmax(best, p);
+      const int my_j = bj;
+      wave_argmax_dpp(bv, bj);
+      double rw = 0.0;
+      if (tol > 0.0 && s > 0) rw = live_sum();
+      if ((my_j == bj) & (bj != 0x7fffffff)) {
+        // the lanes of the wave's winning column publish their rows of it
+#pragma unroll
+        for (int i = 0; i < RPT; i += 2) {
+          double x0 = w[0][i], x1 = w[0][i + 1];
+#pragma unroll
+          for (int c = 1; c < CPL; ++c) {
+            x0 = bc == c ? w[c][i] : x0;
+            x1 = bc == c ? w[c][i + 1] : x1;
+          }
+          *reinterpret_cast<f64x2*>(&slot[buf][wave][r0 + i]) = f64x2{x0, x1};
+        }
+      }
+      if (lane == 0) {
+        cand_v[buf][wave] = bv;
+        cand_i[buf][wave] = bj;
+        cand_r[buf][wave] = rw;
+      }
+      // orders LDS only: the R stores of the previous step stay in flight
+      lds_barrier();
+      // lane v < NWMAX takes wave v's candidate (entries past the last wave
+      // hold -1 / 0); the argmax over those 16 lanes, then lane 0's result is
+      // the block's, uniform in scalar registers
+      double best;
+      int p;
+      {
+        double cv = lane < NWMAX ? cand_v[buf][lane] : -1.0;
+        int ci = lane < NWMAX ? cand_i[buf][lane] : 0x7fffffff;
+        argmax_dpp_level<0xB1>(cv, ci);
+        argmax_dpp_level<0x4E>(cv, ci);
+        argmax_dpp_level<0x141>(cv, ci);
+        argmax_dpp_level<0x140>(cv, ci);
+        best = readfirstlane_f64(cv);
+        p = __builtin_amdgcn_readfirstlane(ci);
+      }
+      if (tol > 0.0 && s > 0) {
+        double cr = lane < NWMAX ? cand_r[buf][lane] : 0.0;
+        cr = group_sum<16>(cr);
+        if (sqrt(readfirstlane_f64(cr)) <= tol * sqrt(F2)) break;
+      }
       if (!(best > 0.0)) {
         status = 1;   // SPID_BLOCK_RANK_DEFICIENT
         break;
@@ -1089,81 +1016,85 @@ __global__ __launch_bounds__(768) void select_pair_kernel(
         status = 1;
         break;
       }
-      // the two lanes of the pivot column publish their rows and its norm
-      if (j == p) {
-        double pn = 0.0;
+      const int pw = ((p / CPL) * LPC) >> 6;   // the wave holding column p
+      const double rss = sqrt(best);
+      const double inv_rss = 1.0 / rss;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          pn += w[i] * w[i];
-          q_lds[r0 + i] = w[i];
+      for (int c = 0; c < CPL; ++c)
+        if (j0 + c == p) {
+          live[c] = false;
+          nu[c] = 0.0;
         }
-        live = false;
-        nu = 0.0;
-        pn += __shfl_xor(pn, 1, kWave);   // both lanes of the column are active here
-        if (h == 0) {
-          const double rss = sqrt(pn);
-          bc_rss = rss;
-          Rb[(int64_t)s * n + p] = rss;
-          S_ws[(int64_t)b * k_max + s] = p;
-        }
+      if (h == 0 && p >= j0 && p < j0 + CPL) {
+        Rb[(int64_t)s * n + p] = rss;
+        S_ws[(int64_t)b * k_max + s] = p;
       }
-      __syncthreads();
-      for (int e = tid; e < 2 * RPT; e += nthr) q_lds[e] = q_lds[e] / bc_rss;
-      __syncthreads();
       taken = s + 1;
-      double d = 0.0;
+      // the lane's rows of the pivot column, held for both passes
+      double q[RPT];
+      const double* __restrict__ qs = &slot[buf][pw][r0];
 #pragma unroll
-      for (int i0 = 0; i0 < RPT; i0 += 8) {
+      for (int i = 0; i < RPT; i += 2) {
+        const f64x2 qa = *reinterpret_cast<const f64x2*>(qs + i);
+        q[i] = qa[0];
+        q[i + 1] = qa[1];
+      }
+      double coef[CPL];
 #pragma unroll
-        for (int i = i0; i < i0 + 8; ++i) d += q_lds[r0 + i] * w[i];
+      for (int c = 0; c < CPL; ++c) {
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; i += 2) {
+          d0 += q[i] * w[c][i];
+          d1 += q[i + 1] * w[c][i + 1];
+        }
+        const double d = live[c] ? group_sum<LPC>(d0 + d1) * inv_rss : 0.0;
+        if (live[c] && h == 0) Rb[(int64_t)s * n + j0 + c] = d;
+        coef[c] = d * inv_rss;
+        __builtin_amdgcn_sched_barrier(0);   // one column at a time: bounded registers
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; i += 2) {
+          w[c][i] -= coef[c] * q[i];
+          w[c][i + 1] -= coef[c] * q[i + 1];
+          a0 += w[c][i] * w[c][i];
+          a1 += w[c][i + 1] * w[c][i + 1];
+        }
+        const double np = group_sum<LPC>(a0 + a1);
+        nu[c] = live[c] ? np : 0.0;
         __builtin_amdgcn_sched_barrier(0);
       }
-      d += __shfl_xor(d, 1, kWave);
-      if (live && h == 0) Rb[(int64_t)s * n + j] = d;
-      d = live ? d : 0.0;
-      double a2 = 0.0;
-#pragma unroll
-      for (int i0 = 0; i0 < RPT; i0 += 8) {
-#pragma unroll
-        for (int i = i0; i < i0 + 8; ++i) {
-          const double qr =
-              __hip_atomic_load(q_lds + r0 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          w[i] -= d * qr;
-          a2 += w[i] * w[i];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      a2 += __shfl_xor(a2, 1, kWave);
-      nu = live ? a2 : 0.0;
-      if (tol > 0.0) {
-        double rest = h == 0 ? nu : 0.0;
-        rest = wave_sum(rest);
-        if (lane == 0) red_v[wave] = rest;
-        __syncthreads();
-        double tot = 0.0;
-        for (int v = 0; v < nwaves; ++v) tot += red_v[v];
-        if (sqrt(tot) <= tol * sqrt(F2)) {
-          __syncthreads();
-          break;
-        }
-        if (s == kcap - 1) status = 3;   // SPID_BLOCK_TOL_NOT_MET
-      }
-      __syncthreads();   // q_lds and red_v reused by the next step
     }
+    ran_out = s == kcap;
+  }
+  if (ran_out && tol > 0.0) {
+    // tolerance after the last step: one more round of per-wave sums
+    const int buf = kcap & 1;
+    const double rw = live_sum();
+    if (lane == 0) cand_r[buf][wave] = rw;
+    lds_barrier();
+    double tot = 0.0;
+    for (int v = 0; v < nwaves; ++v) tot += cand_r[buf][v];
+    if (!(sqrt(tot) <= tol * sqrt(F2))) status = 3;   // SPID_BLOCK_TOL_NOT_MET
   }
   if (tid == 0) {
     k_ws[b] = taken;
     st_ws[b] = status;
   }
-  for (int s = taken + tid; s < k_max; s += nthr) S_ws[(int64_t)b * k_max + s] = -1;
+  for (int t = taken + tid; t < k_max; t += blockDim.x) S_ws[(int64_t)b * k_max + t] = -1;
 }
 
 // ---------------------------------------------------------------------------
 // Column selection for sketches too large for registers alone: thread t owns
 // column t; rows [0, RR) of its sketch column live in registers, rows
 // [RR, l) in LDS laid out row-major over the threads ([r - RR][t], so a
-// wave's accesses are consecutive).  Same steps and reductions as
-// select_kernel.  Dynamic LDS: (l - RR) * blockDim doubles.
+// wave's accesses are consecutive).  Per step: block argmax of the residual
+// norms by wave butterfly and LDS (ties to the lowest index), the owner
+// publishes q = w_p / ||w_p|| in LDS, every column is orthogonalised against
+// q and its norm recomputed.  Dynamic LDS: (l - RR) * blockDim doubles.
 // ---------------------------------------------------------------------------
 template <typename TY, int RR, int MAXTHR>
 __global__ __launch_bounds__(MAXTHR) void select_hybrid_kernel(
@@ -1237,7 +1168,7 @@ __global__ __launch_bounds__(MAXTHR) void select_hybrid_kernel(
         red_v[wave] = bv;
         red_i[wave] = bj;
       }
-      __syncthreads();
+      lds_barrier();
       // every wave reduces the per-wave winners itself (ties to the lowest index); the
       // next write of red_v comes after the pivot barrier below
       double best = lane < nwaves ? red_v[lane] : -1.0;
@@ -1270,9 +1201,9 @@ __global__ __launch_bounds__(MAXTHR) void select_hybrid_kernel(
         nu = 0.0;
       }
       if (tid == 0) S_ws[(int64_t)b * k_max + s] = p;
-      __syncthreads();
+      lds_barrier();
       if (tid < RR + lr) q_lds[tid] = q_lds[tid] / bc_rss;
-      __syncthreads();
+      lds_barrier();
       taken = s + 1;
       double d = 0.0;
 #pragma unroll
@@ -1306,16 +1237,16 @@ __global__ __launch_bounds__(MAXTHR) void select_hybrid_kernel(
       if (tol > 0.0) {
         const double rest = wave_sum(nu);
         if (lane == 0) red_v[wave] = rest;
-        __syncthreads();
+        lds_barrier();
         double tot = 0.0;
         for (int v = 0; v < nwaves; ++v) tot += red_v[v];
         if (sqrt(tot) <= tol * sqrt(F2)) {
-          __syncthreads();
+          lds_barrier();
           break;
         }
         if (s == kcap - 1) status = 3;
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
   if (tid == 0) {

@@ -5,10 +5,24 @@
 namespace spid_host {
 
 
-template <typename TY, int LMAX>
-void launch_select_l(const SelJob<TY>& j, hipStream_t s) {
-  hipLaunchKernelGGL((select_kernel<TY, LMAX, 1>), dim3(j.nblocks), dim3(j.sh.sel_thr), 0, s,
-                     j.blks, j.l, j.k_max, j.tol, j.rank_floor, j.Y, j.R, j.S, j.k, j.st);
+// register kernel: groups of LPC lanes holding 4 columns, RPT rows per lane,
+// one barrier per step
+template <typename TY, int RPT, int LPC, int MAXTHR>
+void launch_select_step(const SelJob<TY>& j, hipStream_t s) {
+  hipLaunchKernelGGL((select_step_kernel<TY, RPT, LPC, 4, MAXTHR>), dim3(j.nblocks),
+                     dim3(j.sh.sel_thr), 0, s, j.blks, j.l, j.k_max, j.tol, j.rank_floor, j.Y,
+                     j.R, j.S, j.k, j.st);
+}
+
+template <typename TY, int LPC, int MAXTHR>
+void launch_select_rpt(const SelJob<TY>& j, hipStream_t s) {
+  // rows per lane: ceil(l / LPC) in fours, so LPC = 4, 8 (l > 32) take 12 or 16
+  if constexpr (LPC == 2) {
+    if (j.sh.sel_rpt == 4) return launch_select_step<TY, 4, LPC, MAXTHR>(j, s);
+    if (j.sh.sel_rpt == 8) return launch_select_step<TY, 8, LPC, MAXTHR>(j, s);
+  }
+  if (j.sh.sel_rpt == 12) launch_select_step<TY, 12, LPC, MAXTHR>(j, s);
+  else launch_select_step<TY, 16, LPC, MAXTHR>(j, s);
 }
 
 template <typename TY, int RR, int MAXTHR>
@@ -18,12 +32,6 @@ bool launch_select_hybrid_t(const SelJob<TY>& j, hipStream_t s) {
   hipLaunchKernelGGL(kern, dim3(j.nblocks), dim3(j.sh.sel_thr), j.sh.sel_lds, s, j.blks, j.l,
                      j.k_max, j.tol, j.rank_floor, j.Y, j.R, j.S, j.k, j.st);
   return true;
-}
-
-template <typename TY, int RPT>
-void launch_select_pair_t(const SelJob<TY>& j, hipStream_t s) {
-  hipLaunchKernelGGL((select_pair_kernel<TY, RPT>), dim3(j.nblocks), dim3(j.sh.sel_thr), 0, s,
-                     j.blks, j.l, j.k_max, j.tol, j.rank_floor, j.Y, j.R, j.S, j.k, j.st);
 }
 
 template <typename TY>
@@ -43,10 +51,10 @@ bool select_job_t(const SelJob<TY>& j, hipStream_t s) {
     }
     return false;   // tall sketches are double precision
   }
-  if (sh.sel_pair) {
-    if (sh.sel_pair == 32) launch_select_pair_t<TY, 32>(j, s);
-    else if (sh.sel_pair == 48) launch_select_pair_t<TY, 48>(j, s);
-    else launch_select_pair_t<TY, 64>(j, s);
+  if (sh.sel_lpc) {
+    if (sh.sel_lpc == 2) launch_select_rpt<TY, 2, 256>(j, s);
+    else if (sh.sel_lpc == 4) launch_select_rpt<TY, 4, 512>(j, s);
+    else launch_select_rpt<TY, 8, 768>(j, s);
     return true;
   }
   if (sh.sel_rr) {
@@ -58,13 +66,7 @@ bool select_job_t(const SelJob<TY>& j, hipStream_t s) {
     if (sh.sel_rr == 32) return launch_select_hybrid_t<TY, 32, 512>(j, s);
     return launch_select_hybrid_t<TY, 16, 512>(j, s);
   }
-  switch (sh.LMAX) {
-    case 16: launch_select_l<TY, 16>(j, s); break;
-    case 32: launch_select_l<TY, 32>(j, s); break;
-    case 48: launch_select_l<TY, 48>(j, s); break;
-    default: launch_select_l<TY, 56>(j, s); break;
-  }
-  return true;
+  return false;   // pick_sel leaves no other case
 }
 
 // Row-split selection of a few very tall coarse sketches: init, then three launches per
