@@ -7,8 +7,10 @@
 //   select_step_kernel pivoted modified Gram-Schmidt on the sketch, one
 //                     workgroup per block, sketch columns in registers (groups
 //                     of lanes holding four columns), one barrier per step.
-//   coeffs_kernel     back-substitution R11 x = R12(:, j), identity columns
-//                     (and the split-bfloat16 coefficients of the mixed error pass).
+//   coeffs_kernel     back-substitution R11 x = R12(:, j) in row blocks of 16
+//                     (diagonal solves in registers, updates on the FP64 matrix
+//                     cores), identity columns (and the split-bfloat16
+//                     coefficients of the mixed error pass).
 //   recon_mfma_kernel streaming residual ||A - A(:,S) P||^2 per row tile, the
 //                     product A(:,S) P on the FP64 matrix cores.
 //   recon_reduce      fixed-order per-block sums of the row-tile partials.
@@ -1271,25 +1273,47 @@ static __global__ void select_export_kernel(int nblocks, int k_max, const int32_
 
 // ---------------------------------------------------------------------------
 // Coefficients: P_b(:, S[t]) = e_t, and for every other column j the
-// back-substitution R11 x = R12(:, j) (Section 2, Algorithm 1), FP64.
-// One workgroup of kCoThreads per block: the non-skeleton columns are listed
-// in ascending order in LDS (the order the error pass uses), R11 is staged in
-// LDS, and each thread solves whole columns with the solution x held in
-// registers (KMAX >= k_max, fully unrolled; R11 entries are LDS broadcasts).
-// When `pt` is given (mixed error pass on FP32 data) the thread also writes
-// its column's three bfloat16 terms (hi, mid, lo: 24 significant bits) and
-// the compact column list, so the error pass stages them by plain copies.
-// Layouts: cols[col_off + q], pt[(col_off + q) * 3 * KP + term * KP + t] with
-// col_off = y_off / l (the block's first column in the batch), KP = 32 KS32.
+// back-substitution R11 x = R12(:, j) (Section 2, Algorithm 1), FP64, done in
+// row blocks of 16.  One workgroup of kCoThreads per block: the non-skeleton
+// columns are listed in ascending order in LDS (the order the error pass
+// uses) and R11 is staged in LDS, padded to KB * 16 rows and columns with the
+// identity past k (the padded unknowns come out as exact zeros and add exact
+// zeros to the real rows).  A wave takes 16 non-skeleton columns at a time,
+// their right-hand sides R12(:, j) held as KB accumulator tiles of the FP64
+// matrix cores (16 rows each).  From the last row block up, the 16 x 16
+// diagonal system is solved by back-substitution, one lane per column through
+// a transpose in LDS (x_s = (b_s - sum_{t > s} R11(s, t) x_t) / R11(s, s), t
+// ascending within the block), and the solved block is taken off every row
+// block above by MFMA products with R11: the arithmetic of the row-by-row
+// back-substitution, the sum over t in blocks.  When `pt` is given (mixed
+// error pass on FP32 data) the wave also writes its columns' three bfloat16
+// terms (hi, mid, lo: 24 significant bits) and the compact column list, so
+// the error pass stages them by plain copies.  Layouts: cols[col_off + q],
+// pt[(col_off + q) * 3 * KP + term * KP + t] with col_off = y_off / l (the
+// block's first column in the batch), KP = 32 KS32.
 // ---------------------------------------------------------------------------
 constexpr int kCoThreads = 256;
+constexpr int kCoSld = 17;    // row stride of a wave's 16 x 16 staging tile (doubles)
 
-template <int KMAX>
+// LDS of coeffs_kernel<KB>: R11 padded to 16 KB rows, row stride 16 KB + 1
+__host__ __device__ constexpr size_t coeffs_lds_bytes(int KB) {
+  return sizeof(double) * (size_t)(16 * KB) * (16 * KB + 1);
+}
+
+// wave-local ordering of LDS accesses (the wave's own writes before its reads)
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+template <int KB>
 __global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
     const BlkInfo* __restrict__ blks, int l, int k_max, const double* __restrict__ R,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws, double* __restrict__ P,
     __bf16* __restrict__ pt, int KP, int32_t* __restrict__ cols_out, int32_t* __restrict__ ncols_out) {
-  extern __shared__ double r11[];               // [k][k] row-major, zero below the diagonal
+  constexpr int KM = 16 * KB;          // padded rank
+  constexpr int LD = KM + 1;           // R11 row stride in LDS (odd: spreads the banks)
+  extern __shared__ double r11[];      // [KM][LD]
+  __shared__ double stage[kCoThreads / 64][16 * kCoSld];
   __shared__ int cols[1024];
   __shared__ unsigned char is_sel[1024];
   __shared__ int wcount[kCoThreads / 64];
@@ -1301,9 +1325,12 @@ __global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
   const int32_t* S = S_ws + (int64_t)b * k_max;
   const double* Rb = R + bi.r_off;
   double* Pb = P + bi.p_off;
-  for (int e = tid; e < k * k; e += kCoThreads) {
-    const int s2 = e / k, t = e - s2 * k;
-    r11[s2 * k + t] = (t >= s2) ? Rb[(int64_t)s2 * n + S[t]] : 0.0;
+  for (int e = tid; e < KM * KM; e += kCoThreads) {
+    const int s2 = e / KM, t = e - s2 * KM;
+    double v = 0.0;
+    if (s2 < k && t < k) v = (t >= s2) ? Rb[(int64_t)s2 * n + S[t]] : 0.0;
+    else if (s2 == t) v = 1.0;
+    r11[s2 * LD + t] = v;
   }
   // compact list of the non-skeleton columns (ascending)
   for (int j = tid; j < n; j += kCoThreads) is_sel[j] = 0;
@@ -1333,64 +1360,93 @@ __global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
     double* pc = Pb + (int64_t)S[t] * k_max;
     for (int u = 0; u < k_max; ++u) pc[u] = (u == t) ? 1.0 : 0.0;
   }
-  for (int q = tid; q < ncols; q += kCoThreads) {
-    const int j = cols[q];
-    double x[KMAX];
+  double* st = stage[wave];
+  const int c16 = lane & 15, g4 = lane >> 4;
+  const int ntiles = (ncols + 15) / 16;
+  for (int tile = wave; tile < ntiles; tile += kCoThreads / 64) {
+    const int cq = tile * 16 + c16;          // compact index of the lane's column
+    const bool cok = cq < ncols;
+    const int j = cok ? cols[cq] : 0;
+    // right-hand sides R12(:, j): tile r, slot v holds row 16 r + g4 + 4 v
+    f64x4 acc[KB];
 #pragma unroll
-    for (int s2 = KMAX - 1; s2 >= 0; --s2) {
-      x[s2] = 0.0;
-      if (s2 < k) {
-        double acc = Rb[(int64_t)s2 * n + j];
-        const double* rr = r11 + s2 * k;
+    for (int r = 0; r < KB; ++r)
 #pragma unroll
-        for (int t = s2 + 1; t < KMAX; ++t)
-          if (t < k) acc -= rr[t] * x[t];
-        x[s2] = acc / rr[s2];
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * r + g4 + 4 * v;
+        acc[r][v] = (cok && row < k) ? Rb[(int64_t)row * n + j] : 0.0;
       }
+#pragma unroll
+    for (int B = KB - 1; B >= 0; --B) {
+      // row block B to one lane per column
+#pragma unroll
+      for (int v = 0; v < 4; ++v) st[(g4 + 4 * v) * kCoSld + c16] = acc[B][v];
+      wave_lds_sync();
+      if (lane < 16) {
+        double x[16];
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+          const double* rr = r11 + (16 * B + i) * LD + 16 * B;
+          double a = st[i * kCoSld + lane];
+#pragma unroll
+          for (int t = i + 1; t < 16; ++t) a -= rr[t] * x[t];
+          x[i] = a / rr[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) st[i * kCoSld + lane] = x[i];
+      }
+      wave_lds_sync();
+      // the solved block in accumulator layout (for the output) and as the
+      // MFMA B operand (k-step qk: rows 4 qk .. 4 qk + 3)
+      double bop[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[B][v] = st[(g4 + 4 * v) * kCoSld + c16];
+#pragma unroll
+      for (int qk = 0; qk < 4; ++qk) bop[qk] = st[(4 * qk + g4) * kCoSld + c16];
+      wave_lds_sync();   // the next transpose overwrites the staging tile
+      // rows above: b(rows r) -= R11(rows r, columns of B) x_B
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int qk = 0; qk < 4; ++qk) {
+          const double a = -r11[(16 * r + c16) * LD + 16 * B + 4 * qk + g4];
+          acc[r] = mfma_f64(a, bop[qk], acc[r]);
+        }
     }
+    if (!cok) continue;
+    // P(:, j): rows below k_max (rows past k are exact zeros)
     double* pc = Pb + (int64_t)j * k_max;
-    if ((k_max & 1) == 0) {
-      // 16-byte stores (an even k_max keeps every column start 16-byte aligned)
 #pragma unroll
-      for (int t0 = 0; t0 < KMAX; t0 += 2)
-        if (t0 < k_max)
-          *reinterpret_cast<f64x2*>(pc + t0) =
-              f64x2{t0 < k ? x[t0] : 0.0, t0 + 1 < k ? x[t0 + 1] : 0.0};
-    } else {
+    for (int r = 0; r < KB; ++r)
 #pragma unroll
-      for (int t = 0; t < KMAX; ++t)
-        if (t < k_max) pc[t] = (t < k) ? x[t] : 0.0;
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * r + g4 + 4 * v;
+        if (row < k_max) pc[row] = acc[r][v];
+      }
     if (pt) {
-      cols_out[col_off + q] = j;
-      // three bfloat16 terms, eight at a time (16-byte stores: KP is a multiple of 32)
-      __bf16* o = pt + (col_off + q) * 3 * KP;
+      if (g4 == 0) cols_out[col_off + cq] = j;
+      // three bfloat16 terms of every coefficient, rows past 16 KB zero up to KP
+      __bf16* o = pt + (col_off + cq) * 3 * KP;
 #pragma unroll
-      for (int t0 = 0; t0 < KMAX; t0 += 8) {
-        if (t0 < KP) {
-          bf16x8 vh, vm, vl;
+      for (int r = 0; r < KB; ++r)
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int t = t0 + e;
-            const double pv = (t < k) ? x[t] : 0.0;
-            const __bf16 h = to_bf16((float)pv);
-            const double r1 = pv - (double)(float)h;
+        for (int v = 0; v < 4; ++v) {
+          const int t = 16 * r + g4 + 4 * v;
+          if (t < KP) {
+            const double pv = acc[r][v];
+            const __bf16 hi = to_bf16((float)pv);
+            const double r1 = pv - (double)(float)hi;
             const __bf16 md = to_bf16((float)r1);
             const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
-            vh[e] = h;
-            vm[e] = md;
-            vl[e] = lo;
+            o[t] = hi;
+            o[KP + t] = md;
+            o[2 * KP + t] = lo;
           }
-          *reinterpret_cast<bf16x8*>(o + t0) = vh;
-          *reinterpret_cast<bf16x8*>(o + KP + t0) = vm;
-          *reinterpret_cast<bf16x8*>(o + 2 * KP + t0) = vl;
         }
-      }
-      const bf16x8 zero8 = {};
-      for (int t0 = KMAX; t0 < KP; t0 += 8) {
-        *reinterpret_cast<bf16x8*>(o + t0) = zero8;
-        *reinterpret_cast<bf16x8*>(o + KP + t0) = zero8;
-        *reinterpret_cast<bf16x8*>(o + 2 * KP + t0) = zero8;
+      for (int t = KM + g4; t < KP; t += 4) {
+        o[t] = to_bf16(0.0f);
+        o[KP + t] = to_bf16(0.0f);
+        o[2 * KP + t] = to_bf16(0.0f);
       }
     }
   }

@@ -63,13 +63,13 @@ bool launch_recon_a(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   }
 }
 
-template <int KMAX>
+template <int KB>
 bool launch_coeffs_t(spid_ctx* c, double* P, hipStream_t s) {
   const Plan& p = c->plan;
-  const size_t lds = sizeof(double) * (size_t)c->desc.k_max * c->desc.k_max;
-  if (!allow_lds((const void*)coeffs_kernel<KMAX>, lds)) return false;
+  const size_t lds = coeffs_lds_bytes(KB);
+  if (!allow_lds((const void*)coeffs_kernel<KB>, lds)) return false;
   const bool bf = p.sh.rc_bf16 != 0;
-  hipLaunchKernelGGL((coeffs_kernel<KMAX>), dim3(c->desc.nblocks), dim3(kCoThreads), lds, s,
+  hipLaunchKernelGGL((coeffs_kernel<KB>), dim3(c->desc.nblocks), dim3(kCoThreads), lds, s,
                      c->at<BlkInfo>(p.off_blk), c->desc.l, c->desc.k_max, c->at<double>(p.off_R),
                      c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
                      bf ? c->at<__bf16>(p.off_pt) : nullptr, 32 * p.sh.KS32,
@@ -123,12 +123,12 @@ bool launch_interp_a(spid_ctx* c, const double* P, void* cskel, hipStream_t s) {
   return true;
 }
 
-template <int KMAX>
+template <int KB>
 bool launch_coeffs_job(const BlkInfo* blks, int nblocks, int l, int k_max, const double* R,
                        const int32_t* S, const int32_t* k, double* P, hipStream_t s) {
-  const size_t lds = sizeof(double) * (size_t)k_max * k_max;
-  if (!allow_lds((const void*)coeffs_kernel<KMAX>, lds)) return false;
-  hipLaunchKernelGGL((coeffs_kernel<KMAX>), dim3(nblocks), dim3(kCoThreads), lds, s, blks, l,
+  const size_t lds = coeffs_lds_bytes(KB);
+  if (!allow_lds((const void*)coeffs_kernel<KB>, lds)) return false;
+  hipLaunchKernelGGL((coeffs_kernel<KB>), dim3(nblocks), dim3(kCoThreads), lds, s, blks, l,
                      k_max, R, S, k, P, (__bf16*)nullptr, 32, (int32_t*)nullptr,
                      (int32_t*)nullptr);
   return true;
@@ -138,24 +138,23 @@ bool launch_coeffs_any(int kmax_t, const BlkInfo* blks, int nblocks, int l, int 
                        const double* R, const int32_t* S, const int32_t* k, double* P,
                        hipStream_t s) {
   switch (kmax_t) {
-    case 8: return launch_coeffs_job<8>(blks, nblocks, l, k_max, R, S, k, P, s);
-    case 16: return launch_coeffs_job<16>(blks, nblocks, l, k_max, R, S, k, P, s);
-    case 32: return launch_coeffs_job<32>(blks, nblocks, l, k_max, R, S, k, P, s);
-    case 48: return launch_coeffs_job<48>(blks, nblocks, l, k_max, R, S, k, P, s);
-    case 64: return launch_coeffs_job<64>(blks, nblocks, l, k_max, R, S, k, P, s);
-    default: return launch_coeffs_job<96>(blks, nblocks, l, k_max, R, S, k, P, s);
+    case 8:
+    case 16: return launch_coeffs_job<1>(blks, nblocks, l, k_max, R, S, k, P, s);
+    case 32: return launch_coeffs_job<2>(blks, nblocks, l, k_max, R, S, k, P, s);
+    case 48: return launch_coeffs_job<3>(blks, nblocks, l, k_max, R, S, k, P, s);
+    case 64: return launch_coeffs_job<4>(blks, nblocks, l, k_max, R, S, k, P, s);
+    default: return launch_coeffs_job<6>(blks, nblocks, l, k_max, R, S, k, P, s);
   }
 }
 
-
 bool launch_coeffs_ctx(spid_ctx* c, double* P, hipStream_t s) {
   switch (c->plan.sh.KMAX) {
-    case 8: return launch_coeffs_t<8>(c, P, s);
-    case 16: return launch_coeffs_t<16>(c, P, s);
-    case 32: return launch_coeffs_t<32>(c, P, s);
-    case 48: return launch_coeffs_t<48>(c, P, s);
-    case 64: return launch_coeffs_t<64>(c, P, s);
-    default: return launch_coeffs_t<96>(c, P, s);
+    case 8:
+    case 16: return launch_coeffs_t<1>(c, P, s);
+    case 32: return launch_coeffs_t<2>(c, P, s);
+    case 48: return launch_coeffs_t<3>(c, P, s);
+    case 64: return launch_coeffs_t<4>(c, P, s);
+    default: return launch_coeffs_t<6>(c, P, s);
   }
 }
 
