@@ -52,6 +52,9 @@ def parse():
                          "snapshots on one stream, the sketch updates run on another")
     ap.add_argument("--solver-substeps", type=int, default=1,
                     help="--insitu: solver steps per stored snapshot")
+    ap.add_argument("--data", choices=("workload", "gaussian"), default="workload",
+                    help="gaussian: the workload's block shapes with i.i.d. N(0,1) entries drawn "
+                         "by a few generator calls (profiling runs with few non-library kernels)")
     ap.add_argument("--profile-region", action="store_true",
                     help="mark only the timed steps for rocprofv3 --selected-regions "
                          "(roctxProfilerResume / roctxProfilerPause): data generation, tuning, "
@@ -106,7 +109,10 @@ def main():
     def progress(f, j):
         if j == 0 or j == w.n - 1:
             log(args, f"  generating field {f} snapshot {j}")
-    A, m, n, off = si.generate(w, device=dev, progress=progress)
+    if args.data == "gaussian":
+        A, m, n, off = si.gaussian_like(w, device=dev)
+    else:
+        A, m, n, off = si.generate(w, device=dev, progress=progress)
     torch.cuda.synchronize()
     log(args, f"generated {w.name}: {A.numel() * A.element_size() / 1e9:.2f} GB in "
               f"{time.time() - t0:.1f}s")
@@ -200,7 +206,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if w.prec in ("f64", "subsample") else f"{w.prec}-sketch/f64",
-        "data": "synthetic",
+        "data": "synthetic" if args.data == "workload" else "synthetic, i.i.d. gaussian entries",
         "config": {"workload": w.name, "description": w.description,
                    "nblocks": int(len(m)), "bytes": nbytes, "l": w.l, "k_max": w.k_max,
                    "tol": w.tol, "sketch_update": "one snapshot per call" if w.stream

@@ -190,7 +190,7 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
       sh.RPI = kRcBfSubs;
     } else {
       // coefficient staging: as many columns as the LDS budget holds (multiple of 16)
-      const size_t per_col = 8 * 4 * (size_t)sh.KS;
+      const size_t per_col = 8 * (4 * (size_t)sh.KS + 1);   // padded LDS stride
       const int cap = (int)(kRcLdsBytes / per_col) / 16 * 16;
       const int need = (p.max_n + 15) / 16 * 16;
       sh.PCAP = std::max(16, std::min(cap, need));
@@ -270,6 +270,26 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   }
   p.rc_first.push_back((int64_t)p.rc.size());
   p.part_elems = part_off;
+  {
+    // error-pass items cut into 8 contiguous ranges of about equal cost (rows x
+    // columns streamed), one per XCD
+    std::vector<double> pre(p.rc.size() + 1, 0.0);
+    for (size_t i = 0; i < p.rc.size(); ++i) {
+      const RcItem& r = p.rc[i];
+      const double rows = std::min<double>((double)r.nsub * sh.RC_SUB, (double)(d->h_m[r.blk] - r.i0));
+      pre[i + 1] = pre[i] + rows * d->h_n[r.blk];
+    }
+    size_t cut = 0, longest = 0;
+    p.rc_xcd.start[0] = 0;
+    for (int x = 1; x <= 8; ++x) {
+      const double goal = pre.back() * x / 8.0;
+      while (cut < p.rc.size() && pre[cut] < goal) ++cut;
+      if (x == 8) cut = p.rc.size();
+      p.rc_xcd.start[x] = (int32_t)cut;
+      longest = std::max<size_t>(longest, cut - (size_t)p.rc_xcd.start[x - 1]);
+    }
+    p.rc_xcd_grid = (unsigned)(8 * std::max<size_t>(1, longest));
+  }
 
   if (p.coarse) {
     p.grid.resize(nb);

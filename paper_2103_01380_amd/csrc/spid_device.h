@@ -223,6 +223,24 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aware work-item order.  The hardware deals the workgroups of a launch to
+// the 8 XCDs in turn (workgroup w to XCD w % 8), each XCD with its own L2.
+// XCD x takes the contiguous items [start[x], start[x + 1]) in order (the host
+// cuts the list into 8 ranges of about equal cost), so consecutive items that
+// share data (the row ranges of one block, which share its coefficients) meet
+// in one L2.  The grid is 8 * the longest range; -1 for the padding workgroups.
+// ---------------------------------------------------------------------------
+struct XcdSplit {
+  int32_t start[9];
+};
+
+__device__ __forceinline__ int xcd_item(const XcdSplit& sp) {
+  const int x = (int)(blockIdx.x & 7);
+  const int it = sp.start[x] + (int)(blockIdx.x >> 3);
+  return it < sp.start[x + 1] ? it : -1;
+}
+
+// ---------------------------------------------------------------------------
 // Wave reductions (64 lanes, fixed butterfly order -> deterministic).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

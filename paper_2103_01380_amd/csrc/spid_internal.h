@@ -129,6 +129,8 @@ struct Plan {
   std::vector<int32_t> split_blocks;
   std::vector<RcItem> rc;
   std::vector<int64_t> rc_first;
+  XcdSplit rc_xcd{};          // error-pass items per XCD (ranges of about equal cost)
+  unsigned rc_xcd_grid = 0;   // 8 * the longest range
   // one-snapshot updates: blocks ordered by m (perm), groups of kStreamGroup
   // equal-m blocks x K ranges (sitems), heads of groups with several K ranges
   bool st_ok = false;

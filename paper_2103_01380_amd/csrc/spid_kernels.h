@@ -1536,17 +1536,21 @@ __device__ __forceinline__ void rc_load4(gptr<TA> __restrict__ colp, int64_t i0,
 // ---------------------------------------------------------------------------
 template <typename TA, int KS, int MTR, bool VEC>
 __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
-    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int k_max, int pcap,
+    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, XcdSplit xs, int k_max, int pcap,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
     const double* __restrict__ P, TA* __restrict__ skel, double* __restrict__ part) {
-  extern __shared__ __attribute__((aligned(16))) double p_lds[];   // [pcap][kp]
+  // [pcap][kp + 1]: the odd stride puts the 16 columns one MFMA reads on
+  // different banks (a stride of kp, a multiple of 16 doubles, is one bank)
+  extern __shared__ __attribute__((aligned(16))) double p_lds[];
   __shared__ double red[8];
   __shared__ int cols[1024];
   __shared__ unsigned char is_sel[1024];
   __shared__ int wcount[4];
   constexpr int kp = 4 * KS;
   constexpr int kSub = 4 * 16 * MTR;
-  const RcItem it = items[blockIdx.x];
+  const int item = xcd_item(xs);
+  if (item < 0) return;
+  const RcItem it = items[item];
   const BlkInfo bi = blks[it.blk];
   const int n = bi.n;
   const int k = k_ws[it.blk];
@@ -1570,7 +1574,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
       const bool ok = q < cc && t < k_max;
       const double x = cc > 0 ? Pb[(int64_t)cols[c0 + min(q, cc - 1)] * k_max + min(t, k_max - 1)]
                               : 0.0;
-      p_lds[e] = ok ? x : 0.0;   // P rows k..k_max-1 are zero
+      p_lds[q * (kp + 1) + t] = ok ? x : 0.0;   // P rows k..k_max-1 are zero
     }
     __syncthreads();
     for (int rs = 0; rs < it.nsub; ++rs) {
@@ -1599,7 +1603,7 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt)
           rc_load4<TA, VEC>(colp, rbase + 16 * mt + 4 * g, bi.m, cok, av[mt]);
-        const double* pc = p_lds + q * kp + g;
+        const double* pc = p_lds + q * (kp + 1) + g;
         f64x4 acc[MTR];
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -1631,8 +1635,8 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
   }
   __syncthreads();
   if (tid == 0) {
-    part[2 * (int64_t)blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-    part[2 * (int64_t)blockIdx.x + 1] = red[4] + red[5] + red[6] + red[7];
+    part[2 * (int64_t)item] = red[0] + red[1] + red[2] + red[3];
+    part[2 * (int64_t)item + 1] = red[4] + red[5] + red[6] + red[7];
   }
 }
 
@@ -1657,16 +1661,22 @@ constexpr int kRcBfSubs = 2;
 
 template <int KS32, int MTR, bool VEC>
 __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
-    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, int l, int k_max,
+    const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, XcdSplit xs, int l, int k_max,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
     const __bf16* __restrict__ pt_g, const int32_t* __restrict__ cols_g,
     const int32_t* __restrict__ ncols_g, float* __restrict__ skel, double* __restrict__ part) {
   constexpr int KP = 32 * KS32;
   constexpr int kSub = 4 * 16 * MTR;
-  __shared__ __attribute__((aligned(16))) __bf16 pt[kRcBfCols][3][KP];
+  // a column's three terms, 3 KP bfloat16 (a multiple of 32 dwords), then 8
+  // bfloat16 of padding: the 16 columns one MFMA reads start 4 banks apart
+  // instead of on one bank
+  constexpr int kPtStride = 3 * KP + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 pt[kRcBfCols * kPtStride];
   __shared__ int cols[kRcBfCols];
   __shared__ double red[8];
-  const RcItem it = items[blockIdx.x];
+  const int item = xcd_item(xs);
+  if (item < 0) return;
+  const RcItem it = items[item];
   const BlkInfo bi = blks[it.blk];
   const int k = k_ws[it.blk];
   const int32_t* S = S_ws + (int64_t)it.blk * k_max;
@@ -1715,11 +1725,11 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
     const int cc = min(kRcBfCols, ncols - c0);
     constexpr int kVec = kRcBfCols * 3 * KP / 8;   // 16-byte pieces of the chunk
     for (int e = tid; e < kVec; e += kRcThreads) {
-      const int q = e / (3 * KP / 8);
+      const int q = e / (3 * KP / 8), r8 = e - q * (3 * KP / 8);
       if (8 * (e % (KP / 8)) >= 32 * ksn) continue;   // terms of k-steps that are skipped
       bf16x8 v = bf16x8{};
       if (q < cc) v = *reinterpret_cast<const bf16x8*>(ptb + (int64_t)c0 * 3 * KP + (int64_t)e * 8);
-      *reinterpret_cast<bf16x8*>(&pt[0][0][0] + (int64_t)e * 8) = v;
+      *reinterpret_cast<bf16x8*>(pt + q * kPtStride + 8 * r8) = v;
     }
     if (tid < kRcBfCols) cols[tid] = (tid < cc) ? colb[c0 + tid] : 0;
     __syncthreads();
@@ -1750,9 +1760,10 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
 #pragma unroll
         for (int ks = 0; ks < KS32; ++ks) {
           if (ks >= ksn) break;     // uniform: zero terms add nothing
-          const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(&pt[q0 + c16][0][32 * ks + 8 * g]);
-          const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(&pt[q0 + c16][1][32 * ks + 8 * g]);
-          const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(&pt[q0 + c16][2][32 * ks + 8 * g]);
+          const __bf16* pq = pt + (q0 + c16) * kPtStride + 32 * ks + 8 * g;
+          const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(pq);
+          const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(pq + KP);
+          const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(pq + 2 * KP);
 #pragma unroll
           for (int mt = 0; mt < MTR; ++mt) {
             // smallest terms first
@@ -1785,8 +1796,8 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
   }
   __syncthreads();
   if (tid == 0) {
-    part[2 * (int64_t)blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-    part[2 * (int64_t)blockIdx.x + 1] = red[4] + red[5] + red[6] + red[7];
+    part[2 * (int64_t)item] = red[0] + red[1] + red[2] + red[3];
+    part[2 * (int64_t)item + 1] = red[4] + red[5] + red[6] + red[7];
   }
 }
 

@@ -9,11 +9,11 @@ namespace spid_host {
 template <typename TA, int KS, int MTR>
 bool launch_recon_t(spid_ctx* c, const double* P, void* skel, hipStream_t s) {
   const Plan& p = c->plan;
-  const size_t lds = sizeof(double) * p.sh.PCAP * 4 * KS;
+  const size_t lds = sizeof(double) * p.sh.PCAP * (4 * KS + 1);
   auto launch = [&](auto kern) {
     if (!allow_lds((const void*)kern, lds)) return false;
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), lds, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.k_max,
+    hipLaunchKernelGGL(kern, dim3(p.rc_xcd_grid), dim3(kRcThreads), lds, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), p.rc_xcd, c->desc.k_max,
                        p.sh.PCAP, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
                        static_cast<TA*>(skel), c->at<double>(p.off_rcpart));
     return true;
@@ -28,8 +28,8 @@ bool launch_recon_bf16_t(spid_ctx* c, const double* P, void* skel, hipStream_t s
   (void)P;   // the split coefficients written by spid_coeffs are used
   const Plan& p = c->plan;
   auto launch = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), 0, s,
-                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), c->desc.l,
+    hipLaunchKernelGGL(kern, dim3(p.rc_xcd_grid), dim3(kRcThreads), 0, s,
+                       c->at<BlkInfo>(p.off_blk), c->at<RcItem>(p.off_rc), p.rc_xcd, c->desc.l,
                        c->desc.k_max, c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
                        c->at<__bf16>(p.off_pt), c->at<int32_t>(p.off_cols),
                        c->at<int32_t>(p.off_ncols), static_cast<float*>(skel),
@@ -81,12 +81,13 @@ bool launch_coeffs_t(spid_ctx* c, double* P, hipStream_t s) {
 template <typename TA, int KS, int MTR>
 bool launch_interp_t(spid_ctx* c, const double* P, hipStream_t s) {
   const Plan& p = c->plan;
-  const size_t lds = sizeof(double) * p.sh.PCAP * 4 * KS;
+  const size_t lds = sizeof(double) * p.sh.PCAP * (4 * KS + 1);
   auto launch = [&](auto kern) {
     if (!allow_lds((const void*)kern, lds)) return false;
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.rc.size()), dim3(kRcThreads), lds, s,
+    hipLaunchKernelGGL(kern, dim3(p.rc_xcd_grid), dim3(kRcThreads), lds, s,
                        c->at<BlkInfo>(p.off_blk), c->at<GridInfo>(p.off_grid),
-                       c->at<RcItem>(p.off_rc), c->desc.l, c->desc.k_max, p.sh.PCAP,
+                       c->at<RcItem>(p.off_rc), p.rc_xcd, c->desc.l, c->desc.k_max,
+                       p.sh.PCAP,
                        c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k),
                        c->at<double>(p.off_Y), P, c->at<double>(p.off_rcpart));
     return true;

@@ -589,14 +589,18 @@ static __global__ __launch_bounds__(kSplitThreads) void split_update_kernel(
 template <typename TA, int KS, int MTR, bool VEC>
 __global__ __launch_bounds__(kRcThreads) void interp_mfma_kernel(
     const BlkInfo* __restrict__ blks, const GridInfo* __restrict__ grids,
-    const RcItem* __restrict__ items, int l, int k_max, int pcap,
+    const RcItem* __restrict__ items, XcdSplit xs, int l, int k_max, int pcap,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
     const double* __restrict__ Y, const double* __restrict__ P, double* __restrict__ part) {
-  extern __shared__ __attribute__((aligned(16))) double p_lds[];   // [pcap][kp]
+  // [pcap][kp + 1]: the odd stride puts the 16 columns one MFMA reads on
+  // different banks (a stride of kp, a multiple of 16 doubles, is one bank)
+  extern __shared__ __attribute__((aligned(16))) double p_lds[];
   __shared__ double red[8];
   constexpr int kp = 4 * KS;
   constexpr int kSub = 4 * 16 * MTR;
-  const RcItem it = items[blockIdx.x];
+  const int item = xcd_item(xs);
+  if (item < 0) return;
+  const RcItem it = items[item];
   const BlkInfo bi = blks[it.blk];
   const GridInfo gr = grids[it.blk];
   const int n = bi.n;
@@ -619,7 +623,7 @@ __global__ __launch_bounds__(kRcThreads) void interp_mfma_kernel(
       const int q = e / kp, t = e - q * kp;
       const bool ok = q < cc && t < k_max;
       const double x = Pb[(int64_t)(c0 + min(q, cc - 1)) * k_max + min(t, k_max - 1)];
-      p_lds[e] = ok ? x : 0.0;   // P rows k..k_max-1 are zero
+      p_lds[q * (kp + 1) + t] = ok ? x : 0.0;   // P rows k..k_max-1 are zero
     }
     __syncthreads();
     for (int rs = 0; rs < it.nsub; ++rs) {
@@ -671,7 +675,7 @@ __global__ __launch_bounds__(kRcThreads) void interp_mfma_kernel(
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt)
           rc_load4<TA, VEC>(colp, rbase + 16 * mt + 4 * g, bi.m, cok, av[mt]);
-        const double* pc = p_lds + q * kp + g;
+        const double* pc = p_lds + q * (kp + 1) + g;
         f64x4 acc[MTR];
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt) acc[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -703,8 +707,8 @@ __global__ __launch_bounds__(kRcThreads) void interp_mfma_kernel(
   }
   __syncthreads();
   if (tid == 0) {
-    part[2 * (int64_t)blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-    part[2 * (int64_t)blockIdx.x + 1] = red[4] + red[5] + red[6] + red[7];
+    part[2 * (int64_t)item] = red[0] + red[1] + red[2] + red[3];
+    part[2 * (int64_t)item + 1] = red[4] + red[5] + red[6] + red[7];
   }
 }
 

@@ -475,6 +475,32 @@ def generate(w: Workload, device="cpu", progress=None):
     return A, m, n, off
 
 
+def gaussian_like(w: Workload, device="cpu", seed: int | None = None):
+    """A batch with the workload's block shapes and data type but i.i.d. N(0, 1)
+    entries, drawn with a handful of generator calls (profiling runs, where the
+    streaming kernels' traffic and instruction counts do not depend on the
+    values; the selection then takes k_max pivots in every block).  Returns
+    (tensor, m[], n[], offsets[]) as ``generate``."""
+    dt = torch.float32 if w.a_dtype == "f32" else torch.float64
+    gen = torch.Generator(device=device)
+    gen.manual_seed(w.data_seed if seed is None else seed)
+    if w.kind == "lowrank":
+        sh = lowrank_shapes(w, **w.extra.get("shape", {}))
+        m, n, off, total = sh.m, sh.n, sh.offsets, sh.total
+        A = torch.empty(total, device=device, dtype=dt)
+    else:
+        nb = w.nblocks
+        m = np.full(nb, w.m_b, dtype=np.int64)
+        n = np.full(nb, w.n, dtype=np.int32)
+        off = np.arange(nb, dtype=np.int64) * (w.n * w.m_b)
+        A = torch.empty((nb, w.n, w.m_b), device=device, dtype=dt)
+    flat = A.view(-1)
+    chunk = 1 << 30
+    for o in range(0, flat.numel(), chunk):
+        flat[o:o + chunk].normal_(generator=gen)
+    return A, m, n, off
+
+
 def block_view(A: torch.Tensor, m, n, off, b: int) -> np.ndarray:
     """Host numpy column-major view (copy) of block b."""
     flat = A.reshape(-1)
