@@ -12,7 +12,8 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["spid.hip", "spid_sketch_f64.hip", "spid_sketch_bf16.hip", "spid_sketch_fp8.hip",
+SOURCES = ["spid.hip", "spid_sketch_f64.hip", "spid_sketch_bf16.hip", "spid_sketch_bf16_tab.hip",
+           "spid_sketch_fp8.hip",
            "spid_select.hip", "spid_recon.hip"]
 OUT = os.path.join(HERE, "libspid.so")
 OBJ_DIR = os.path.join(HERE, "_build")

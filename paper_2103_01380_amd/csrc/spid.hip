@@ -473,6 +473,12 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_sitems = take(sizeof(SkItem) * std::max<size_t>(1, p.sitems.size()));
   p.off_sheads = take(sizeof(int32_t) * std::max<size_t>(1, p.sheads.size()));
   p.off_ritems = take(sizeof(int32_t) * std::max<size_t>(1, p.ritems.size()));
+  if (d->prec == SPID_SK_BF16 && d->omega_per_block == 0 && !p.coarse) {
+    int64_t max_m = 0;
+    for (int b = 0; b < nb; ++b) max_m = std::max<int64_t>(max_m, d->h_m[b]);
+    p.omtab_cols = (max_m + kKC - 1) / kKC * kKC;
+  }
+  p.off_omtab = take(sizeof(uint16_t) * (size_t)sh.MT * 16 * (size_t)std::max<int64_t>(1, p.omtab_cols));
   // mixed error pass: split-bfloat16 coefficients and compact column lists
   const size_t kp_bf = 32 * (size_t)sh.KS32;
   p.off_pt = take(sh.rc_bf16 ? sizeof(uint16_t) * 3 * kp_bf * (size_t)p.sum_n : 256);
@@ -655,6 +661,11 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
   if (e == hipSuccess && p.ts_nwin > 0)
     e = hipMemcpy(c->ws + p.off_tsblk2, p.ts_blk2.data(), sizeof(BlkInfo) * p.ts_blk2.size(),
                   hipMemcpyHostToDevice);
+  // shared bfloat16 sketch matrix, generated once (the sketch kernels read it)
+  if (e == hipSuccess && p.omtab_cols > 0) {
+    if (!launch_omega_table(c, nullptr)) e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  }
 
   if (e != hipSuccess) {
     delete c;

@@ -155,6 +155,11 @@ struct Plan {
   int64_t ts_n2sum = 0;
   int64_t sum_n = 0, sum_m = 0, part_elems = 0;
   int max_n = 0, max_split_n = 0;
+  // bfloat16 sketch with Omega shared by all blocks: the sketch matrix as a
+  // table in MFMA operand order (MT*16 rows x omtab_cols columns), written at
+  // create (omtab_cols = max m rounded up to the 32-row chunk; 0: no table)
+  int64_t omtab_cols = 0;
+  size_t off_omtab = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
       off_st, off_rcpart, off_perm, off_sitems, off_sheads, off_ritems, off_pt, off_cols, off_ncols,
       off_grid, off_W, off_spoff, off_spnorm, off_spdot, off_spused, off_spstate, off_spbad,
@@ -211,6 +216,9 @@ struct SelJob {
 // sketch of columns [j0, j1) of every block, one launch over the batch items
 void sketch_batch_f64(spid_ctx* c, int j0, int j1, hipStream_t s);    // spid_sketch_f64.hip
 void sketch_batch_bf16(spid_ctx* c, int j0, int j1, hipStream_t s);   // spid_sketch_bf16.hip
+void sketch_batch_bf16_tab(spid_ctx* c, int j0, int j1, hipStream_t s); // spid_sketch_bf16_tab.hip
+// the bfloat16 Omega table (spid_sketch_bf16_tab.hip); false if the launch failed
+bool launch_omega_table(spid_ctx* c, hipStream_t s);
 void sketch_batch_fp8(spid_ctx* c, int j0, int j1, hipStream_t s);    // spid_sketch_fp8.hip
 // one-snapshot sketch of column j (blocks as the MFMA columns); false if the
 // LDS opt-in failed

@@ -334,37 +334,181 @@ __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Sketch, bfloat16 (FP32 accumulation): Omega rounded to nearest-even
-// bfloat16 in LDS; A split into `terms` bfloat16 terms in registers
-// (hi = bf16(a), lo = bf16(a - hi), lo2 = bf16(a - hi - lo));
-// v_mfma_f32_16x16x32_bf16.  Lane (g, r16) supplies rows 16h + 4g + e
-// (h = 0..1, e = 0..3) of its column as the 8 k-values of one MFMA (64
-// contiguous bytes per column and load instruction); Omega row 16t+r16
-// supplies the same rows.  Same software pipeline as the double-precision
-// kernel.
+// Loads of A in whole 128-byte lines.  A load instruction whose lanes read
+// only 64 contiguous bytes of each column (four lanes per column, the MFMA
+// operand layout) streams at about 5.4 TB/s on MI355X; one whose eight lanes
+// per column read a whole 128-byte line reaches about 7 TB/s.  So a wave
+// loads each 32-row chunk of its 16-column tiles as two instructions per
+// tile: instruction h covers columns 8h..8h+7 of the tile, lane
+// (c8 = lane / 8, p = lane % 8) reading rows 4p..4p+3 of column 8h + c8
+// (FP64 A: rows 2p, 2p+1 and 16+2p, 17+2p, two 16-byte loads), and passes
+// them through a wave-private LDS tile (column stride 36 floats: both the
+// writes and the operand reads are free of bank conflicts) into the MFMA
+// operand layout.  No barrier: a wave's LDS operations run in order.
 // ---------------------------------------------------------------------------
-template <typename TA, int MT, int TN, int NW, bool VEC, bool ST>
+constexpr int kLineSt = kKC + 4;   // floats per staged column
+
+template <typename TA, int TN>
+struct SkLines {
+  gptr<TA> cb[TN][2];   // load column starts (an invalid column: a valid stand-in)
+};
+
+// lane's load columns of a batch item: tile u, instruction h -> column
+// cwave + 16 u + 8 h + lane / 8
+template <typename TA, int TN>
+__device__ __forceinline__ void sk_lines(const BlkInfo& bi, int cwave, int lane, int j0, int j1,
+                                         SkLines<TA, TN>& ld) {
+  const int clo = max(j0, 0), chi = min(j1, bi.n);
+  gptr<TA> A = (gptr<TA>)bi.A;
+#pragma unroll
+  for (int u = 0; u < TN; ++u)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = cwave + 16 * u + 8 * h + (lane >> 3);
+      const bool ok = col >= clo && col < chi;
+      ld.cb[u][h] = A + (int64_t)(ok ? col : clo) * bi.lda;
+    }
+}
+
+// the same for a one-snapshot item (column = block perm[c0 + local], snapshot j)
+template <typename TA, int TN>
+__device__ __forceinline__ void sk_lines_stream(const BlkInfo* __restrict__ blks,
+                                                const int32_t* __restrict__ perm, const SkItem& it,
+                                                int cw, int lane, int j, SkLines<TA, TN>& ld) {
+#pragma unroll
+  for (int u = 0; u < TN; ++u)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int local = cw + 16 * u + 8 * h + (lane >> 3);
+      const bool valid = local < it.gsize;
+      const BlkInfo& bb = blks[perm[it.c0 + (valid ? local : 0)]];
+      const bool ok = valid && j < bb.n;
+      ld.cb[u][h] = (gptr<TA>)bb.A + (int64_t)(ok ? j : 0) * bb.lda;
+    }
+}
+
+// One line piece: rows row + 4p .. +3 (FP64: row + 2p, +1, row + 16 + 2p, +1)
+// of a full chunk, straight-line loads.  An invalid column reads its clamped
+// stand-in unmasked: an MFMA output column depends on its own input column
+// only, and invalid output columns are never stored.
+template <typename TA, bool VEC>
+__device__ __forceinline__ void load_line(gptr<TA> __restrict__ cb, int64_t row, int p,
+                                          float (&x)[4]) {
+  if constexpr (sizeof(TA) == 4) {
+    if constexpr (VEC) {
+      const f32x4 v = __builtin_nontemporal_load((gptr<f32x4>)(cb + row + 4 * p));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = v[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = __builtin_nontemporal_load(cb + row + 4 * p + e);
+    }
+  } else {
+    if constexpr (VEC) {
+      const f64x2 v0 = __builtin_nontemporal_load((gptr<f64x2>)(cb + row + 2 * p));
+      const f64x2 v1 = __builtin_nontemporal_load((gptr<f64x2>)(cb + row + 16 + 2 * p));
+      x[0] = (float)v0[0];
+      x[1] = (float)v0[1];
+      x[2] = (float)v1[0];
+      x[3] = (float)v1[1];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        x[e] = (float)__builtin_nontemporal_load(cb + row + 16 * (e >> 1) + 2 * p + (e & 1));
+    }
+  }
+}
+
+// ragged chunk: rows at or past rend read as zero
+template <typename TA>
+__device__ __forceinline__ void load_line_tail(gptr<TA> __restrict__ cb, int64_t row, int64_t rend,
+                                               int p, float (&x)[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t r = sizeof(TA) == 4 ? row + 4 * p + e : row + 16 * (e >> 1) + 2 * p + (e & 1);
+    x[e] = r < rend ? (float)cb[r] : 0.0f;
+  }
+}
+
+// staged position of a lane's piece in column col of the wave's tile
+template <typename TA>
+__device__ __forceinline__ void stage_line(float* __restrict__ st, int col, int p,
+                                           const float (&x)[4]) {
+  float* c = st + col * kLineSt;
+  if constexpr (sizeof(TA) == 4) {
+    *reinterpret_cast<f32x4*>(c + 4 * p) = f32x4{x[0], x[1], x[2], x[3]};
+  } else {
+    *reinterpret_cast<f32x2*>(c + 2 * p) = f32x2{x[0], x[1]};
+    *reinterpret_cast<f32x2*>(c + 16 + 2 * p) = f32x2{x[2], x[3]};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sketch, bfloat16 (FP32 accumulation): Omega rounded to nearest-even
+// bfloat16; A split into `terms` bfloat16 terms in registers
+// (hi = bf16(a), lo = bf16(a - hi), lo2 = bf16(a - hi - lo));
+// v_mfma_f32_16x16x32_bf16.  The k-values of lane (g, r16) are rows
+// 8g..8g+7 of the chunk, of its column r16 (from the staged lines) and of
+// Omega row 16t + r16.
+//
+// Omega shared by all blocks (TAB): read from the table omega_table_kernel
+// wrote at set-up, already in MFMA operand order (16 bytes per lane and
+// tile, one coalesced load per tile), software-pipelined with A in registers;
+// the waves run without barriers.  Omega keyed per block (!TAB): regenerated
+// per 32-row chunk into LDS, double-buffered like A, one LDS-only barrier per
+// chunk.  The ragged last chunk is handled after the loop.
+// ---------------------------------------------------------------------------
+// Table entry of Omega row r, column i (sketch-matrix column = A row): chunk
+// i / 32, tile r / 16, lane 16 g + r % 16 with g = (i % 32) / 8, element i % 8;
+// 8 bfloat16 per lane.
+__host__ __device__ constexpr int64_t omega_tab_index(int MT, int r, int64_t i) {
+  return (((i >> 5) * MT + (r >> 4)) * 64 + 16 * ((i & 31) >> 3) + (r & 15)) * 8 + (i & 7);
+}
+
+// The table: MT*16 rows (rows l.. zero) x ncols columns (a multiple of 32),
+// one thread per pair of rows and column, values of omega_pair_rounded.
+template <int KIND>
+__global__ __launch_bounds__(256) void omega_table_kernel(int l, int MT, int64_t ncols,
+                                                          uint64_t seed, __bf16* __restrict__ tab) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)MT * 8 * ncols) return;
+  const int q = (int)(e / ncols);
+  const int64_t i = e - (int64_t)q * ncols;
+  float z0 = 0.0f, z1 = 0.0f;
+  if (2 * q < l) omega_pair_rounded<KIND>(seed, 0u, (uint32_t)i, (uint32_t)q, z0, z1);
+  if (2 * q + 1 >= l) z1 = 0.0f;
+  tab[omega_tab_index(MT, 2 * q, i)] = to_bf16(z0);
+  tab[omega_tab_index(MT, 2 * q + 1, i)] = to_bf16(z1);
+}
+
+template <typename TA, int MT, int TN, int NW, bool VEC, bool ST, bool TAB>
 __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
     int omega_per_block, int j0, int j1, const int32_t* __restrict__ perm, int jst, int terms,
-    float* __restrict__ Y, float* __restrict__ part) {
-  constexpr int kS = kKC + 8;   // LDS row stride in bf16 elements (80 bytes)
-  __shared__ __attribute__((aligned(16))) __bf16 om[2][MT * 16 * kS];
+    const bf16x8* __restrict__ omtab, float* __restrict__ Y, float* __restrict__ part) {
+  constexpr int kS = kKC + 8;   // LDS row stride of the generated Omega (bf16, 80 bytes)
+  __shared__ __attribute__((aligned(16))) __bf16 om[2][TAB ? 8 : MT * 16 * kS];
+  __shared__ __attribute__((aligned(16))) float stage_all[NW * TN * 16 * kLineSt];
   const SkItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, r16 = lane & 15;
+  const int g = lane >> 4, r16 = lane & 15, p8 = lane & 7;
   const int cwave = it.c0 + wave * 16 * TN;
-  SkLane<TA, TN> ln;
+  SkLane<TA, TN> ln;      // output columns (lane column r16 of each tile)
+  SkLines<TA, TN> ld;     // load columns
   if constexpr (ST) {
     sk_setup_stream<TA, TN>(blks, perm, it, wave * 16 * TN, r16, jst, ln);
+    sk_lines_stream<TA, TN>(blks, perm, it, wave * 16 * TN, lane, jst, ld);
   } else {
     if (!sk_setup<TA, TN>(bi, it, cwave, r16, NW * 16 * TN, j0, j1, ln)) return;
+    sk_lines<TA, TN>(bi, cwave, lane, j0, j1, ld);
   }
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
+  float* __restrict__ st = stage_all + wave * TN * 16 * kLineSt;
 
-  for (int e = tid; e < 2 * MT * 16 * kS; e += 64 * NW) (&om[0][0])[e] = (__bf16)0.0f;
+  if constexpr (!TAB)
+    for (int e = tid; e < 2 * MT * 16 * kS; e += 64 * NW) (&om[0][0])[e] = (__bf16)0.0f;
 
   f32x4 acc[MT][TN];
 #pragma unroll
@@ -372,21 +516,52 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  auto load_full = [&](int64_t k0, float (&a)[TN][8]) {
+  auto load_full = [&](int64_t k0, float (&a)[TN][2][4]) {
 #pragma unroll
     for (int u = 0; u < TN; ++u)
-      load_pieces_full<TA, 2, 4, 16, VEC>(ln.cb[u], k0 + 4 * g, ln.ok[u], a[u]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) load_line<TA, VEC>(ld.cb[u][h], k0, p8, a[u][h]);
+  };
+  auto load_tail = [&](int64_t k0, float (&a)[TN][2][4]) {
+#pragma unroll
+    for (int u = 0; u < TN; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        load_line_tail<TA>(ld.cb[u][h], k0, it.r1, p8, a[u][h]);
+  };
+  // lines -> LDS -> operand layout (rows 8g..8g+7 of column r16 of each tile)
+  auto transpose = [&](const float (&a)[TN][2][4], float (&b)[TN][8]) {
+#pragma unroll
+    for (int u = 0; u < TN; ++u)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) stage_line<TA>(st, 16 * u + 8 * h + (lane >> 3), p8, a[u][h]);
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      const float* c = st + (16 * u + r16) * kLineSt + 8 * g;
+      const f32x4 lo = *reinterpret_cast<const f32x4*>(c);
+      const f32x4 hi = *reinterpret_cast<const f32x4*>(c + 4);
+      b[u][0] = lo[0];
+      b[u][1] = lo[1];
+      b[u][2] = lo[2];
+      b[u][3] = lo[3];
+      b[u][4] = hi[0];
+      b[u][5] = hi[1];
+      b[u][6] = hi[2];
+      b[u][7] = hi[3];
+    }
   };
   // A split into `terms` (1..3) bfloat16 terms and the MFMAs of every term.
   // Each pair of values is rounded by one packed conversion; the terms'
   // values are read back from its halves by shifts, and the last term forms
   // no remainder (uniform branches on the term count).
-  auto split_mfma = [&](const bf16x8 (&oa)[MT], float (&a)[TN][8]) {
+  auto split_mfma = [&](const bf16x8 (&oa)[MT], const float (&a)[TN][2][4]) {
+    float b[TN][8];
+    transpose(a, b);
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
       float rem[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rem[e] = a[u][e];
+      for (int e = 0; e < 8; ++e) rem[e] = b[u][e];
 #pragma unroll
       for (int h = 0; h < 3; ++h) {
         if (h >= terms) break;
@@ -407,49 +582,74 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
       }
     }
   };
-  auto mfma_chunk = [&](const __bf16* __restrict__ omb, float (&a)[TN][8]) {
+  auto mfma_chunk = [&](const __bf16* __restrict__ omb, const float (&a)[TN][2][4]) {
     bf16x8 oa[MT];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      const __bf16* orow = omb + (16 * t + r16) * kS + 4 * g;
-      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(orow);
-      const bf16x4 hi = *reinterpret_cast<const bf16x4*>(orow + 16);
-      oa[t] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-    }
+    for (int t = 0; t < MT; ++t)
+      oa[t] = *reinterpret_cast<const bf16x8*>(omb + (16 * t + r16) * kS + 8 * g);
     split_mfma(oa, a);
   };
 
   const int64_t nfull = (it.r1 - it.r0) / kKC;
   const int64_t klast = it.r0 + (nfull - 1) * kKC;
-  float a0[TN][8], a1[TN][8];
-  __syncthreads();
-  if (nfull > 0) {
-    load_full(it.r0, a0);
-    gen_omega_chunk_bf16<kS, 64 * NW>(om[0], l, seed, bkey, it.r0, tid);
-  }
-  lds_barrier();
-  auto step = [&](float (&cur)[TN][8], float (&nxt)[TN][8], int b, int64_t k0) {
-    const int64_t k1 = min(k0 + kKC, klast);
-    load_full(k1, nxt);
-    gen_omega_chunk_bf16<kS, 64 * NW>(om[b ^ 1], l, seed, bkey, k1, tid);
-    mfma_chunk(om[b], cur);
-    lds_barrier();
-  };
-  int64_t c = 0;
-  for (; c + 2 <= nfull; c += 2) {
-    step(a0, a1, 0, it.r0 + c * kKC);
-    step(a1, a0, 1, it.r0 + (c + 1) * kKC);
-  }
-  if (c < nfull) step(a0, a1, 0, it.r0 + c * kKC);
   const int64_t kt = it.r0 + nfull * kKC;
-  if (kt < it.r1) {
-    const int b = (int)(nfull & 1);
-    gen_omega_chunk_bf16<kS, 64 * NW>(om[b], l, seed, bkey, kt, tid);
+  float a0[TN][2][4], a1[TN][2][4];
+  if constexpr (TAB) {
+    const bf16x8* __restrict__ ot = omtab + lane;
+    auto load_om = [&](int64_t k0, bf16x8 (&o)[MT]) {
 #pragma unroll
-    for (int u = 0; u < TN; ++u)
-      load_pieces_tail<TA, 2, 4, 16>(ln.cb[u], kt + 4 * g, it.r1, ln.ok[u], a0[u]);
+      for (int t = 0; t < MT; ++t) o[t] = ot[((k0 >> 5) * MT + t) * 64];
+    };
+    bf16x8 o0[MT], o1[MT];
+    if (nfull > 0) {
+      load_full(it.r0, a0);
+      load_om(it.r0, o0);
+    }
+    auto step = [&](float (&cur)[TN][2][4], float (&nxt)[TN][2][4], bf16x8 (&ocur)[MT],
+                    bf16x8 (&onxt)[MT], int64_t k0) {
+      const int64_t k1 = min(k0 + kKC, klast);
+      load_full(k1, nxt);
+      load_om(k1, onxt);
+      split_mfma(ocur, cur);
+    };
+    int64_t c = 0;
+    for (; c + 2 <= nfull; c += 2) {
+      step(a0, a1, o0, o1, it.r0 + c * kKC);
+      step(a1, a0, o1, o0, it.r0 + (c + 1) * kKC);
+    }
+    if (c < nfull) step(a0, a1, o0, o1, it.r0 + c * kKC);
+    if (kt < it.r1) {
+      load_om(kt, o0);
+      load_tail(kt, a0);
+      split_mfma(o0, a0);
+    }
+  } else {
+    __syncthreads();
+    if (nfull > 0) {
+      load_full(it.r0, a0);
+      gen_omega_chunk_bf16<kS, 64 * NW>(om[0], l, seed, bkey, it.r0, tid);
+    }
     lds_barrier();
-    mfma_chunk(om[b], a0);
+    auto step = [&](float (&cur)[TN][2][4], float (&nxt)[TN][2][4], int b, int64_t k0) {
+      const int64_t k1 = min(k0 + kKC, klast);
+      load_full(k1, nxt);
+      gen_omega_chunk_bf16<kS, 64 * NW>(om[b ^ 1], l, seed, bkey, k1, tid);
+      mfma_chunk(om[b], cur);
+      lds_barrier();
+    };
+    int64_t c = 0;
+    for (; c + 2 <= nfull; c += 2) {
+      step(a0, a1, 0, it.r0 + c * kKC);
+      step(a1, a0, 1, it.r0 + (c + 1) * kKC);
+    }
+    if (c < nfull) step(a0, a1, 0, it.r0 + c * kKC);
+    if (kt < it.r1) {
+      const int b = (int)(nfull & 1);
+      gen_omega_chunk_bf16<kS, 64 * NW>(om[b], l, seed, bkey, kt, tid);
+      load_tail(kt, a0);
+      lds_barrier();
+      mfma_chunk(om[b], a0);
+    }
   }
   const bool direct = ST ? it.gnsplit == 1 : bi.nsplit == 1;
   float* dst = direct ? Y : part;

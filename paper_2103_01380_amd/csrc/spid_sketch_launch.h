@@ -10,8 +10,9 @@ namespace spid_host {
 
 constexpr int kPrF64 = 0, kPrBF16 = 1, kPrFP8 = 2;
 
-// ST: one-snapshot update of snapshot jst over the block groups
-template <int PR, typename TA, int MT, int TN, int NW, bool VEC, bool ST>
+// ST: one-snapshot update of snapshot jst over the block groups; TAB: the
+// bfloat16 kernel reads Omega from the set-up table (shared Omega only)
+template <int PR, typename TA, int MT, int TN, int NW, bool VEC, bool ST, bool TAB>
 void launch_sketch_k(spid_ctx* c, int j0, int j1, int jst, hipStream_t s) {
   const Plan& p = c->plan;
   const size_t nitems = ST ? p.sitems.size() : p.items.size();
@@ -34,53 +35,54 @@ void launch_sketch_k(spid_ctx* c, int j0, int j1, int jst, hipStream_t s) {
                          c->at<float>(p.off_Y), c->at<float>(p.off_part));
   } else {
     if constexpr (TN <= 2 || MT < 6)
-      hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, NW, VEC, ST>), grid, block, 0, s,
+      hipLaunchKernelGGL((sketch_bf16_kernel<TA, MT, TN, NW, VEC, ST, TAB>), grid, block, 0, s,
                          c->at<BlkInfo>(p.off_blk), items, c->desc.l, c->desc.seed,
                          c->desc.omega_per_block, j0, j1, perm, jst, c->desc.lp_terms,
-                         c->at<float>(p.off_Y), c->at<float>(p.off_part));
+                         TAB ? c->at<bf16x8>(p.off_omtab) : nullptr, c->at<float>(p.off_Y),
+                         c->at<float>(p.off_part));
   }
 }
 
 // instantiated (TN, NW) pairs: 8 waves x 1-4 tiles or 4 waves x 1 tile
-template <int PR, typename TA, int MT, int TN>
+template <int PR, bool TAB, typename TA, int MT, int TN>
 void launch_sketch_t(spid_ctx* c, int j0, int j1, hipStream_t s) {
   const bool vec = c->all_vec;
   if (c->plan.sh.NW == 8) {
-    if (vec) launch_sketch_k<PR, TA, MT, TN, 8, true, false>(c, j0, j1, 0, s);
-    else launch_sketch_k<PR, TA, MT, TN, 8, false, false>(c, j0, j1, 0, s);
+    if (vec) launch_sketch_k<PR, TA, MT, TN, 8, true, false, TAB>(c, j0, j1, 0, s);
+    else launch_sketch_k<PR, TA, MT, TN, 8, false, false, TAB>(c, j0, j1, 0, s);
   } else {
     if constexpr (TN == 1) {
-      if (vec) launch_sketch_k<PR, TA, MT, 1, 4, true, false>(c, j0, j1, 0, s);
-      else launch_sketch_k<PR, TA, MT, 1, 4, false, false>(c, j0, j1, 0, s);
+      if (vec) launch_sketch_k<PR, TA, MT, 1, 4, true, false, TAB>(c, j0, j1, 0, s);
+      else launch_sketch_k<PR, TA, MT, 1, 4, false, false, TAB>(c, j0, j1, 0, s);
     }
   }
 }
 
-template <int PR, typename TA, int MT>
+template <int PR, bool TAB, typename TA, int MT>
 void launch_sketch_mt(spid_ctx* c, int j0, int j1, hipStream_t s) {
   switch (c->plan.sh.TN) {
-    case 1: launch_sketch_t<PR, TA, MT, 1>(c, j0, j1, s); break;
-    case 2: launch_sketch_t<PR, TA, MT, 2>(c, j0, j1, s); break;
-    default: launch_sketch_t<PR, TA, MT, 4>(c, j0, j1, s); break;
+    case 1: launch_sketch_t<PR, TAB, TA, MT, 1>(c, j0, j1, s); break;
+    case 2: launch_sketch_t<PR, TAB, TA, MT, 2>(c, j0, j1, s); break;
+    default: launch_sketch_t<PR, TAB, TA, MT, 4>(c, j0, j1, s); break;
   }
 }
 
-template <int PR, typename TA>
+template <int PR, bool TAB, typename TA>
 void launch_sketch_a(spid_ctx* c, int j0, int j1, hipStream_t s) {
   switch (c->plan.sh.MT) {
-    case 1: launch_sketch_mt<PR, TA, 1>(c, j0, j1, s); break;
-    case 2: launch_sketch_mt<PR, TA, 2>(c, j0, j1, s); break;
-    case 3: launch_sketch_mt<PR, TA, 3>(c, j0, j1, s); break;
-    case 4: launch_sketch_mt<PR, TA, 4>(c, j0, j1, s); break;
-    case 6: launch_sketch_mt<PR, TA, 6>(c, j0, j1, s); break;
-    default: launch_sketch_mt<PR, TA, 8>(c, j0, j1, s); break;
+    case 1: launch_sketch_mt<PR, TAB, TA, 1>(c, j0, j1, s); break;
+    case 2: launch_sketch_mt<PR, TAB, TA, 2>(c, j0, j1, s); break;
+    case 3: launch_sketch_mt<PR, TAB, TA, 3>(c, j0, j1, s); break;
+    case 4: launch_sketch_mt<PR, TAB, TA, 4>(c, j0, j1, s); break;
+    case 6: launch_sketch_mt<PR, TAB, TA, 6>(c, j0, j1, s); break;
+    default: launch_sketch_mt<PR, TAB, TA, 8>(c, j0, j1, s); break;
   }
 }
 
-template <int PR>
+template <int PR, bool TAB = false>
 void sketch_batch(spid_ctx* c, int j0, int j1, hipStream_t s) {
-  if (c->desc.a_dtype == SPID_A_F64) launch_sketch_a<PR, double>(c, j0, j1, s);
-  else launch_sketch_a<PR, float>(c, j0, j1, s);
+  if (c->desc.a_dtype == SPID_A_F64) launch_sketch_a<PR, TAB, double>(c, j0, j1, s);
+  else launch_sketch_a<PR, TAB, float>(c, j0, j1, s);
 }
 
 // one-snapshot form: one 16-column tile per wave (the blocks of a group), or
@@ -90,8 +92,9 @@ bool launch_sketch_stream_mt(spid_ctx* c, int j, hipStream_t s);
 
 template <int PR, typename TA, int MT>
 bool launch_sketch_stream_plain(spid_ctx* c, int j, hipStream_t s) {
-  if (c->all_vec) launch_sketch_k<PR, TA, MT, 1, kStreamNW, true, true>(c, 0, 0, j, s);
-  else launch_sketch_k<PR, TA, MT, 1, kStreamNW, false, true>(c, 0, 0, j, s);
+  constexpr bool kTab = PR == kPrBF16;   // one-snapshot updates need a shared Omega
+  if (c->all_vec) launch_sketch_k<PR, TA, MT, 1, kStreamNW, true, true, kTab>(c, 0, 0, j, s);
+  else launch_sketch_k<PR, TA, MT, 1, kStreamNW, false, true, kTab>(c, 0, 0, j, s);
   return true;
 }
 
