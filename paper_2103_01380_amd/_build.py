@@ -42,10 +42,15 @@ def _run(cmd, verbose):
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + r.stderr[-8000:])
 
 
+# per-source additions: the error passes keep their MFMA accumulators in VGPRs
+# (their residual arithmetic reads them; AGPRs would need a copy per value)
+EXTRA = {"spid_recon.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(OBJ_DIR, exist_ok=True)
     objs = [os.path.join(OBJ_DIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
-    cmds = [[hipcc(), *FLAGS, "-c", os.path.join(CSRC, s), "-o", o]
+    cmds = [[hipcc(), *FLAGS, *EXTRA.get(s, []), "-c", os.path.join(CSRC, s), "-o", o]
             for s, o in zip(SOURCES, objs)]
     jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
     with ThreadPoolExecutor(jobs) as ex:

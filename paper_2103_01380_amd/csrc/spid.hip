@@ -185,8 +185,8 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     sh.MTR = sh.rc_bf16 ? 2 : (sh.KS <= 8 ? 4 : 2);
     sh.RC_SUB = 4 * 16 * sh.MTR;
     if (sh.rc_bf16) {
-      // kRcBfSubs sub-tiles per item, split coefficients staged 64 columns at a time
-      sh.PCAP = kRcBfCols;
+      // one sub-tile per item, split coefficients staged rcbf_cols(KS32) columns at a time
+      sh.PCAP = rcbf_cols(sh.KS32);
       sh.RPI = kRcBfSubs;
     } else {
       // coefficient staging: as many columns as the LDS budget holds (multiple of 16)

@@ -29,6 +29,7 @@ constexpr int kMaxL = 128;
 constexpr int kMaxLCoarse = 1 << 22;               // coarse-grid sketch rows
 constexpr int kMaxK = 96;
 constexpr int kMaxN = 1024;
+static_assert(kRcMaxCols >= kMaxN, "the mixed error pass stages a whole column list");
 constexpr int kStreamNW = 8;                       // waves of a one-snapshot sketch workgroup
 constexpr int kStreamGroup = 16 * kStreamNW;       // blocks per group (one 16-column tile per wave)
 constexpr int kStreamMaxW = 4;                     // updates of up to this many snapshots use it

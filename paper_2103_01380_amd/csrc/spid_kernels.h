@@ -342,11 +342,22 @@ __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
 // tile: instruction h covers columns 8h..8h+7 of the tile, lane
 // (c8 = lane / 8, p = lane % 8) reading rows 4p..4p+3 of column 8h + c8
 // (FP64 A: rows 2p, 2p+1 and 16+2p, 17+2p, two 16-byte loads), and passes
-// them through a wave-private LDS tile (column stride 36 floats: both the
-// writes and the operand reads are free of bank conflicts) into the MFMA
-// operand layout.  No barrier: a wave's LDS operations run in order.
+// them through a wave-private LDS tile into the MFMA operand layout.  No
+// barrier: a wave's LDS operations run in order.
+//
+// The staged column is one 128-byte line whose eight 16-byte pieces are
+// permuted: piece q of column c sits at position q ^ line_swz(c).  Both the
+// writes (eight lanes per column) and the operand reads (sixteen columns,
+// one piece each) then touch distinct banks in every group of 8 lanes (32
+// banks) and of 16 lanes (64 banks).
 // ---------------------------------------------------------------------------
-constexpr int kLineSt = kKC + 4;   // floats per staged column
+constexpr int kLineSt = kKC;   // floats per staged column
+
+__device__ __forceinline__ int line_swz(int col) { return ((col >> 1) ^ (col << 2)) & 7; }
+
+__device__ __forceinline__ float* line_piece(float* st, int col, int q) {
+  return st + col * kLineSt + 4 * (q ^ line_swz(col));
+}
 
 template <typename TA, int TN>
 struct SkLines {
@@ -419,27 +430,29 @@ __device__ __forceinline__ void load_line(gptr<TA> __restrict__ cb, int64_t row,
   }
 }
 
-// ragged chunk: rows at or past rend read as zero
+// ragged chunk (cb = column start, row and rend absolute): rows at or past
+// rend read row 0 and are zeroed (no branches, so the loads overlap)
 template <typename TA>
 __device__ __forceinline__ void load_line_tail(gptr<TA> __restrict__ cb, int64_t row, int64_t rend,
                                                int p, float (&x)[4]) {
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int64_t r = sizeof(TA) == 4 ? row + 4 * p + e : row + 16 * (e >> 1) + 2 * p + (e & 1);
-    x[e] = r < rend ? (float)cb[r] : 0.0f;
+    const float v = (float)cb[r < rend ? r : 0];
+    x[e] = r < rend ? v : 0.0f;
   }
 }
 
-// staged position of a lane's piece in column col of the wave's tile
+// a lane's piece into column col of the wave's tile
 template <typename TA>
 __device__ __forceinline__ void stage_line(float* __restrict__ st, int col, int p,
                                            const float (&x)[4]) {
-  float* c = st + col * kLineSt;
   if constexpr (sizeof(TA) == 4) {
-    *reinterpret_cast<f32x4*>(c + 4 * p) = f32x4{x[0], x[1], x[2], x[3]};
+    *reinterpret_cast<f32x4*>(line_piece(st, col, p)) = f32x4{x[0], x[1], x[2], x[3]};
   } else {
-    *reinterpret_cast<f32x2*>(c + 2 * p) = f32x2{x[0], x[1]};
-    *reinterpret_cast<f32x2*>(c + 16 + 2 * p) = f32x2{x[2], x[3]};
+    // rows 2p, 2p+1 (piece p / 2) and 16 + 2p, 17 + 2p (piece 4 + p / 2)
+    *reinterpret_cast<f32x2*>(line_piece(st, col, p >> 1) + 2 * (p & 1)) = f32x2{x[0], x[1]};
+    *reinterpret_cast<f32x2*>(line_piece(st, col, 4 + (p >> 1)) + 2 * (p & 1)) = f32x2{x[2], x[3]};
   }
 }
 
@@ -537,9 +550,8 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
       for (int h = 0; h < 2; ++h) stage_line<TA>(st, 16 * u + 8 * h + (lane >> 3), p8, a[u][h]);
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
-      const float* c = st + (16 * u + r16) * kLineSt + 8 * g;
-      const f32x4 lo = *reinterpret_cast<const f32x4*>(c);
-      const f32x4 hi = *reinterpret_cast<const f32x4*>(c + 4);
+      const f32x4 lo = *reinterpret_cast<const f32x4*>(line_piece(st, 16 * u + r16, 2 * g));
+      const f32x4 hi = *reinterpret_cast<const f32x4*>(line_piece(st, 16 * u + r16, 2 * g + 1));
       b[u][0] = lo[0];
       b[u][1] = lo[1];
       b[u][2] = lo[2];
@@ -1486,9 +1498,9 @@ static __global__ void select_export_kernel(int nblocks, int k_max, const int32_
 // ascending within the block), and the solved block is taken off every row
 // block above by MFMA products with R11: the arithmetic of the row-by-row
 // back-substitution, the sum over t in blocks.  When `pt` is given (mixed
-// error pass on FP32 data) the wave also writes its columns' three bfloat16
-// terms (hi, mid, lo: 24 significant bits) and the compact column list, so
-// the error pass stages them by plain copies.  Layouts: cols[col_off + q],
+// error pass on FP32 data) the wave also writes the three bfloat16 terms
+// (hi, mid, lo: 24 significant bits) of its columns' negated coefficients and
+// the compact column list, so the error pass stages them by plain copies.  Layouts: cols[col_off + q],
 // pt[(col_off + q) * 3 * KP + term * KP + t] with col_off = y_off / l (the
 // block's first column in the batch), KP = 32 KS32.
 // ---------------------------------------------------------------------------
@@ -1633,7 +1645,7 @@ __global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
         for (int v = 0; v < 4; ++v) {
           const int t = 16 * r + g4 + 4 * v;
           if (t < KP) {
-            const double pv = acc[r][v];
+            const double pv = -acc[r][v];   // the error pass adds the products to A
             const __bf16 hi = to_bf16((float)pv);
             const double r1 = pv - (double)(float)hi;
             const __bf16 md = to_bf16((float)r1);
@@ -1842,22 +1854,30 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
 
 // ---------------------------------------------------------------------------
 // Reconstruction error for single-precision data on the bfloat16 matrix
-// cores.  A(rows, S) and P are split into three bfloat16 terms each
-// (hi + mid + lo carries all 24 bits of a float), and
-// Ahat = A(rows,S) P is accumulated in FP32 from the six term products whose
-// weight is at least 2^-16 (hi*hi, hi*mid, mid*hi, hi*lo, mid*mid, lo*hi)
-// with v_mfma_f32_16x16x32_bf16.  The residual is formed in FP32 and its
-// square accumulated in FP64.  Lane (g, c) of the bf16 MFMA output holds rows
-// 4g..4g+3 of column c, so each lane loads 16 contiguous bytes per tile.
-// KS32 = k-steps of 32 selected columns.  A work item is SUBS sub-tiles of
-// 4 * 16 * MTR rows; their skeleton terms stay in registers while the P
-// terms (split once by the coefficients kernel, with the compact column
-// list) are staged kRcBfCols columns at a time by plain 16-byte copies into
-// 12-36 KiB of static LDS: the kernel is bound by VALU latency, and the small
-// footprint keeps five or more waves per SIMD resident.
+// cores.  A(rows, S) and the negated coefficients -P are split into three
+// bfloat16 terms each (hi + mid + lo carries all 24 bits of a float); the
+// accumulator of v_mfma_f32_16x16x32_bf16 starts at A(rows, j) and takes the
+// six term products of weight at least 2^-16 (hi*hi, hi*mid, mid*hi, hi*lo,
+// mid*mid, lo*hi), largest first, so it ends at the residual
+// A(rows, j) - A(rows, S) P(:, j) with every rounding at the size of what is
+// left.  Squared residuals are summed in FP32 over one step (16 per lane,
+// relative error at most 16 * 2^-24) and the step sums in FP64; |A|^2 in
+// FP64 throughout.  KS32 = k-steps of 32 selected columns.
+//
+// A work item is 128 rows (4 waves x 32) of one block; a wave's skeleton
+// terms (its 32 rows of A(:, S)) stay in registers.  The non-skeleton columns
+// are streamed in steps of 32: the step's A values arrive as whole 128-byte
+// lines (two load instructions per 16 columns) loaded one step ahead, and are
+// passed through a wave-private LDS tile into the MFMA output layout (lane
+// (g, c16) holds rows 4g..4g+3 of column c16 of each 16-row tile).  The P
+// terms (split once by the coefficients kernel, with the compact column list)
+// are staged rcbf_cols(KS32) columns at a time (about 26 KiB of LDS) by plain
+// 16-byte copies behind LDS-only barriers; the columns' element offsets are
+// staged whole at the start, so the prefetch runs across those barriers.
 // ---------------------------------------------------------------------------
-constexpr int kRcBfCols = 64;
-constexpr int kRcBfSubs = 2;
+constexpr int kRcBfSubs = 1;
+constexpr int kRcMaxCols = 1024;   // widest block (the descriptor limit on n)
+__host__ __device__ constexpr int rcbf_cols(int KS32) { return KS32 == 1 ? 128 : (KS32 == 2 ? 64 : 32); }
 
 template <int KS32, int MTR, bool VEC>
 __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
@@ -1866,14 +1886,16 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
     const __bf16* __restrict__ pt_g, const int32_t* __restrict__ cols_g,
     const int32_t* __restrict__ ncols_g, float* __restrict__ skel, double* __restrict__ part) {
   constexpr int KP = 32 * KS32;
-  constexpr int kSub = 4 * 16 * MTR;
+  constexpr int kCols = rcbf_cols(KS32);
   // a column's three terms, 3 KP bfloat16 (a multiple of 32 dwords), then 8
   // bfloat16 of padding: the 16 columns one MFMA reads start 4 banks apart
   // instead of on one bank
   constexpr int kPtStride = 3 * KP + 8;
-  __shared__ __attribute__((aligned(16))) __bf16 pt[kRcBfCols * kPtStride];
-  __shared__ int cols[kRcBfCols];
+  __shared__ __attribute__((aligned(16))) __bf16 pt[kCols * kPtStride];
+  __shared__ __attribute__((aligned(16))) float stage_all[kRcThreads / 64 * 16 * kLineSt];
+  __shared__ int64_t coff[kRcMaxCols];   // element offset of each non-skeleton column
   __shared__ double red[8];
+  static_assert(MTR == 2, "a wave's rows are one 128-byte line of each column");
   const int item = xcd_item(xs);
   if (item < 0) return;
   const RcItem it = items[item];
@@ -1882,48 +1904,58 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
   const int32_t* S = S_ws + (int64_t)it.blk * k_max;
   gptr<float> __restrict__ A = (gptr<float>)bi.A;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, c16 = lane & 15;
+  const int g = lane >> 4, c16 = lane & 15, p8 = lane & 7;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);   // wave-uniform (scalar) copy
+  float* __restrict__ st = stage_all + wave * 16 * kLineSt;
   const int64_t col_off = bi.y_off / l;
   const int ncols = ncols_g[it.blk];
   const int ksn = (k + 31) >> 5;   // k-steps holding selected columns (the rest are zero)
   const __bf16* __restrict__ ptb = pt_g + col_off * 3 * KP;
   const int32_t* __restrict__ colb = cols_g + col_off;
+  const int64_t rbase = it.i0 + wave_u * 16 * MTR;   // the wave's 32 rows
 
   // A operand: tile row c16, selected columns 32 ks + 8 g + v, three terms (k-steps past
   // ksn are never read)
-  bf16x8 at[kRcBfSubs][MTR][KS32][3];
+  bf16x8 at[MTR][KS32][3];
   double a2 = 0.0, e2 = 0.0;
 #pragma unroll
-  for (int sb = 0; sb < kRcBfSubs; ++sb)
+  for (int mt = 0; mt < MTR; ++mt) {
+    const int64_t i = rbase + 16 * mt + c16;
+    const bool iok = i < bi.m;
 #pragma unroll
-    for (int mt = 0; mt < MTR; ++mt) {
-      const int64_t i = it.i0 + (int64_t)sb * kSub + wave * 16 * MTR + 16 * mt + c16;
+    for (int ks = 0; ks < KS32; ++ks) {
+      if (ks >= ksn) break;
+      // gather without branches (out-of-range entries read row 0 / the
+      // first selected column, then are zeroed), so the loads overlap
+      float xv[8];
 #pragma unroll
-      for (int ks = 0; ks < KS32; ++ks) {
-        if (ks >= ksn) break;
+      for (int v = 0; v < 8; ++v) {
+        const int t = 32 * ks + 8 * g + v;
+        xv[v] = A[(int64_t)S[t < k ? t : 0] * bi.lda + (iok ? i : 0)];
+      }
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          const int t = 32 * ks + 8 * g + v;
-          float x = 0.0f;
-          if (t < k && i < bi.m) {
-            x = A[(int64_t)S[t] * bi.lda + i];
-            if (skel) skel[bi.sk_off + (int64_t)t * bi.m + i] = x;
-          }
-          a2 += (double)x * (double)x;
-          const __bf16 h = to_bf16(x);
-          const float r1 = x - (float)h;
-          const __bf16 md = to_bf16(r1);
-          const __bf16 lo = to_bf16(r1 - (float)md);
-          at[sb][mt][ks][0][v] = h;
-          at[sb][mt][ks][1][v] = md;
-          at[sb][mt][ks][2][v] = lo;
-        }
+      for (int v = 0; v < 8; ++v) {
+        const int t = 32 * ks + 8 * g + v;
+        const bool ok = t < k && iok;
+        const float x = ok ? xv[v] : 0.0f;
+        if (skel && ok) skel[bi.sk_off + (int64_t)t * bi.m + i] = x;
+        a2 += (double)x * (double)x;
+        const __bf16 h = to_bf16(x);
+        const float r1 = x - (float)h;
+        const __bf16 md = to_bf16(r1);
+        const __bf16 lo = to_bf16(r1 - (float)md);
+        at[mt][ks][0][v] = h;
+        at[mt][ks][1][v] = md;
+        at[mt][ks][2][v] = lo;
       }
     }
+  }
 
-  for (int c0 = 0; c0 < ncols; c0 += kRcBfCols) {
-    const int cc = min(kRcBfCols, ncols - c0);
-    constexpr int kVec = kRcBfCols * 3 * KP / 8;   // 16-byte pieces of the chunk
+  // P terms of columns c0 .. c0 + kCols - 1 into LDS (zero past ncols)
+  auto stage_p = [&](int c0) {
+    const int cc = min(kCols, ncols - c0);
+    lds_barrier();   // every wave is done with the previous chunk
+    constexpr int kVec = kCols * 3 * KP / 8;   // 16-byte pieces of the chunk
     for (int e = tid; e < kVec; e += kRcThreads) {
       const int q = e / (3 * KP / 8), r8 = e - q * (3 * KP / 8);
       if (8 * (e % (KP / 8)) >= 32 * ksn) continue;   // terms of k-steps that are skipped
@@ -1931,61 +1963,94 @@ __global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
       if (q < cc) v = *reinterpret_cast<const bf16x8*>(ptb + (int64_t)c0 * 3 * KP + (int64_t)e * 8);
       *reinterpret_cast<bf16x8*>(pt + q * kPtStride + 8 * r8) = v;
     }
-    if (tid < kRcBfCols) cols[tid] = (tid < cc) ? colb[c0 + tid] : 0;
-    __syncthreads();
+    lds_barrier();
+  };
+
+  const int nst = (ncols + 31) >> 5;   // 32-column steps
+  // the block's non-skeleton column offsets, once per item (the loads index them)
+  for (int c = tid; c < ncols; c += kRcThreads) coff[c] = (int64_t)colb[c] * bi.lda;
+  lds_barrier();
+  auto body = [&](auto full_c) {
+    constexpr bool kFull = decltype(full_c)::value;
+    // lines of step s: group gq, instruction h -> column 32 s + 16 gq + 8 h + lane / 8
+    // (clamped to the last column; columns past ncols are masked below)
+    auto load = [&](int s, float (&x)[2][2][4]) {
 #pragma unroll
-    for (int sb = 0; sb < kRcBfSubs; ++sb) {
-      const int64_t rbase = it.i0 + (int64_t)sb * kSub + wave * 16 * MTR;
-      for (int q0 = 0; q0 < cc; q0 += 16) {
-        const int q = q0 + c16;
-        const bool cok = q < cc;
-        const int64_t j = cols[cok ? q : 0];
-        float av[MTR][4];
+      for (int gq = 0; gq < 2; ++gq)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int c = min(32 * s + 16 * gq + 8 * h + (lane >> 3), ncols - 1);
+          gptr<float> src = A + coff[c];
+          if constexpr (kFull) load_line<float, VEC>(src, rbase, p8, x[gq][h]);
+          else load_line_tail<float>(src, rbase, bi.m, p8, x[gq][h]);
+        }
+    };
+    auto step = [&](const float (&x)[2][2][4], float (&xn)[2][2][4], int s) {
+      if ((32 * s) % kCols == 0) stage_p(32 * s);
+      load(min(s + 1, nst - 1), xn);
+      float es = 0.0f;   // the step's squared residuals
+      // one 16-column group; MASK: some of its columns lie past ncols (the
+      // block's last group only)
+      auto group = [&](auto mask_c, const float (&xg)[2][4], int q0) {
+        constexpr bool kMask = decltype(mask_c)::value;
+        const bool cok = q0 + c16 < ncols;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) stage_line<float>(st, 8 * h + (lane >> 3), p8, xg[h]);
+        f32x4 acc[MTR];   // A(rows, j), then the residual
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt) {
-          const int64_t i0 = rbase + 16 * mt + 4 * g;
-          gptr<float> src = A + j * bi.lda + i0;
-          if (VEC && cok && i0 + 4 <= bi.m) {
-            const f32x4 x = __builtin_nontemporal_load((gptr<f32x4>)src);
+          const f32x4 v = *reinterpret_cast<const f32x4*>(line_piece(st, c16, 4 * mt + g));
 #pragma unroll
-            for (int v = 0; v < 4; ++v) av[mt][v] = x[v];
-          } else {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) av[mt][v] = (cok && i0 + v < bi.m) ? src[v] : 0.0f;
+          for (int e = 0; e < 4; ++e) {
+            const float a = (!kMask || cok) ? v[e] : 0.0f;
+            acc[mt][e] = a;
+            a2 += (double)a * (double)a;
           }
         }
-        f32x4 acc[MTR];
-#pragma unroll
-        for (int mt = 0; mt < MTR; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int qp = q0 % kCols + c16;           // column within the staged chunk
 #pragma unroll
         for (int ks = 0; ks < KS32; ++ks) {
           if (ks >= ksn) break;     // uniform: zero terms add nothing
-          const __bf16* pq = pt + (q0 + c16) * kPtStride + 32 * ks + 8 * g;
+          const __bf16* pq = pt + qp * kPtStride + 32 * ks + 8 * g;
           const bf16x8 p0 = *reinterpret_cast<const bf16x8*>(pq);
           const bf16x8 p1 = *reinterpret_cast<const bf16x8*>(pq + KP);
           const bf16x8 p2 = *reinterpret_cast<const bf16x8*>(pq + 2 * KP);
 #pragma unroll
           for (int mt = 0; mt < MTR; ++mt) {
-            // smallest terms first
-            acc[mt] = mfma_bf16(at[sb][mt][ks][2], p0, acc[mt]);
-            acc[mt] = mfma_bf16(at[sb][mt][ks][1], p1, acc[mt]);
-            acc[mt] = mfma_bf16(at[sb][mt][ks][0], p2, acc[mt]);
-            acc[mt] = mfma_bf16(at[sb][mt][ks][1], p0, acc[mt]);
-            acc[mt] = mfma_bf16(at[sb][mt][ks][0], p1, acc[mt]);
-            acc[mt] = mfma_bf16(at[sb][mt][ks][0], p0, acc[mt]);
+            // largest terms first (p* are the terms of -P)
+            acc[mt] = mfma_bf16(at[mt][ks][0], p0, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][0], p1, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][1], p0, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][0], p2, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][1], p1, acc[mt]);
+            acc[mt] = mfma_bf16(at[mt][ks][2], p0, acc[mt]);
           }
         }
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const float r = av[mt][v] - acc[mt][v];
-            e2 += (double)r * (double)r;
-            a2 += (double)av[mt][v] * (double)av[mt][v];
-          }
+          for (int v = 0; v < 4; ++v) es = __builtin_fmaf(acc[mt][v], acc[mt][v], es);
+      };
+#pragma unroll
+      for (int gq = 0; gq < 2; ++gq) {
+        const int q0 = 32 * s + 16 * gq;           // first column of the group
+        if (q0 + 16 <= ncols) group(std::false_type{}, x[gq], q0);
+        else group(std::true_type{}, x[gq], q0);
       }
+      e2 += (double)es;
+    };
+    float xa[2][2][4], xb[2][2][4];
+    load(0, xa);
+    int s = 0;
+    for (; s + 1 < nst; s += 2) {
+      step(xa, xb, s);
+      step(xb, xa, s + 1);
     }
-    __syncthreads();
+    if (s < nst) step(xa, xb, s);
+  };
+  if (ncols > 0) {
+    if (rbase + 16 * MTR <= bi.m) body(std::true_type{});
+    else body(std::false_type{});
   }
 
   e2 = wave_sum(e2);

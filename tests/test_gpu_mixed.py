@@ -33,7 +33,9 @@ def _gates(blocks, g, o, gamma=1e-3, y_rtol=2e-6):
     |err2 - e_direct| <= 2 |<r, delta>| + |delta|^2; the cross term is bounded by
     2 sqrt(e_direct) |delta| (|delta| about 1e-7 ||A||) and in practice far smaller,
     since the residual and the rounding are uncorrelated (measured at most 4.2e-9
-    sqrt(e_direct) ||A|| on these blocks), so the test holds it to 5e-8."""
+    sqrt(e_direct) ||A|| on these blocks), so the test holds it to 5e-8; the squares
+    are summed in FP32 over 16 terms before the FP64 sum (at most 16 * 2^-24 < 1e-6
+    of e_direct)."""
     num = den = rdiff = 0.0
     worst = 0.0
     for b, A in enumerate(blocks):
@@ -53,7 +55,7 @@ def _gates(blocks, g, o, gamma=1e-3, y_rtol=2e-6):
         a_norm = math.sqrt((Ad ** 2).sum())
         gap = abs(g.err2[b] - e_direct)
         worst = max(worst, gap / (math.sqrt(e_direct) * a_norm + 1e-300))
-        assert gap <= 5e-8 * math.sqrt(e_direct) * a_norm + 1e-13 * a_norm ** 2, \
+        assert gap <= 5e-8 * math.sqrt(e_direct) * a_norm + 1e-6 * e_direct + 1e-13 * a_norm ** 2, \
             (b, g.err2[b], e_direct, gap / (math.sqrt(e_direct) * a_norm + 1e-300))
     e_gpu = math.sqrt(num / den)
     r2 = math.sqrt(rdiff / den)
