@@ -1877,10 +1877,13 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
 // ---------------------------------------------------------------------------
 constexpr int kRcBfSubs = 1;
 constexpr int kRcMaxCols = 1024;   // widest block (the descriptor limit on n)
-__host__ __device__ constexpr int rcbf_cols(int KS32) { return KS32 == 1 ? 128 : (KS32 == 2 ? 64 : 32); }
+__host__ __device__ constexpr int rcbf_cols(int KS32) { return KS32 == 1 ? 96 : (KS32 == 2 ? 64 : 32); }
+// resident waves per SIMD the register allocation targets (LDS allows four)
+__host__ __device__ constexpr int rcbf_waves(int KS32) { return KS32 == 1 ? 4 : 2; }
 
 template <int KS32, int MTR, bool VEC>
-__global__ __launch_bounds__(kRcThreads) void recon_bf16x3_kernel(
+__global__ __launch_bounds__(kRcThreads) __attribute__((amdgpu_waves_per_eu(rcbf_waves(KS32))))
+void recon_bf16x3_kernel(
     const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, XcdSplit xs, int l, int k_max,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
     const __bf16* __restrict__ pt_g, const int32_t* __restrict__ cols_g,
