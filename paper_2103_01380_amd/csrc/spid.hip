@@ -661,11 +661,6 @@ extern "C" spid_status spid_create_tuned(const spid_desc* desc, const spid_tunin
   if (e == hipSuccess && p.ts_nwin > 0)
     e = hipMemcpy(c->ws + p.off_tsblk2, p.ts_blk2.data(), sizeof(BlkInfo) * p.ts_blk2.size(),
                   hipMemcpyHostToDevice);
-  // shared bfloat16 sketch matrix, generated once (the sketch kernels read it)
-  if (e == hipSuccess && p.omtab_cols > 0) {
-    if (!launch_omega_table(c, nullptr)) e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-  }
 
   if (e != hipSuccess) {
     delete c;
@@ -778,6 +773,11 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
     c->selected = false;
     c->coeffs_done = false;
     return SPID_OK;
+  }
+  // shared Omega: regenerated from the generator for this update into the
+  // small table the sketch kernels read (l x max m_b, L2-resident)
+  if (p.omtab_cols > 0) {
+    if (!launch_omega_table(c, s)) return fail(SPID_EHIP, "Omega table launch failed");
   }
   if (p.st_ok && j1 - j0 <= kStreamMaxW) {
     // a few snapshots: one launch per snapshot with the blocks as MFMA columns

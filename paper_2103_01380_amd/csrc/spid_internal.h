@@ -157,8 +157,9 @@ struct Plan {
   int64_t sum_n = 0, sum_m = 0, part_elems = 0;
   int max_n = 0, max_split_n = 0;
   // bfloat16 sketch with Omega shared by all blocks: the sketch matrix as a
-  // table in MFMA operand order (MT*16 rows x omtab_cols columns), written at
-  // create (omtab_cols = max m rounded up to the 32-row chunk; 0: no table)
+  // table in MFMA operand order (MT*16 rows x omtab_cols columns), regenerated
+  // at the start of every sketch update (omtab_cols = max m rounded up to the
+  // 32-row chunk; 0: no table)
   int64_t omtab_cols = 0;
   size_t off_omtab = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,

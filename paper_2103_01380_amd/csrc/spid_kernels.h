@@ -464,10 +464,11 @@ __device__ __forceinline__ void stage_line(float* __restrict__ st, int col, int 
 // 8g..8g+7 of the chunk, of its column r16 (from the staged lines) and of
 // Omega row 16t + r16.
 //
-// Omega shared by all blocks (TAB): read from the table omega_table_kernel
-// wrote at set-up, already in MFMA operand order (16 bytes per lane and
-// tile, one coalesced load per tile), software-pipelined with A in registers;
-// the waves run without barriers.  Omega keyed per block (!TAB): regenerated
+// Omega shared by all blocks (TAB): regenerated once per sketch update by
+// omega_table_kernel into a small table (l x max m_b, resident in L2) already
+// in MFMA operand order (16 bytes per lane and tile, one coalesced load per
+// tile), instead of once per work item and chunk; software-pipelined with A
+// in registers, the waves run without barriers.  Omega keyed per block (!TAB): regenerated
 // per 32-row chunk into LDS, double-buffered like A, one LDS-only barrier per
 // chunk.  The ragged last chunk is handled after the loop.
 // ---------------------------------------------------------------------------

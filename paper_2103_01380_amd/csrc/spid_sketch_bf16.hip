@@ -1,6 +1,6 @@
 // spid_sketch_bf16.hip -- bfloat16 sketch launches (split-term A, FP32
 // accumulation) with Omega keyed per block, regenerated in the kernels; the
-// shared-Omega launches read the set-up table (spid_sketch_bf16_tab.hip).
+// shared-Omega launches read the per-update table (spid_sketch_bf16_tab.hip).
 #include "spid_sketch_launch.h"
 
 namespace spid_host {

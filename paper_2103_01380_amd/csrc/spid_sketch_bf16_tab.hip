@@ -1,5 +1,5 @@
 // spid_sketch_bf16_tab.hip -- bfloat16 sketch launches with Omega shared by
-// all blocks (Section 2): the sketch matrix is written once at set-up as a
+// all blocks (Section 2): the sketch matrix is regenerated once per update as a
 // table in MFMA operand order and read by the batch and one-snapshot kernels.
 #include "spid_sketch_launch.h"
 

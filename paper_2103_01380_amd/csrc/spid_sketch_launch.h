@@ -11,7 +11,7 @@ namespace spid_host {
 constexpr int kPrF64 = 0, kPrBF16 = 1, kPrFP8 = 2;
 
 // ST: one-snapshot update of snapshot jst over the block groups; TAB: the
-// bfloat16 kernel reads Omega from the set-up table (shared Omega only)
+// bfloat16 kernel reads Omega from the per-update table (shared Omega only)
 template <int PR, typename TA, int MT, int TN, int NW, bool VEC, bool ST, bool TAB>
 void launch_sketch_k(spid_ctx* c, int j0, int j1, int jst, hipStream_t s) {
   const Plan& p = c->plan;
