@@ -473,12 +473,15 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_sitems = take(sizeof(SkItem) * std::max<size_t>(1, p.sitems.size()));
   p.off_sheads = take(sizeof(int32_t) * std::max<size_t>(1, p.sheads.size()));
   p.off_ritems = take(sizeof(int32_t) * std::max<size_t>(1, p.ritems.size()));
-  if (d->prec == SPID_SK_BF16 && d->omega_per_block == 0 && !p.coarse) {
+  if (d->omega_per_block == 0 && !p.coarse &&
+      (d->prec == SPID_SK_BF16 || (d->prec == SPID_SK_FP8E4M3 && !p.ritems.empty()))) {
     int64_t max_m = 0;
     for (int b = 0; b < nb; ++b) max_m = std::max<int64_t>(max_m, d->h_m[b]);
-    p.omtab_cols = (max_m + kKC - 1) / kKC * kKC;
+    const int64_t ch = d->prec == SPID_SK_BF16 ? kKC : kKC8;
+    p.omtab_cols = (max_m + ch - 1) / ch * ch;
   }
-  p.off_omtab = take(sizeof(uint16_t) * (size_t)sh.MT * 16 * (size_t)std::max<int64_t>(1, p.omtab_cols));
+  p.off_omtab = take((d->prec == SPID_SK_BF16 ? 2 : 1) * (size_t)sh.MT * 16 *
+                     (size_t)std::max<int64_t>(1, p.omtab_cols));
   // mixed error pass: split-bfloat16 coefficients and compact column lists
   const size_t kp_bf = 32 * (size_t)sh.KS32;
   p.off_pt = take(sh.rc_bf16 ? sizeof(uint16_t) * 3 * kp_bf * (size_t)p.sum_n : 256);
@@ -775,11 +778,13 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
     return SPID_OK;
   }
   // shared Omega: regenerated from the generator for this update into the
-  // small table the sketch kernels read (l x max m_b, L2-resident)
-  if (p.omtab_cols > 0) {
+  // small table the sketch kernels read (l x max m_b, L2-resident): the
+  // bfloat16 kernels, and the FP8 one-snapshot (resident-Omega) kernel
+  const bool one_snapshot = p.st_ok && j1 - j0 <= kStreamMaxW;
+  if (p.omtab_cols > 0 && (c->desc.prec == SPID_SK_BF16 || one_snapshot)) {
     if (!launch_omega_table(c, s)) return fail(SPID_EHIP, "Omega table launch failed");
   }
-  if (p.st_ok && j1 - j0 <= kStreamMaxW) {
+  if (one_snapshot) {
     // a few snapshots: one launch per snapshot with the blocks as MFMA columns
     for (int j = j0; j < j1; ++j) {
       const bool ok = sketch_stream_prec(c, j, s);

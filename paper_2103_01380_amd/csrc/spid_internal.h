@@ -156,10 +156,10 @@ struct Plan {
   int64_t ts_n2sum = 0;
   int64_t sum_n = 0, sum_m = 0, part_elems = 0;
   int max_n = 0, max_split_n = 0;
-  // bfloat16 sketch with Omega shared by all blocks: the sketch matrix as a
-  // table in MFMA operand order (MT*16 rows x omtab_cols columns), regenerated
-  // at the start of every sketch update (omtab_cols = max m rounded up to the
-  // 32-row chunk; 0: no table)
+  // Omega shared by all blocks, regenerated at the start of every sketch update
+  // into a table of MT*16 rows x omtab_cols columns (max m rounded up to the
+  // chunk; 0: no table): bfloat16 in MFMA operand order for the bfloat16
+  // kernels, e4m3 chunk rows for the FP8 one-snapshot kernel
   int64_t omtab_cols = 0;
   size_t off_omtab = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,
@@ -219,7 +219,7 @@ struct SelJob {
 void sketch_batch_f64(spid_ctx* c, int j0, int j1, hipStream_t s);    // spid_sketch_f64.hip
 void sketch_batch_bf16(spid_ctx* c, int j0, int j1, hipStream_t s);   // spid_sketch_bf16.hip
 void sketch_batch_bf16_tab(spid_ctx* c, int j0, int j1, hipStream_t s); // spid_sketch_bf16_tab.hip
-// the bfloat16 Omega table (spid_sketch_bf16_tab.hip); false if the launch failed
+// the Omega table of the update (spid_sketch_bf16_tab.hip); false if the launch failed
 bool launch_omega_table(spid_ctx* c, hipStream_t s);
 void sketch_batch_fp8(spid_ctx* c, int j0, int j1, hipStream_t s);    // spid_sketch_fp8.hip
 // one-snapshot sketch of column j (blocks as the MFMA columns); false if the

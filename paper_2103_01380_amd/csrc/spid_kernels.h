@@ -693,6 +693,31 @@ __global__ __launch_bounds__(64 * NW) void sketch_bf16_kernel(
 constexpr int kKC8 = 128;
 constexpr int kOm8Stride = kKC8 + 16;   // bytes per Omega row in LDS
 
+// position of chunk row kk (0..127) in an Omega row of the chunk (the k
+// layout below)
+__host__ __device__ constexpr int fp8_kpos(int kk) {
+  return (kk & ~63) | (((kk >> 2) & 3) << 4) | (((kk >> 4) & 3) << 2) | (kk & 3);
+}
+
+// Shared e4m3 Omega for the one-snapshot updates, regenerated once per update:
+// chunk c (rows 128c.. of A), Omega row r: 128 bytes at ((c * MT*16 + r) * 128),
+// entry of A row 128c + kk at byte fp8_kpos(kk); rows l.. zero.  One thread
+// per pair of Omega rows and A row.
+template <typename TB>   // uint8_t
+__global__ __launch_bounds__(256) void omega_table_e4m3_kernel(int l, int MT, int64_t ncols,
+                                                               uint64_t seed, TB* __restrict__ tab) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)MT * 8 * ncols) return;
+  const int q = (int)(e / ncols);
+  const int64_t i = e - (int64_t)q * ncols;
+  float z0 = 0.0f, z1 = 0.0f;
+  if (2 * q < l) omega_pair_rounded<1>(seed, 0u, (uint32_t)i, (uint32_t)q, z0, z1);
+  if (2 * q + 1 >= l) z1 = 0.0f;
+  const int64_t base = (i >> 7) * MT * 16 * kKC8 + fp8_kpos((int)(i & 127));
+  tab[base + (int64_t)(2 * q) * kKC8] = (TB)to_e4m3_byte(z0);
+  tab[base + (int64_t)(2 * q + 1) * kKC8] = (TB)to_e4m3_byte(z1);
+}
+
 template <int NTHR>
 __device__ __forceinline__ void gen_omega_chunk_e4m3(uint8_t* __restrict__ om, int l,
                                                      uint64_t seed, uint32_t bkey, int64_t k0,
@@ -703,7 +728,7 @@ __device__ __forceinline__ void gen_omega_chunk_e4m3(uint8_t* __restrict__ om, i
     float z0, z1;
     omega_pair_rounded<1>(seed, bkey, (uint32_t)(k0 + kk), (uint32_t)q, z0, z1);
     // chunk row kk = 64 h + 16 w + 4 g + x sits at k = 64 h + 16 g + 4 w + x
-    const int kpos = (kk & ~63) | (((kk >> 2) & 3) << 4) | (((kk >> 4) & 3) << 2) | (kk & 3);
+    const int kpos = fp8_kpos(kk);
     om[(2 * q) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte(z0);
     if (2 * q + 1 < l) om[(2 * q + 1) * kOm8Stride + kpos] = (uint8_t)to_e4m3_byte(z1);
   }
@@ -726,12 +751,23 @@ __device__ __forceinline__ int fp8_block_exp(float amax) {
   return max(ex - 8, -127);
 }
 
-// One split term of a lane's 32 values (two 16-value halves, each in its own
-// 32-row K block): e4m3 bytes packed 4 per int with each half scaled by its
-// block's power of two, the residual left for the next term, and the E8M0
-// scale byte of K block g that this lane supplies to the MFMA.
-__device__ __forceinline__ i32x8 fp8_term(float res[32], int g, int& scale_byte,
-                                          bool rem_needed) {
+// The split terms of a lane's 32 values (two 16-value halves, each in its own
+// 32-row K block).  Term h of a K block is taken at the power of two
+// 2^(E - 4h), E from the block maximum (amax * 2^-E < 256): rounding to e4m3
+// leaves at most 1/16 of a value's own binade, so every later residual times
+// 2^-(E - 4h) stays below 256 too and no term saturates.  fp8_block_scales
+// finds E for the lane's two halves (the block maxima are combined over the
+// two lanes holding each block) and the exponent of the K block g that this
+// lane's scale operand supplies to the MFMA; fp8_term forms one term: e4m3
+// bytes packed 4 per int (v_cvt_scalef32_pk_fp8_f32: x / 2^E' rounded to
+// nearest even) and, unless it is the last term, what it represents
+// (v_cvt_scalef32_pk_f32_fp8: byte * 2^E') taken off the residual.
+struct Fp8Scales {
+  int e_first, e_second;   // exponents of the lane's two K blocks
+  int e_g;                 // exponent of K block g (the lane's MFMA scale)
+};
+
+__device__ __forceinline__ Fp8Scales fp8_block_scales(const float res[32], int g) {
   float h0 = 0.0f, h1 = 0.0f;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -747,42 +783,47 @@ __device__ __forceinline__ i32x8 fp8_term(float res[32], int g, int& scale_byte,
   const bool lo_pair = g < 2;
   const float b0 = lo_pair ? h0 : o0, b1 = lo_pair ? o0 : h0;
   const float b2 = lo_pair ? h1 : o1, b3 = lo_pair ? o1 : h1;
-  const int e_first = fp8_block_exp(lo_pair ? b0 : b1);
-  const int e_second = fp8_block_exp(lo_pair ? b2 : b3);
-  const float bg = g == 0 ? b0 : (g == 1 ? b1 : (g == 2 ? b2 : b3));
-  scale_byte = fp8_block_exp(bg) + 127;
+  Fp8Scales sc;
+  sc.e_first = fp8_block_exp(lo_pair ? b0 : b1);
+  sc.e_second = fp8_block_exp(lo_pair ? b2 : b3);
+  sc.e_g = fp8_block_exp(g == 0 ? b0 : (g == 1 ? b1 : (g == 2 ? b2 : b3)));
+  return sc;
+}
+
+__device__ __forceinline__ i32x8 fp8_term(float res[32], const Fp8Scales& sc, int h,
+                                          bool rem_needed) {
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
   i32x8 out;
 #pragma unroll
   for (int hh = 0; hh < 2; ++hh) {
-    const float down = ldexpf(1.0f, -(hh ? e_second : e_first));
+    const float scale = ldexpf(1.0f, max((hh ? sc.e_second : sc.e_first) - 4 * h, -127));
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
       const int e = 16 * hh + 4 * w;
-      const int p0 = __builtin_amdgcn_cvt_pk_fp8_f32(res[e] * down, res[e + 1] * down, 0, false);
-      const int p1 =
-          __builtin_amdgcn_cvt_pk_fp8_f32(res[e + 2] * down, res[e + 3] * down, 0, false);
-      out[4 * hh + w] = (int)(((uint32_t)p0 & 0xffffu) | ((uint32_t)p1 << 16));
+      s16x2 pk = s16x2{0, 0};
+      pk = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(pk, res[e], res[e + 1], scale, false);
+      pk = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(pk, res[e + 2], res[e + 3], scale, true);
+      out[4 * hh + w] = __builtin_bit_cast(int, pk);
     }
-  }
-  // what the term represents is taken off the residual (not after the last
-  // term): bytes 0-1 and 2-3 of each word back to single precision in pairs
-  if (rem_needed) {
-#pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-      const float up = ldexpf(1.0f, hh ? e_second : e_first);
+    if (rem_needed) {
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         const int e = 16 * hh + 4 * w;
-        const f32x2 q0 = __builtin_amdgcn_cvt_pk_f32_fp8(out[4 * hh + w], false);
-        const f32x2 q1 = __builtin_amdgcn_cvt_pk_f32_fp8(out[4 * hh + w], true);
-        res[e] -= q0[0] * up;
-        res[e + 1] -= q0[1] * up;
-        res[e + 2] -= q1[0] * up;
-        res[e + 3] -= q1[1] * up;
+        const f32x2 q0 = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(out[4 * hh + w], scale, false);
+        const f32x2 q1 = __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(out[4 * hh + w], scale, true);
+        res[e] -= q0[0];
+        res[e + 1] -= q0[1];
+        res[e + 2] -= q1[0];
+        res[e + 3] -= q1[1];
       }
     }
   }
   return out;
+}
+
+// E8M0 scale byte of term h for the lane's K block g
+__device__ __forceinline__ int fp8_scale_byte(const Fp8Scales& sc, int h) {
+  return max(sc.e_g - 4 * h, -127) + 127;
 }
 
 template <typename TA, int MT, int TN, int NW, bool VEC, bool ST>
@@ -832,9 +873,10 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
     }
 #pragma unroll
     for (int u = 0; u < TN; ++u) {
+      const Fp8Scales sc = fp8_block_scales(a[u], g);
       for (int h = 0; h < terms; ++h) {
-        int sb;
-        const i32x8 bt = fp8_term(a[u], g, sb, h + 1 < terms);
+        const i32x8 bt = fp8_term(a[u], sc, h, h + 1 < terms);
+        const int sb = fp8_scale_byte(sc, h);
 #pragma unroll
         for (int t = 0; t < MT; ++t) acc[t][u] = mfma_fp8_scaled(oa[t], bt, acc[t][u], 127, sb);
       }
@@ -895,18 +937,19 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
 // One-snapshot FP8 update with the sketch matrix resident in LDS.  A work
 // item is one K range [r0, r1) of at most kResChunks chunks shared by `cnt`
 // block groups (stream items first, first + stride, ...; equal m and K
-// split).  The workgroup generates Omega for the whole range once, then each
-// wave streams its 16 blocks of every group through it; the main loop has no
-// barriers.  Omega is regenerated once per item instead of once per group
-// and chunk.  Dynamic LDS: kResChunks * MT * 16 * kOm8Stride bytes.
+// split).  The workgroup copies the range's Omega rows from the table the
+// update regenerated (omega_table_e4m3_kernel), then each wave streams its 16
+// blocks of every group through it; the main loop has no barriers.  Dynamic
+// LDS: kResChunks * MT * 16 * kOm8Stride bytes.
 // ---------------------------------------------------------------------------
 constexpr int kResChunks = 5;
 
 template <typename TA, int MT, int NW, bool VEC>
 __global__ __launch_bounds__(64 * NW) void sketch_fp8_resident_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ sitems,
-    const int32_t* __restrict__ ritems, int l, uint64_t seed, const int32_t* __restrict__ perm,
-    int jst, int terms, float* __restrict__ Y, float* __restrict__ part) {
+    const int32_t* __restrict__ ritems, int l, const uint8_t* __restrict__ omtab,
+    const int32_t* __restrict__ perm, int jst, int terms, float* __restrict__ Y,
+    float* __restrict__ part) {
   extern __shared__ __attribute__((aligned(16))) uint8_t omr[];
   constexpr int kCh = MT * 16 * kOm8Stride;
   const int first = ritems[3 * blockIdx.x], cnt = ritems[3 * blockIdx.x + 1];
@@ -916,10 +959,18 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_resident_kernel(
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r16 = lane & 15;
   const int nch = (int)((r1 - r0 + kKC8 - 1) / kKC8);
-  for (int e = tid; e < nch * kCh; e += 64 * NW) omr[e] = 0;
-  __syncthreads();
-  for (int c = 0; c < nch; ++c)
-    gen_omega_chunk_e4m3<64 * NW>(omr + c * kCh, l, seed, 0u, r0 + (int64_t)c * kKC8, tid);
+  // the range's Omega rows from the update's table (r0 is a multiple of the
+  // chunk), 16-byte pieces
+  {
+    const i32x4* __restrict__ src =
+        reinterpret_cast<const i32x4*>(omtab + (r0 / kKC8) * MT * 16 * kKC8);
+    const int npc = nch * MT * 16 * (kKC8 / 16);
+    for (int e = tid; e < npc; e += 64 * NW) {
+      const int row = e / (kKC8 / 16), pc = e - row * (kKC8 / 16);   // row over chunks x rows
+      const int c = row / (MT * 16), r = row - c * (MT * 16);
+      *reinterpret_cast<i32x4*>(omr + c * kCh + r * kOm8Stride + 16 * pc) = src[e];
+    }
+  }
   lds_barrier();
 
   const int64_t nfull = (r1 - r0) / kKC8;
@@ -944,9 +995,10 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_resident_kernel(
         const i32x4 hi = *reinterpret_cast<const i32x4*>(orow + 64 + 16 * g);
         oa[t] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
       }
+      const Fp8Scales sc = fp8_block_scales(a, g);
       for (int h = 0; h < terms; ++h) {
-        int sb;
-        const i32x8 bt = fp8_term(a, g, sb, h + 1 < terms);
+        const i32x8 bt = fp8_term(a, sc, h, h + 1 < terms);
+        const int sb = fp8_scale_byte(sc, h);
 #pragma unroll
         for (int t = 0; t < MT; ++t) acc[t] = mfma_fp8_scaled(oa[t], bt, acc[t], 127, sb);
       }

@@ -12,7 +12,7 @@ bool launch_fp8_resident(spid_ctx* c, int j, hipStream_t s) {
   if (!allow_lds((const void*)kern, lds)) return false;
   hipLaunchKernelGGL(kern, dim3((unsigned)(p.ritems.size() / 3)), dim3(64 * kStreamNW), lds, s,
                      c->at<BlkInfo>(p.off_blk), c->at<SkItem>(p.off_sitems),
-                     c->at<int32_t>(p.off_ritems), c->desc.l, c->desc.seed,
+                     c->at<int32_t>(p.off_ritems), c->desc.l, c->at<uint8_t>(p.off_omtab),
                      c->at<int32_t>(p.off_perm), j, c->desc.lp_terms, c->at<float>(p.off_Y),
                      c->at<float>(p.off_part));
   return true;
