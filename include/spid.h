@@ -141,9 +141,8 @@ typedef struct {
  *            split along their rows (K) until about this many items exist
  *   rc_rpi   error-pass row sub-tiles per work item, 1..16 (double-precision
  *            error pass only; the split-bfloat16 pass uses one)
- *   st_groups one-snapshot FP8 updates: groups of 128 equal-m blocks that share
- *            one resident sketch-matrix range per work item, 1..16 (default:
- *            enough to leave about one work item per compute unit, at most 8) */
+ *   st_groups one-snapshot FP8 updates of FP32 data: groups of 128 equal-m
+ *            blocks one work item streams in turn, 1..16 (default 1) */
 typedef struct {
   int32_t sk_tn;
   int32_t sk_nw;

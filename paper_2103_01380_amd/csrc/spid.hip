@@ -389,11 +389,9 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
       int64_t rows = (m + nsplit - 1) / nsplit;
       rows = (rows + kKC - 1) / kKC * kKC;
       if (d->prec == SPID_SK_FP8E4M3) {
-        // resident Omega: K ranges of whole 128-row chunks, at most kResChunks of them
-        const int64_t rmax = (int64_t)kResChunks * kKC8;
-        nsplit = (int)std::max<int64_t>(1, (m + rmax - 1) / rmax);
-        rows = (m + nsplit - 1) / nsplit;
-        rows = (rows + kKC8 - 1) / kKC8 * kKC8;
+        // one work item streams a group over all of K (Omega from the update's table)
+        nsplit = 1;
+        rows = m;
       }
       nsplit = (int)((m + rows - 1) / rows);
       const int64_t gpart = nsplit > 1 ? st_off : 0;
@@ -417,11 +415,9 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     }
     p.st_part_elems = st_off;
     if (d->prec == SPID_SK_FP8E4M3) {
-      // groups sharing (m, K split) in runs; pack gw of them per resident item, so
-      // that about one item per compute unit (256) exists: more groups per item
-      // amortise the Omega generation further (measured on 32768 blocks of 2560 rows:
-      // 2 groups per item 87 ms per 384 snapshots, 4 groups 68 ms, 8 groups 95 ms)
-      int64_t gw = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)p.sitems.size() / 256));
+      // groups in runs of equal m; gw of them per work item (one by default: the
+      // items need no shared set-up, so more of them only lengthen each)
+      int64_t gw = 1;
       if (tune && tune->st_groups) gw = tune->st_groups;
       sh.st_groups = (int)gw;
       size_t i = 0;
@@ -474,7 +470,8 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_sheads = take(sizeof(int32_t) * std::max<size_t>(1, p.sheads.size()));
   p.off_ritems = take(sizeof(int32_t) * std::max<size_t>(1, p.ritems.size()));
   if (d->omega_per_block == 0 && !p.coarse &&
-      (d->prec == SPID_SK_BF16 || (d->prec == SPID_SK_FP8E4M3 && !p.ritems.empty()))) {
+      (d->prec == SPID_SK_BF16 ||
+       (d->prec == SPID_SK_FP8E4M3 && d->a_dtype == SPID_A_F32 && !p.ritems.empty()))) {
     int64_t max_m = 0;
     for (int b = 0; b < nb; ++b) max_m = std::max<int64_t>(max_m, d->h_m[b]);
     const int64_t ch = d->prec == SPID_SK_BF16 ? kKC : kKC8;
@@ -779,7 +776,7 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
   }
   // shared Omega: regenerated from the generator for this update into the
   // small table the sketch kernels read (l x max m_b, L2-resident): the
-  // bfloat16 kernels, and the FP8 one-snapshot (resident-Omega) kernel
+  // bfloat16 kernels, and the FP8 one-snapshot kernel
   const bool one_snapshot = p.st_ok && j1 - j0 <= kStreamMaxW;
   if (p.omtab_cols > 0 && (c->desc.prec == SPID_SK_BF16 || one_snapshot)) {
     if (!launch_omega_table(c, s)) return fail(SPID_EHIP, "Omega table launch failed");

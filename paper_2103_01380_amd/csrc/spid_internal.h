@@ -64,7 +64,7 @@ struct Shape {
   int rc_bf16;   // 1: split-bfloat16 error pass (FP32 data, low-precision sketch)
   int KS32;      // k-steps of 32 selected columns in the split-bfloat16 error pass
   int sk_items;  // target number of sketch work items
-  int st_groups = 0;  // one-snapshot FP8 updates: block groups per resident-Omega item
+  int st_groups = 0;  // one-snapshot FP8 updates: block groups per work item
 };
 
 inline int pick_mt(int l) {
@@ -138,7 +138,7 @@ struct Plan {
   std::vector<int32_t> perm;
   std::vector<SkItem> sitems;
   std::vector<int32_t> sheads;
-  std::vector<int32_t> ritems;   // FP8 resident-Omega items: (first stream item, count, stride)
+  std::vector<int32_t> ritems;   // FP8 one-snapshot items: (first stream item, count, stride)
   int64_t st_part_elems = 0;
   // coarse-grid sketch: block grids (the single-pass error uses the error-pass items)
   bool coarse = false;

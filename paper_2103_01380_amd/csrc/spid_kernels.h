@@ -699,10 +699,16 @@ __host__ __device__ constexpr int fp8_kpos(int kk) {
   return (kk & ~63) | (((kk >> 2) & 3) << 4) | (((kk >> 4) & 3) << 2) | (kk & 3);
 }
 
-// Shared e4m3 Omega for the one-snapshot updates, regenerated once per update:
-// chunk c (rows 128c.. of A), Omega row r: 128 bytes at ((c * MT*16 + r) * 128),
-// entry of A row 128c + kk at byte fp8_kpos(kk); rows l.. zero.  One thread
-// per pair of Omega rows and A row.
+// Shared e4m3 Omega for the one-snapshot updates, regenerated once per update,
+// in the f8f6f4 A-operand order of sketch_fp8_stream_kernel: chunk c (A rows
+// 128c..), tile t, lane 16 g + r (Omega row 16t + r), 32 bytes: k = 16g..16g+15
+// then 64+16g..64+16g+15 of the chunk, k = the A row within the chunk.  Rows
+// l.. zero.  One thread per pair of Omega rows and A row.
+__host__ __device__ constexpr int64_t omega_tab8_index(int MT, int r, int64_t i) {
+  return (((i >> 7) * MT + (r >> 4)) * 64 + 16 * ((i >> 4) & 3) + (r & 15)) * 32 +
+         16 * ((i >> 6) & 1) + (i & 15);
+}
+
 template <typename TB>   // uint8_t
 __global__ __launch_bounds__(256) void omega_table_e4m3_kernel(int l, int MT, int64_t ncols,
                                                                uint64_t seed, TB* __restrict__ tab) {
@@ -713,9 +719,8 @@ __global__ __launch_bounds__(256) void omega_table_e4m3_kernel(int l, int MT, in
   float z0 = 0.0f, z1 = 0.0f;
   if (2 * q < l) omega_pair_rounded<1>(seed, 0u, (uint32_t)i, (uint32_t)q, z0, z1);
   if (2 * q + 1 >= l) z1 = 0.0f;
-  const int64_t base = (i >> 7) * MT * 16 * kKC8 + fp8_kpos((int)(i & 127));
-  tab[base + (int64_t)(2 * q) * kKC8] = (TB)to_e4m3_byte(z0);
-  tab[base + (int64_t)(2 * q + 1) * kKC8] = (TB)to_e4m3_byte(z1);
+  tab[omega_tab8_index(MT, 2 * q, i)] = (TB)to_e4m3_byte(z0);
+  tab[omega_tab8_index(MT, 2 * q + 1, i)] = (TB)to_e4m3_byte(z1);
 }
 
 template <int NTHR>
@@ -934,67 +939,91 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// One-snapshot FP8 update with the sketch matrix resident in LDS.  A work
-// item is one K range [r0, r1) of at most kResChunks chunks shared by `cnt`
-// block groups (stream items first, first + stride, ...; equal m and K
-// split).  The workgroup copies the range's Omega rows from the table the
-// update regenerated (omega_table_e4m3_kernel), then each wave streams its 16
-// blocks of every group through it; the main loop has no barriers.  Dynamic
-// LDS: kResChunks * MT * 16 * kOm8Stride bytes.
+// One-snapshot FP8 update (FP32 data).  A work item is `cnt` groups of up to
+// 128 equal-m blocks (stream items first, first + stride, ...); wave w takes
+// blocks 16w..16w+15 of a group, column j of each, over all of K (no K split,
+// so no partial sketches and no reduction launch).  Per 128-row chunk the
+// wave loads its 16 columns as whole 128-byte lines (8 lanes per column: four
+// lines x two halves of 8 columns), passes them through its LDS tile into the
+// f8f6f4 B-operand layout (lane (g, c): rows 16g..16g+15 and 64+16g..64+16g+15
+// of column c, k = the row), and reads its Omega operands from the update's
+// table (omega_table_e4m3_kernel: 32 bytes per lane and tile, L2-resident)
+// ahead of the next chunk's lines, so that waiting for Omega does not wait
+// for them.  No barriers.
+//
+// A staged column is 128 floats (512 bytes, 32 pieces of 16); piece q sits at
+// (q & 16) | ((q & 15) ^ s(c)) with s(c) = 8 (c & 1) + c / 2 (c < 16): the 16
+// columns of a read and the two columns of every 16-lane write phase then hit
+// distinct banks.
 // ---------------------------------------------------------------------------
-constexpr int kResChunks = 5;
+__device__ __forceinline__ int fp8_piece_pos(int q, int col) {
+  return (q & 16) | ((q & 15) ^ (((col & 1) << 3) | ((col >> 1) & 7)));
+}
 
-template <typename TA, int MT, int NW, bool VEC>
-__global__ __launch_bounds__(64 * NW) void sketch_fp8_resident_kernel(
+template <int MT, int NW, bool VEC>
+__global__ __launch_bounds__(64 * NW) void sketch_fp8_stream_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ sitems,
-    const int32_t* __restrict__ ritems, int l, const uint8_t* __restrict__ omtab,
-    const int32_t* __restrict__ perm, int jst, int terms, float* __restrict__ Y,
-    float* __restrict__ part) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t omr[];
-  constexpr int kCh = MT * 16 * kOm8Stride;
+    const int32_t* __restrict__ ritems, int l, const i32x4* __restrict__ omtab,
+    const int32_t* __restrict__ perm, int jst, int terms, float* __restrict__ Y) {
+  __shared__ __attribute__((aligned(16))) float stage_all[NW * 16 * kKC8];
   const int first = ritems[3 * blockIdx.x], cnt = ritems[3 * blockIdx.x + 1];
   const int stride = ritems[3 * blockIdx.x + 2];
-  const int64_t r0 = sitems[first].r0, r1 = sitems[first].r1;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, r16 = lane & 15;
-  const int nch = (int)((r1 - r0 + kKC8 - 1) / kKC8);
-  // the range's Omega rows from the update's table (r0 is a multiple of the
-  // chunk), 16-byte pieces
-  {
-    const i32x4* __restrict__ src =
-        reinterpret_cast<const i32x4*>(omtab + (r0 / kKC8) * MT * 16 * kKC8);
-    const int npc = nch * MT * 16 * (kKC8 / 16);
-    for (int e = tid; e < npc; e += 64 * NW) {
-      const int row = e / (kKC8 / 16), pc = e - row * (kKC8 / 16);   // row over chunks x rows
-      const int c = row / (MT * 16), r = row - c * (MT * 16);
-      *reinterpret_cast<i32x4*>(omr + c * kCh + r * kOm8Stride + 16 * pc) = src[e];
-    }
-  }
-  lds_barrier();
-
-  const int64_t nfull = (r1 - r0) / kKC8;
-  const int64_t kt = r0 + nfull * kKC8;
+  const int g = lane >> 4, r16 = lane & 15, p8 = lane & 7, c8 = lane >> 3;
+  float* __restrict__ st = stage_all + wave * 16 * kKC8;
+  const i32x4* __restrict__ ot = omtab + 2 * lane;
   for (int gi = 0; gi < cnt; ++gi) {
     const SkItem it = sitems[first + gi * stride];
-    SkLane<TA, 1> ln;
-    sk_setup_stream<TA, 1>(blks, perm, it, wave * 16, r16, jst, ln);
+    SkLane<float, 1> ln;   // output column: block perm[c0 + 16 wave + r16]
+    sk_setup_stream<float, 1>(blks, perm, it, wave * 16, r16, jst, ln);
+    SkLines<float, 1> ld;  // load columns: blocks 16 wave + 8 h + c8
+    sk_lines_stream<float, 1>(blks, perm, it, wave * 16, lane, jst, ld);
     f32x4 acc[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    auto load_full = [&](int64_t k0, float (&a)[32]) {
-      load_pieces_full<TA, 4, 4, 16, VEC>(ln.cb[0], k0 + 4 * g, ln.ok[0], a);
-      load_pieces_full<TA, 4, 4, 16, VEC>(ln.cb[0], k0 + 64 + 4 * g, ln.ok[0], a + 16);
+    // lines L = 0..3 of half h: rows k0 + 32 L + 4 p8 .. +3 of load column h
+    auto load_full = [&](int64_t k0, float (&x)[2][4][4]) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int L = 0; L < 4; ++L) load_line<float, VEC>(ld.cb[0][h], k0 + 32 * L, p8, x[h][L]);
     };
-    auto mfma_chunk = [&](const uint8_t* __restrict__ omb, float (&a)[32]) {
-      i32x8 oa[MT];
+    auto load_tail = [&](int64_t k0, float (&x)[2][4][4]) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int L = 0; L < 4; ++L)
+          load_line_tail<float>(ld.cb[0][h], k0 + 32 * L, it.r1, p8, x[h][L]);
+    };
+    auto load_om = [&](int64_t k0, i32x8 (&o)[MT]) {
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        const uint8_t* orow = omb + (16 * t + r16) * kOm8Stride;
-        const i32x4 lo = *reinterpret_cast<const i32x4*>(orow + 16 * g);
-        const i32x4 hi = *reinterpret_cast<const i32x4*>(orow + 64 + 16 * g);
-        oa[t] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        const i32x4* q = ot + ((k0 >> 7) * MT + t) * 128;
+        const i32x4 lo = q[0], hi = q[1];
+        o[t] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
       }
+    };
+    // stage the chunk's lines, read back the operand layout, split and multiply
+    auto chunk = [&](const float (&x)[2][4][4], const i32x8 (&oa)[MT]) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int L = 0; L < 4; ++L) {
+          const int col = 8 * h + c8;
+          *reinterpret_cast<f32x4*>(st + col * kKC8 + 4 * fp8_piece_pos(8 * L + p8, col)) =
+              f32x4{x[h][L][0], x[h][L][1], x[h][L][2], x[h][L][3]};
+        }
+      float a[32];
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const f32x4 v = *reinterpret_cast<const f32x4*>(
+              st + r16 * kKC8 + 4 * fp8_piece_pos(16 * hf + 4 * g + w, r16));
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[16 * hf + 4 * w + e] = v[e];
+        }
       const Fp8Scales sc = fp8_block_scales(a, g);
       for (int h = 0; h < terms; ++h) {
         const i32x8 bt = fp8_term(a, sc, h, h + 1 < terms);
@@ -1003,32 +1032,37 @@ __global__ __launch_bounds__(64 * NW) void sketch_fp8_resident_kernel(
         for (int t = 0; t < MT; ++t) acc[t] = mfma_fp8_scaled(oa[t], bt, acc[t], 127, sb);
       }
     };
-    float a0[32], a1[32];
-    if (nfull > 0) load_full(r0, a0);
-    const int64_t klast = r0 + (nfull - 1) * kKC8;
+    const int64_t nfull = (it.r1 - it.r0) / kKC8;
+    const int64_t klast = it.r0 + (nfull - 1) * kKC8;
+    const int64_t kt = it.r0 + nfull * kKC8;
+    float x0[2][4][4], x1[2][4][4];
+    i32x8 oa[MT];
+    if (nfull > 0) load_full(it.r0, x0);
+    auto step = [&](const float (&cur)[2][4][4], float (&nxt)[2][4][4], int64_t k0) {
+      load_om(k0, oa);                            // before the next lines: waited for first
+      load_full(min(k0 + kKC8, klast), nxt);
+      chunk(cur, oa);
+    };
     int64_t c = 0;
     for (; c + 2 <= nfull; c += 2) {
-      load_full(min(r0 + (c + 1) * kKC8, klast), a1);
-      mfma_chunk(omr + c * kCh, a0);
-      load_full(min(r0 + (c + 2) * kKC8, klast), a0);
-      mfma_chunk(omr + (c + 1) * kCh, a1);
+      step(x0, x1, it.r0 + c * kKC8);
+      step(x1, x0, it.r0 + (c + 1) * kKC8);
     }
-    if (c < nfull) mfma_chunk(omr + c * kCh, a0);
-    if (kt < r1) {
-      load_pieces_tail<TA, 4, 4, 16>(ln.cb[0], kt + 4 * g, r1, ln.ok[0], a0);
-      load_pieces_tail<TA, 4, 4, 16>(ln.cb[0], kt + 64 + 4 * g, r1, ln.ok[0], a0 + 16);
-      mfma_chunk(omr + nfull * kCh, a0);
+    if (c < nfull) step(x0, x1, it.r0 + c * kKC8);
+    if (kt < it.r1) {
+      load_om(kt, oa);
+      load_tail(kt, x0);
+      chunk(x0, oa);
     }
     if (ln.ok[0]) {
       const BlkInfo bi = blks[it.blk];
-      float* dst = it.gnsplit == 1 ? Y : part;
-      const int64_t ob = sk_out_offset<TA, 1, NW * 16, true>(blks, perm, bi, it, ln, 0, l, jst);
+      const int64_t ob = sk_out_offset<float, 1, NW * 16, true>(blks, perm, bi, it, ln, 0, l, jst);
 #pragma unroll
       for (int t = 0; t < MT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = 16 * t + 4 * g + v;
-          if (row < l) dst[ob + row] = acc[t][v];
+          if (row < l) Y[ob + row] = acc[t][v];
         }
     }
   }

@@ -112,11 +112,11 @@ def _fp8_gates(blocks, g, o, gamma=1e-2, y_rtol=2e-4):
 
 
 @pytest.mark.parametrize("groups", [2, 4, 0])
-def test_stream_fp8_resident_multi_group(groups):
-    """One-snapshot FP8 updates with several groups of 128 equal-m blocks sharing one
-    resident sketch-matrix range per work item (st_groups; 0 = the library's choice).
-    Three groups of 2560-row blocks (four K ranges each, reduced in a fixed order)
-    and a 128 + 2 block run of 1000-row blocks (two K ranges)."""
+def test_stream_fp8_multi_group(groups):
+    """One-snapshot FP8 updates with several groups of 128 equal-m blocks per work
+    item (st_groups; 0 = the library's choice, one): three groups of 2560-row blocks
+    and a 128 + 2 block run of 1000-row blocks (a partial group, a ragged last
+    chunk: 1000 = 7 x 128 + 104)."""
     shapes = [(2560, 80)] * 384 + [(1000, 80)] * 130
     rng = np.random.default_rng(41)
     blocks = []
@@ -126,14 +126,14 @@ def test_stream_fp8_resident_multi_group(groups):
         # columns decaying in time keep the first pivots decidable at the FP8 gap
         A = (U @ V.T + 1e-5 * rng.standard_normal((m, n))) * (0.85 ** np.arange(n))
         blocks.append(np.asfortranarray(A.astype(np.float32)))
-    print(f"case: fp8 resident st_groups={groups}", flush=True)
+    print(f"case: fp8 one-snapshot st_groups={groups}", flush=True)
     g = gpu_run(blocks, 64, 40, 19, prec="fp8", lp_terms=3, stream_columns=True,
                 tuning={"st_groups": groups} if groups else None)
     if groups:
         assert g.tuning["st_groups"] == groups
     o = oracle_run(blocks, 64, 40, 19, prec="fp8")
     e_gpu, r2, pre = _fp8_gates(blocks, g, o)
-    print(f"fp8 resident groups={g.tuning['st_groups']} e_gpu={e_gpu:.3e} "
+    print(f"fp8 one-snapshot groups={g.tuning['st_groups']} e_gpu={e_gpu:.3e} "
           f"e_oracle={o.rel_error:.3e} R2={r2:.3e} min prefix={min(pre)}")
     # the oracle decides 3.6 pivots per block on average at the FP8 gap (0 to 7)
     assert np.mean(pre) >= 3 and max(pre) >= 6

@@ -3,7 +3,7 @@ workloads, and a graph-captured ragged (uneven-batch) step.
 
 Launch shapes change only how the independent blocks of Section 3.2 map onto
 the GPU (column tiles per wave, waves per workgroup, how far blocks are split
-along their rows, error-pass rows per item, resident groups per item), never
+along their rows, error-pass rows per item, block groups per item), never
 the method: every committed shape must meet the same parity rules against the
 oracle as the library's defaults.  Each table entry is run on a small batch with
 the entry's method parameters (sketch arithmetic, data type, l, k, tolerance,
