@@ -470,15 +470,15 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   p.off_sheads = take(sizeof(int32_t) * std::max<size_t>(1, p.sheads.size()));
   p.off_ritems = take(sizeof(int32_t) * std::max<size_t>(1, p.ritems.size()));
   if (d->omega_per_block == 0 && !p.coarse &&
-      (d->prec == SPID_SK_BF16 ||
+      (d->prec == SPID_SK_BF16 || d->prec == SPID_SK_F64 ||
        (d->prec == SPID_SK_FP8E4M3 && d->a_dtype == SPID_A_F32 && !p.ritems.empty()))) {
     int64_t max_m = 0;
     for (int b = 0; b < nb; ++b) max_m = std::max<int64_t>(max_m, d->h_m[b]);
-    const int64_t ch = d->prec == SPID_SK_BF16 ? kKC : kKC8;
+    const int64_t ch = d->prec == SPID_SK_FP8E4M3 ? kKC8 : kKC;
     p.omtab_cols = (max_m + ch - 1) / ch * ch;
   }
-  p.off_omtab = take((d->prec == SPID_SK_BF16 ? 2 : 1) * (size_t)sh.MT * 16 *
-                     (size_t)std::max<int64_t>(1, p.omtab_cols));
+  const size_t om_es = d->prec == SPID_SK_F64 ? 8 : (d->prec == SPID_SK_BF16 ? 2 : 1);
+  p.off_omtab = take(om_es * (size_t)sh.MT * 16 * (size_t)std::max<int64_t>(1, p.omtab_cols));
   // mixed error pass: split-bfloat16 coefficients and compact column lists
   const size_t kp_bf = 32 * (size_t)sh.KS32;
   p.off_pt = take(sh.rc_bf16 ? sizeof(uint16_t) * 3 * kp_bf * (size_t)p.sum_n : 256);
@@ -776,9 +776,9 @@ extern "C" spid_status spid_sketch_update(spid_ctx* c, int32_t j0, int32_t w, vo
   }
   // shared Omega: regenerated from the generator for this update into the
   // small table the sketch kernels read (l x max m_b, L2-resident): the
-  // bfloat16 kernels, and the FP8 one-snapshot kernel
+  // double-precision and bfloat16 kernels, and the FP8 one-snapshot kernel
   const bool one_snapshot = p.st_ok && j1 - j0 <= kStreamMaxW;
-  if (p.omtab_cols > 0 && (c->desc.prec == SPID_SK_BF16 || one_snapshot)) {
+  if (p.omtab_cols > 0 && (c->desc.prec != SPID_SK_FP8E4M3 || one_snapshot)) {
     if (!launch_omega_table(c, s)) return fail(SPID_EHIP, "Omega table launch failed");
   }
   if (one_snapshot) {

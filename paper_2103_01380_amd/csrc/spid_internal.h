@@ -158,8 +158,9 @@ struct Plan {
   int max_n = 0, max_split_n = 0;
   // Omega shared by all blocks, regenerated at the start of every sketch update
   // into a table of MT*16 rows x omtab_cols columns (max m rounded up to the
-  // chunk; 0: no table): bfloat16 in MFMA operand order for the bfloat16
-  // kernels, e4m3 chunk rows for the FP8 one-snapshot kernel
+  // chunk; 0: no table): double chunk rows for the double-precision kernel,
+  // bfloat16 in MFMA operand order for the bfloat16 kernels, e4m3 in f8f6f4
+  // operand order for the FP8 one-snapshot kernel
   int64_t omtab_cols = 0;
   size_t off_omtab = 0;
   size_t off_blk, off_items, off_split, off_rc, off_rcfirst, off_Y, off_part, off_R, off_S, off_k,

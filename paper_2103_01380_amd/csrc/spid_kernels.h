@@ -151,6 +151,38 @@ __device__ __forceinline__ void gen_omega_chunk(TO* __restrict__ om, int l, uint
   }
 }
 
+// Shared double-precision Omega, regenerated once per update: chunk c (A rows
+// 32c..32c+31), Omega row r: 32 doubles at ((c * MT*16 + r) * 32), the
+// chunk's LDS row without its padding; rows l.. zero.  A work item copies its
+// chunks into LDS (copy_omega_chunk_f64) instead of generating them.
+template <typename TD>   // double
+__global__ __launch_bounds__(256) void omega_table_f64_kernel(int l, int MT, int64_t ncols,
+                                                              uint64_t seed, TD* __restrict__ tab) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)MT * 8 * ncols) return;
+  const int q = (int)(e / ncols);
+  const int64_t i = e - (int64_t)q * ncols;
+  double2 z = make_double2(0.0, 0.0);
+  if (2 * q < l) z = omega_pair(seed, 0u, (uint32_t)i, (uint32_t)q);
+  if (2 * q + 1 >= l) z.y = 0.0;
+  const int64_t base = (i >> 5) * MT * 16 * kKC + (i & 31);
+  tab[base + (int64_t)(2 * q) * kKC] = z.x;
+  tab[base + (int64_t)(2 * q + 1) * kKC] = z.y;
+}
+
+template <int STRIDE, int NTHR>
+__device__ __forceinline__ void copy_omega_chunk_f64(double* __restrict__ om, int MT,
+                                                     const double* __restrict__ tab, int64_t k0,
+                                                     int tid) {
+  const f64x2* __restrict__ src = reinterpret_cast<const f64x2*>(tab + (k0 / kKC) * MT * 16 * kKC);
+  for (int e = tid; e < MT * 16 * (kKC / 2); e += NTHR) {
+    const int r = e / (kKC / 2), c2 = e - r * (kKC / 2);
+    const f64x2 v = src[e];
+    om[r * STRIDE + 2 * c2] = v[0];
+    om[r * STRIDE + 2 * c2 + 1] = v[1];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Common set-up of a sketch work item: the lane's columns (clamped to a valid
 // column, with a validity flag), the updated column window, the Omega key.
@@ -233,7 +265,7 @@ template <typename TA, int MT, int TN, int NW, bool VEC, bool ST>
 __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
     const BlkInfo* __restrict__ blks, const SkItem* __restrict__ items, int l, uint64_t seed,
     int omega_per_block, int j0, int j1, const int32_t* __restrict__ perm, int jst,
-    double* __restrict__ Y, double* __restrict__ part) {
+    const double* __restrict__ omtab, double* __restrict__ Y, double* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) double om[2][MT * 16 * kOmStride];
   const SkItem it = items[blockIdx.x];
   const BlkInfo bi = blks[it.blk];
@@ -249,6 +281,35 @@ __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
   }
   const uint32_t bkey = omega_per_block ? (uint32_t)(it.blk + 1) : 0u;
   auto ident = [](double x) { return x; };
+  // a chunk of Omega into LDS: copied from the update's table (shared Omega)
+  // or generated (Omega keyed per block); uniform branch
+  auto fill_om = [&](double* __restrict__ omb, int64_t k0) {
+    if (omtab) copy_omega_chunk_f64<kOmStride, 64 * NW>(omb, MT, omtab, k0, tid);
+    else gen_omega_chunk<double, kOmStride, 64 * NW>(omb, l, seed, bkey, k0, tid, ident);
+  };
+  // the table path split in two, so that its loads are issued before the A
+  // prefetch of the same step and their wait leaves that prefetch in flight
+  constexpr int kOmPieces = MT * 16 * (kKC / 2);   // 16-byte pieces of a chunk
+  constexpr int kOmPer = (kOmPieces + 64 * NW - 1) / (64 * NW);
+  f64x2 omr[kOmPer];
+  auto om_load = [&](int64_t k0) {
+    const f64x2* __restrict__ src = reinterpret_cast<const f64x2*>(omtab + (k0 / kKC) * MT * 16 * kKC);
+#pragma unroll
+    for (int i = 0; i < kOmPer; ++i) {
+      const int e = tid + i * 64 * NW;
+      if (e < kOmPieces) omr[i] = src[e];
+    }
+  };
+  auto om_store = [&](double* __restrict__ omb) {
+#pragma unroll
+    for (int i = 0; i < kOmPer; ++i) {
+      const int e = tid + i * 64 * NW;
+      if (e < kOmPieces) {
+        const int r = e / (kKC / 2), c2 = e - r * (kKC / 2);
+        *reinterpret_cast<f64x2*>(omb + r * kOmStride + 2 * c2) = omr[i];
+      }
+    }
+  };
 
   for (int e = tid; e < 2 * MT * 16 * kOmStride; e += 64 * NW) (&om[0][0])[e] = 0.0;
 
@@ -287,16 +348,23 @@ __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
   __syncthreads();                                      // zero fill before generation
   if (nfull > 0) {
     load_full(it.r0, a0);
-    gen_omega_chunk<double, kOmStride, 64 * NW>(om[0], l, seed, bkey, it.r0, tid, ident);
+    fill_om(om[0], it.r0);
   }
   lds_barrier();
   // one pipeline step: prefetch (clamped: redundant on the last chunk), Omega of
   // the next chunk, MFMAs of this chunk
   auto step = [&](double (&cur)[TN][8], double (&nxt)[TN][8], int b, int64_t k0) {
     const int64_t k1 = min(k0 + kKC, klast);
-    load_full(k1, nxt);
-    gen_omega_chunk<double, kOmStride, 64 * NW>(om[b ^ 1], l, seed, bkey, k1, tid, ident);
-    mfma_chunk(om[b], cur);
+    if (omtab) {
+      om_load(k1);
+      load_full(k1, nxt);
+      mfma_chunk(om[b], cur);
+      om_store(om[b ^ 1]);
+    } else {
+      load_full(k1, nxt);
+      fill_om(om[b ^ 1], k1);
+      mfma_chunk(om[b], cur);
+    }
     lds_barrier();
   };
   int64_t c = 0;
@@ -309,7 +377,7 @@ __global__ __launch_bounds__(64 * NW) void sketch_f64_kernel(
   const int64_t kt = it.r0 + nfull * kKC;
   if (kt < it.r1) {
     const int b = (int)(nfull & 1);
-    gen_omega_chunk<double, kOmStride, 64 * NW>(om[b], l, seed, bkey, kt, tid, ident);
+    fill_om(om[b], kt);
 #pragma unroll
     for (int u = 0; u < TN; ++u)
       load_pieces_tail<TA, 4, 2, 8>(ln.cb[u], kt + 2 * g, it.r1, ln.ok[u], a0[u]);

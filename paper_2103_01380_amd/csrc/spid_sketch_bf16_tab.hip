@@ -1,7 +1,8 @@
 // spid_sketch_bf16_tab.hip -- bfloat16 sketch launches with Omega shared by
 // all blocks (Section 2): the sketch matrix is regenerated once per update as a
 // table in MFMA operand order and read by the batch and one-snapshot kernels;
-// the launch of the tables (bfloat16, and e4m3 for the FP8 one-snapshot kernel).
+// the launch of every Omega table (double, bfloat16, and e4m3 for the FP8
+// one-snapshot kernel).
 #include "spid_sketch_launch.h"
 
 namespace spid_host {
@@ -13,6 +14,9 @@ bool launch_omega_table(spid_ctx* c, hipStream_t s) {
   if (c->desc.prec == SPID_SK_BF16)
     hipLaunchKernelGGL((omega_table_kernel<0>), grid, dim3(256), 0, s, c->desc.l, p.sh.MT,
                        p.omtab_cols, c->desc.seed, c->at<__bf16>(p.off_omtab));
+  else if (c->desc.prec == SPID_SK_F64)
+    hipLaunchKernelGGL((omega_table_f64_kernel<double>), grid, dim3(256), 0, s, c->desc.l, p.sh.MT,
+                       p.omtab_cols, c->desc.seed, c->at<double>(p.off_omtab));
   else
     hipLaunchKernelGGL((omega_table_e4m3_kernel<uint8_t>), grid, dim3(256), 0, s, c->desc.l,
                        p.sh.MT, p.omtab_cols, c->desc.seed, c->at<uint8_t>(p.off_omtab));

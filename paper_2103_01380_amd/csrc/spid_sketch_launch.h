@@ -25,8 +25,9 @@ void launch_sketch_k(spid_ctx* c, int j0, int j1, int jst, hipStream_t s) {
     if constexpr (TN == 1 || (TN == 2 && MT <= 4))
       hipLaunchKernelGGL((sketch_f64_kernel<TA, MT, TN, NW, VEC, ST>), grid, block, 0, s,
                          c->at<BlkInfo>(p.off_blk), items, c->desc.l, c->desc.seed,
-                         c->desc.omega_per_block, j0, j1, perm, jst, c->at<double>(p.off_Y),
-                         c->at<double>(p.off_part));
+                         c->desc.omega_per_block, j0, j1, perm, jst,
+                         p.omtab_cols > 0 ? c->at<double>(p.off_omtab) : nullptr,
+                         c->at<double>(p.off_Y), c->at<double>(p.off_part));
   } else if constexpr (PR == kPrFP8) {
     if constexpr (TN == 1)
       hipLaunchKernelGGL((sketch_fp8_kernel<TA, MT, TN, NW, VEC, ST>), grid, block, 0, s,
