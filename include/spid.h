@@ -247,7 +247,8 @@ spid_status spid_coeffs(spid_ctx* ctx, double* d_P, void* stream);
  * d_P as written by spid_coeffs (ESTATE unless spid_coeffs ran after the last
  * spid_select).  With FP32 data and a BF16/FP8 sketch the error pass reads
  * the split-bfloat16 copy of the same P that spid_coeffs keeps in the
- * workspace.  d_skeleton (nullable) receives A_b(:,S_b),
+ * workspace, and sums the squares of 16 entries per lane in FP32 before the
+ * FP64 sums (relative error of those partial sums at most 16 * 2^-24).  d_skeleton (nullable) receives A_b(:,S_b),
  * m_b x k_max column-major in the A dtype at element offset
  * k_max * sum_{c<b} m_c (columns >= k_b untouched).  Sums are deterministic
  * (fixed reduction order).  ESTATE before spid_coeffs. */

@@ -2015,9 +2015,10 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
 // six term products of weight at least 2^-16 (hi*hi, hi*mid, mid*hi, hi*lo,
 // mid*mid, lo*hi), largest first, so it ends at the residual
 // A(rows, j) - A(rows, S) P(:, j) with every rounding at the size of what is
-// left.  Squared residuals are summed in FP32 over one step (16 per lane,
-// relative error at most 16 * 2^-24) and the step sums in FP64; |A|^2 in
-// FP64 throughout.  KS32 = k-steps of 32 selected columns.
+// left.  Squared residuals and squared entries of the non-skeleton columns
+// are summed in FP32 over one step (16 per lane, relative error at most
+// 16 * 2^-24) and the step sums in FP64 (the skeleton columns' entries in
+// FP64).  KS32 = k-steps of 32 selected columns.
 //
 // A work item is 128 rows (4 waves x 32) of one block; a wave's skeleton
 // terms (its 32 rows of A(:, S)) stay in registers.  The non-skeleton columns
@@ -2071,6 +2072,13 @@ void recon_bf16x3_kernel(
   const __bf16* __restrict__ ptb = pt_g + col_off * 3 * KP;
   const int32_t* __restrict__ colb = cols_g + col_off;
   const int64_t rbase = it.i0 + wave_u * 16 * MTR;   // the wave's 32 rows
+  // the lane's LDS tile offsets: its two line pieces (columns 8h + lane / 8),
+  // and its operand pieces (rows 16 mt + 4g.., column c16)
+  int st_w[2], st_r[MTR];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) st_w[h] = (int)(line_piece(st, 8 * h + (lane >> 3), p8) - st);
+#pragma unroll
+  for (int mt = 0; mt < MTR; ++mt) st_r[mt] = (int)(line_piece(st, c16, 4 * mt + g) - st);
 
   // A operand: tile row c16, selected columns 32 ks + 8 g + v, three terms (k-steps past
   // ksn are never read)
@@ -2146,23 +2154,24 @@ void recon_bf16x3_kernel(
     auto step = [&](const float (&x)[2][2][4], float (&xn)[2][2][4], int s) {
       if ((32 * s) % kCols == 0) stage_p(32 * s);
       load(min(s + 1, nst - 1), xn);
-      float es = 0.0f;   // the step's squared residuals
+      float es = 0.0f, as = 0.0f;   // the step's squared residuals and squared entries
       // one 16-column group; MASK: some of its columns lie past ncols (the
       // block's last group only)
       auto group = [&](auto mask_c, const float (&xg)[2][4], int q0) {
         constexpr bool kMask = decltype(mask_c)::value;
         const bool cok = q0 + c16 < ncols;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) stage_line<float>(st, 8 * h + (lane >> 3), p8, xg[h]);
+        for (int h = 0; h < 2; ++h)
+          *reinterpret_cast<f32x4*>(st + st_w[h]) = f32x4{xg[h][0], xg[h][1], xg[h][2], xg[h][3]};
         f32x4 acc[MTR];   // A(rows, j), then the residual
 #pragma unroll
         for (int mt = 0; mt < MTR; ++mt) {
-          const f32x4 v = *reinterpret_cast<const f32x4*>(line_piece(st, c16, 4 * mt + g));
+          const f32x4 v = *reinterpret_cast<const f32x4*>(st + st_r[mt]);
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const float a = (!kMask || cok) ? v[e] : 0.0f;
             acc[mt][e] = a;
-            a2 += (double)a * (double)a;
+            as = __builtin_fmaf(a, a, as);
           }
         }
         const int qp = q0 % kCols + c16;           // column within the staged chunk
@@ -2196,6 +2205,7 @@ void recon_bf16x3_kernel(
         else group(std::true_type{}, x[gq], q0);
       }
       e2 += (double)es;
+      a2 += (double)as;
     };
     float xa[2][2][4], xb[2][2][4];
     load(0, xa);
