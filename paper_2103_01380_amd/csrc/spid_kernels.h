@@ -97,6 +97,18 @@ __device__ __forceinline__ void load_pieces_full(gptr<TA> __restrict__ cb, int64
       const f32x2 v = __builtin_nontemporal_load((gptr<f32x2>)p);
       out[2 * pc] = ok ? (TO)v[0] : (TO)0;
       out[2 * pc + 1] = ok ? (TO)v[1] : (TO)0;
+    } else if constexpr (sizeof(TA) == 4 && W == 4) {
+      // element-aligned vector load through the caches (see load_line)
+      const f32x4u v = *(gptr<f32x4u>)p;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[W * pc + e] = ok ? (TO)v[e] : (TO)0;
+    } else if constexpr (sizeof(TA) == 8 && W % 2 == 0) {
+#pragma unroll
+      for (int h = 0; h < W / 2; ++h) {
+        const f64x2u v = *((gptr<f64x2u>)p + h);
+        out[W * pc + 2 * h] = ok ? (TO)v[0] : (TO)0;
+        out[W * pc + 2 * h + 1] = ok ? (TO)v[1] : (TO)0;
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < W; ++e) {
@@ -473,14 +485,20 @@ __device__ __forceinline__ void sk_lines_stream(const BlkInfo* __restrict__ blks
 template <typename TA, bool VEC>
 __device__ __forceinline__ void load_line(gptr<TA> __restrict__ cb, int64_t row, int p,
                                           float (&x)[4]) {
+  // VEC: 16-byte aligned column starts, streaming (non-temporal) loads.
+  // Otherwise element-aligned vector loads through the caches: a chunk of a
+  // column that does not start on a 128-byte line shares its first and last
+  // lines with the neighbouring chunks, which then hit in L2 instead of being
+  // fetched twice.
   if constexpr (sizeof(TA) == 4) {
     if constexpr (VEC) {
       const f32x4 v = __builtin_nontemporal_load((gptr<f32x4>)(cb + row + 4 * p));
 #pragma unroll
       for (int e = 0; e < 4; ++e) x[e] = v[e];
     } else {
+      const f32x4u v = *(gptr<f32x4u>)(cb + row + 4 * p);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) x[e] = __builtin_nontemporal_load(cb + row + 4 * p + e);
+      for (int e = 0; e < 4; ++e) x[e] = v[e];
     }
   } else {
     if constexpr (VEC) {
@@ -491,9 +509,12 @@ __device__ __forceinline__ void load_line(gptr<TA> __restrict__ cb, int64_t row,
       x[2] = (float)v1[0];
       x[3] = (float)v1[1];
     } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        x[e] = (float)__builtin_nontemporal_load(cb + row + 16 * (e >> 1) + 2 * p + (e & 1));
+      const f64x2u v0 = *(gptr<f64x2u>)(cb + row + 2 * p);
+      const f64x2u v1 = *(gptr<f64x2u>)(cb + row + 16 + 2 * p);
+      x[0] = (float)v0[0];
+      x[1] = (float)v0[1];
+      x[2] = (float)v1[0];
+      x[3] = (float)v1[1];
     }
   }
 }
