@@ -135,7 +135,9 @@ typedef struct {
  * sketch column (K splits), so every choice meets the same parity rules.
  *   sk_tn    16-column MFMA tiles per wave in the sketch: 1, 2 or 4
  *            (FP64: 1 or 2, and 2 only for l <= 64; BF16: 4 only for
- *            l <= 80; FP8: 1)
+ *            l <= 80; FP8: 1).  BF16 default (0, 8 waves): each block's
+ *            tiles sized to its width (1 per wave up to 128 columns, 2 up to
+ *            256, else 4), one launch per size; spid_get_tuning reports 0
  *   sk_nw    waves per sketch workgroup: 8, or 4 with sk_tn = 1
  *   sk_items target number of sketch work items (64..65536): blocks are
  *            split along their rows (K) until about this many items exist

@@ -405,8 +405,6 @@ class SPID:
         o, nb = int(self.p_off[b]), int(self.n[b])
         return self.P[o:o + self.k_max * nb].cpu().numpy().reshape(nb, self.k_max).T
 
-    def rel_error(self) -> float:
-        return float((self.err2.sum() / self.nrm2.sum()).sqrt())
 
     def close(self):
         if self.ctx is not None:

@@ -49,6 +49,8 @@ def sketch_candidates(prec: str, l: int, max_n: int):
     else:
         tns = [1]
     shapes = [(tn, 8) for tn in tns if 16 * 8 * tn <= max(128, 2 * max_n)] + [(1, 4)]
+    if prec == "bf16":
+        shapes = [(0, 8)] + shapes   # tiles sized per block (the library's default)
     out = []
     for tn, nw in shapes:
         for items in (1024, 2048, 4096, 8192):

@@ -202,7 +202,19 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     }
   }
 
-  // sketch work items: column tiles x K splits
+  // sketch work items: column tiles x K splits.  BF16 with the default shape:
+  // each block's tile is as narrow as its width allows (TN = 1, 2 or 4 tiles of
+  // 16 columns per wave), so narrow blocks of an uneven batch do not run
+  // mostly-empty tiles; otherwise every block uses sh.TN.
+  const bool tn_by_block = p.ydt == 1 && d->prec == SPID_SK_BF16 && !(tune && tune->sk_tn) &&
+                           sh.NW == 8;
+  sh.tn_by_block = tn_by_block ? 1 : 0;
+  auto tn_of = [&](int32_t nb_cols) {
+    if (!tn_by_block) return sh.TN;
+    int t = nb_cols <= 16 * sh.NW ? 1 : (nb_cols <= 32 * sh.NW ? 2 : 4);
+    if (t == 4 && sh.MT >= 6) t = 2;
+    return t;
+  };
   const int tile_cols = 16 * sh.NW * sh.TN;
   // Cost-balanced K splits: an item's cost ~ rows x columns it streams.  A
   // block is split along K when its column tiles exceed the target item cost
@@ -218,7 +230,8 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
   for (int b = 0; b < nb; ++b) {
     const int64_t m = d->h_m[b];
     const int32_t n = d->h_n[b];
-    const double tile_cost = (double)m * std::min(n, tile_cols);
+    const int tcols = 16 * sh.NW * tn_of(n);
+    const double tile_cost = (double)m * std::min(n, tcols);
     int nsplit = (int)std::ceil(tile_cost / target_cost);
     nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(nsplit, m / min_rows));
     if (p.coarse) nsplit = 1;
@@ -248,7 +261,7 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
       p.split_blocks.push_back(b);
       p.max_split_n = std::max(p.max_split_n, (int)n);
     }
-    for (int c0 = 0; c0 < n && !p.coarse; c0 += tile_cols)
+    for (int c0 = 0; c0 < n && !p.coarse; c0 += tcols)
       for (int s = 0; s < nsplit; ++s) {
         SkItem it{};
         it.blk = b;
@@ -441,11 +454,27 @@ spid_status make_plan(const spid_desc* d, const spid_tuning* tune, Plan& p) {
     }
   }
   // longest items first (the hardware dispatches workgroups in grid order)
-  std::stable_sort(p.items.begin(), p.items.end(), [&](const SkItem& a, const SkItem& b2) {
-    const int64_t ca = (a.r1 - a.r0) * std::min<int64_t>(tile_cols, d->h_n[a.blk] - a.c0);
-    const int64_t cb = (b2.r1 - b2.r0) * std::min<int64_t>(tile_cols, d->h_n[b2.blk] - b2.c0);
-    return ca > cb;
-  });
+  // grouped by TN (1, 2, 4), within a group longest items first (the hardware
+  // dispatches workgroups in grid order)
+  {
+    auto tn_index = [&](const SkItem& it) {
+      const int t = tn_of(d->h_n[it.blk]);
+      return t == 1 ? 0 : (t == 2 ? 1 : 2);
+    };
+    auto cost = [&](const SkItem& it) {
+      return (it.r1 - it.r0) *
+             std::min<int64_t>(16 * sh.NW * tn_of(d->h_n[it.blk]), d->h_n[it.blk] - it.c0);
+    };
+    std::stable_sort(p.items.begin(), p.items.end(), [&](const SkItem& a, const SkItem& b2) {
+      const int ta = tn_index(a), tb = tn_index(b2);
+      if (ta != tb) return ta < tb;
+      return cost(a) > cost(b2);
+    });
+    int64_t cnt[3] = {0, 0, 0};
+    for (const SkItem& it : p.items) ++cnt[tn_index(it)];
+    p.tn_start[0] = 0;
+    for (int i = 0; i < 3; ++i) p.tn_start[i + 1] = p.tn_start[i] + cnt[i];
+  }
   const size_t ysz = p.ydt == 0 ? 8 : 4;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -587,7 +616,7 @@ extern "C" spid_status spid_create(const spid_desc* desc, void* d_workspace, siz
 extern "C" spid_status spid_get_tuning(const spid_ctx* c, spid_tuning* out) {
   if (!c || !out) return fail(SPID_EINVAL, "NULL argument to spid_get_tuning");
   const Shape& sh = c->plan.sh;
-  out->sk_tn = sh.TN;
+  out->sk_tn = sh.tn_by_block ? 0 : sh.TN;
   out->sk_nw = sh.NW;
   out->sk_items = sh.sk_items;
   out->rc_rpi = sh.rc_bf16 ? 1 : sh.RPI;

@@ -65,6 +65,7 @@ struct Shape {
   int KS32;      // k-steps of 32 selected columns in the split-bfloat16 error pass
   int sk_items;  // target number of sketch work items
   int st_groups = 0;  // one-snapshot FP8 updates: block groups per work item
+  int tn_by_block = 0;  // 1: BF16 batch sketch tiles sized per block (TN 1, 2, 4)
 };
 
 inline int pick_mt(int l) {
@@ -127,6 +128,11 @@ struct Plan {
   int ydt;                       // 0: Y in FP64, 1: Y in FP32
   std::vector<BlkInfo> blk;
   std::vector<SkItem> items;
+  // batch sketch items grouped by column tiles per wave: items
+  // [tn_start[i], tn_start[i+1]) run with TN = 1, 2, 4 (i = 0, 1, 2); one launch
+  // per non-empty group.  BF16 sketches by default size TN to each block's
+  // width; otherwise every item is in the group of sh.TN.
+  int64_t tn_start[4] = {0, 0, 0, 0};
   std::vector<int32_t> split_blocks;
   std::vector<RcItem> rc;
   std::vector<int64_t> rc_first;

@@ -12,11 +12,13 @@ constexpr int kPrF64 = 0, kPrBF16 = 1, kPrFP8 = 2;
 
 // ST: one-snapshot update of snapshot jst over the block groups; TAB: the
 // bfloat16 kernel reads Omega from the per-update table (shared Omega only)
+// batch: items [i0, i0 + ni) of the batch table (one TN group)
 template <int PR, typename TA, int MT, int TN, int NW, bool VEC, bool ST, bool TAB>
-void launch_sketch_k(spid_ctx* c, int j0, int j1, int jst, hipStream_t s) {
+void launch_sketch_k(spid_ctx* c, int j0, int j1, int jst, hipStream_t s, int64_t i0 = 0,
+                     int64_t ni = 0) {
   const Plan& p = c->plan;
-  const size_t nitems = ST ? p.sitems.size() : p.items.size();
-  const SkItem* items = c->at<SkItem>(ST ? p.off_sitems : p.off_items);
+  const size_t nitems = ST ? p.sitems.size() : (size_t)ni;
+  const SkItem* items = c->at<SkItem>(ST ? p.off_sitems : p.off_items) + (ST ? 0 : i0);
   const int32_t* perm = c->at<int32_t>(p.off_perm);
   dim3 grid((unsigned)nitems), block(64 * NW);
   // shapes the planner can choose (others are not instantiated): FP64 TN <= 2
@@ -46,26 +48,26 @@ void launch_sketch_k(spid_ctx* c, int j0, int j1, int jst, hipStream_t s) {
 
 // instantiated (TN, NW) pairs: 8 waves x 1-4 tiles or 4 waves x 1 tile
 template <int PR, bool TAB, typename TA, int MT, int TN>
-void launch_sketch_t(spid_ctx* c, int j0, int j1, hipStream_t s) {
+void launch_sketch_t(spid_ctx* c, int j0, int j1, hipStream_t s, int64_t i0, int64_t ni) {
   const bool vec = c->all_vec;
   if (c->plan.sh.NW == 8) {
-    if (vec) launch_sketch_k<PR, TA, MT, TN, 8, true, false, TAB>(c, j0, j1, 0, s);
-    else launch_sketch_k<PR, TA, MT, TN, 8, false, false, TAB>(c, j0, j1, 0, s);
+    if (vec) launch_sketch_k<PR, TA, MT, TN, 8, true, false, TAB>(c, j0, j1, 0, s, i0, ni);
+    else launch_sketch_k<PR, TA, MT, TN, 8, false, false, TAB>(c, j0, j1, 0, s, i0, ni);
   } else {
     if constexpr (TN == 1) {
-      if (vec) launch_sketch_k<PR, TA, MT, 1, 4, true, false, TAB>(c, j0, j1, 0, s);
-      else launch_sketch_k<PR, TA, MT, 1, 4, false, false, TAB>(c, j0, j1, 0, s);
+      if (vec) launch_sketch_k<PR, TA, MT, 1, 4, true, false, TAB>(c, j0, j1, 0, s, i0, ni);
+      else launch_sketch_k<PR, TA, MT, 1, 4, false, false, TAB>(c, j0, j1, 0, s, i0, ni);
     }
   }
 }
 
+// one launch per non-empty TN group of the batch items (widest tiles first)
 template <int PR, bool TAB, typename TA, int MT>
 void launch_sketch_mt(spid_ctx* c, int j0, int j1, hipStream_t s) {
-  switch (c->plan.sh.TN) {
-    case 1: launch_sketch_t<PR, TAB, TA, MT, 1>(c, j0, j1, s); break;
-    case 2: launch_sketch_t<PR, TAB, TA, MT, 2>(c, j0, j1, s); break;
-    default: launch_sketch_t<PR, TAB, TA, MT, 4>(c, j0, j1, s); break;
-  }
+  const int64_t* ts = c->plan.tn_start;
+  if (ts[3] > ts[2]) launch_sketch_t<PR, TAB, TA, MT, 4>(c, j0, j1, s, ts[2], ts[3] - ts[2]);
+  if (ts[2] > ts[1]) launch_sketch_t<PR, TAB, TA, MT, 2>(c, j0, j1, s, ts[1], ts[2] - ts[1]);
+  if (ts[1] > ts[0]) launch_sketch_t<PR, TAB, TA, MT, 1>(c, j0, j1, s, ts[0], ts[1] - ts[0]);
 }
 
 template <int PR, bool TAB, typename TA>

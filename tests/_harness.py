@@ -38,9 +38,12 @@ class GpuResult:
 
 def gpu_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=False,
             prec="f64", lp_terms=1, skeleton=False, stream_columns=False, lda_pad=0,
-            grids=None, tuning=None):
+            grids=None, tuning=None, graph_replays=0):
     """Run the four stages on the GPU for host column-major blocks.  ``grids``: the
-    coarse-grid sketch (SubID) plus the single-pass error and coarse skeleton."""
+    coarse-grid sketch (SubID) plus the single-pass error and coarse skeleton.
+    ``graph_replays``: after the eager run, capture the four stages into one HIP
+    graph and replay it that many times (eager work between the replays),
+    asserting every replay equal to the eager results bit for bit."""
     import paper_2103_01380_amd as sp
     dt = blocks[0].dtype
     a_dtype = "f64" if dt == np.float64 else "f32"
@@ -74,6 +77,27 @@ def gpu_run(blocks, l, k_max, seed, tol=0.0, rank_floor=0.0, omega_per_block=Fal
     if skeleton:
         skel_t = torch.full((int((m * k_max).sum()),), float("nan"), dtype=A.dtype, device=A.device)
     ctx.reconstruct(skeleton=skel_t)
+    if graph_replays:
+        torch.cuda.synchronize()
+        outs = (ctx.S, ctx.k, ctx.status, ctx.P, ctx.err2, ctx.nrm2)
+        ref = [t.clone() for t in outs]
+        ref_y = ctx.sketch()
+        graph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(graph, stream=cap):
+                ctx.run(cap)
+        torch.cuda.current_stream().wait_stream(cap)
+        torch.cuda.synchronize()
+        for rep in range(graph_replays):
+            for t in outs:
+                t.fill_(7)                      # eager work between replays
+            graph.replay()
+            torch.cuda.synchronize()
+            for a, b in zip(outs, ref):
+                assert torch.equal(a, b), rep
+            assert torch.equal(ctx.sketch(), ref_y), rep
     cs_t = None
     if grids is not None:
         mc = ctx.mc

@@ -121,3 +121,46 @@ def test_graph_two_stage():
 
     _capture_and_check(ctx, step, (ctx.S, ctx.k, ctx.P, ctx.err2, ctx.nrm2))
     ctx.close()
+
+
+def test_graph_uneven_batch_matches_oracle():
+    """A ragged batch shaped like the uneven workload (edges log-uniform in [4, 16]:
+    m_b = 5 e^3 from 320 to 20480 rows, mostly not multiples of 4; n_b log-uniform in
+    [40, 300]; low rank with decaying singular values, FP32), BF16 sketch with a
+    tolerance: the four stages captured into one graph replay the eager results bit
+    for bit, and the eager results pass the mixed-precision gates against the oracle
+    (pivot prefix by the 1e-3 gap rule, sketch to the split-term rounding, R2 and the
+    error of the factors)."""
+    import math
+    from _harness import gpu_run, matched_prefix, oracle_run
+    rng = np.random.default_rng(33)
+    blocks = []
+    for b in range(40):
+        e = int(round(math.exp(rng.uniform(math.log(4), math.log(16)))))
+        m = 5 * e ** 3
+        n = int(round(math.exp(rng.uniform(math.log(40), math.log(300)))))
+        r = int(rng.integers(2, 16))
+        U = rng.standard_normal((m, r))
+        V = rng.standard_normal((n, r)) * 10.0 ** (-0.25 * np.arange(r))
+        blocks.append(np.asfortranarray((U @ V.T + 1e-7 * rng.standard_normal((m, n))).astype(np.float32)))
+    print("case: graph uneven", [b.shape for b in blocks[:4]], flush=True)
+    g = gpu_run(blocks, 30, 20, 17, tol=1e-4, prec="bf16", lp_terms=2, graph_replays=3)
+    o = oracle_run(blocks, 30, 20, 17, tol=1e-4, prec="bf16")
+    num = den = rd = 0.0
+    for b, A in enumerate(blocks):
+        Ad = A.astype(np.float64)
+        scale = np.linalg.norm(o.Y[b], axis=0).max()
+        assert np.abs(g.Y[b] - o.Y[b]).max() <= 2e-6 * scale, b
+        s_star, ok = matched_prefix(g.S[b], o.S[b], o.gaps[b], g.k[b], o.k[b], 1e-3)
+        assert ok, (b, s_star)
+        kg, ko = int(g.k[b]), int(o.k[b])
+        ag = Ad[:, g.S[b][:kg]] @ g.P[b][:kg]
+        ao = Ad[:, o.S[b][:ko]] @ o.P[b][:ko]
+        e_direct = ((Ad - ag) ** 2).sum()
+        a_norm = math.sqrt((Ad ** 2).sum())
+        assert abs(g.err2[b] - e_direct) <= 5e-8 * math.sqrt(e_direct) * a_norm + \
+            1e-6 * e_direct + 1e-13 * a_norm ** 2, b
+        num += e_direct
+        rd += ((ag - ao) ** 2).sum()
+        den += (Ad ** 2).sum()
+    assert math.sqrt(num / den) <= 1e-3 and math.sqrt(rd / den) <= 1e-3
