@@ -281,9 +281,9 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 template <int CTRL>
 __device__ __forceinline__ void argmax_dpp_level(double& v, int& idx) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-  const int oi = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+  const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xf, 0xf, true);
   const double ov = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
                                                      (unsigned)lo));
   const bool take = (ov > v) | ((ov == v) & (oi < idx));

@@ -1218,8 +1218,16 @@ __global__ __launch_bounds__(256) void sketch_stream_reduce_kernel(
 // barrier per step suffices.  The pivot column is used unscaled:
 // R(s, j) = <w_p, w_j> / r_ss and w_j -= (R(s, j) / r_ss) w_p, the modified
 // Gram-Schmidt step of Algorithm 1 with q = w_p / r_ss folded into two
-// products with 1 / r_ss (r_ss^2 is the pivot's residual norm^2, computed as
-// every norm).  Norms are recomputed after every update.  The tolerance test
+// products with 1 / r_ss, where r_ss^2 is the pivot's residual norm^2 summed
+// by its group from its rows as they are published (the same sum as a
+// recomputed norm; it is also the value the waves' candidates are compared
+// by).  The other residual norms are downdated, nu_j -= R(s, j)^2, as in the pivoted QR of
+// Golub and Van Loan, and recomputed from the column when the downdated value
+// falls below kNormRecompute of the last computed one; the downdate then errs
+// by at most a few hundred units of rounding of that larger value, so the
+// pivot choice can differ from one with norms recomputed every step only
+// where two candidates' norms agree to about 1e-12 of the largest.  The
+// tolerance test
 // after step s (Remark 2.1) runs at the start of step s + 1 on per-wave sums of
 // the live residual norms published with the candidates (after the last step,
 // in one more round), so it ends the selection at the same step.
@@ -1229,9 +1237,11 @@ __global__ __launch_bounds__(256) void sketch_stream_reduce_kernel(
 // addition is commutative)
 template <int CTRL>
 __device__ __forceinline__ double dpp_add(double v) {
+  // every pattern used reads a lane of the same row, so no lane is out of
+  // bounds and the moves need no initial value
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
   return v + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
                                               (unsigned)lo));
 }
@@ -1253,6 +1263,8 @@ __device__ __forceinline__ double readfirstlane_f64(double v) {
                                           (unsigned)lo));
 }
 
+constexpr double kNormRecompute = 1e-3;
+
 template <typename TY, int RPT, int LPC, int CPL, int MAXTHR>
 __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
     const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor,
@@ -1269,7 +1281,8 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
   const BlkInfo bi = blks[b];
   const int n = bi.n;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int lane = tid & 63, nwaves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: LDS slot addresses in scalars
   const int h = tid % LPC;                 // row slice of the lane
   const int j0 = (tid / LPC) * CPL;        // first column of the lane's group
   const int r0 = h * RPT;
@@ -1277,7 +1290,11 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
   double* __restrict__ Rb = R + bi.r_off;
 
   double w[CPL][RPT];
-  double nu[CPL];
+  double nu[CPL];    // residual norm^2 (downdated)
+  // last computed residual norm^2 of each column (only compared with), in LDS
+  // by group: it is read once per step
+  __shared__ __attribute__((aligned(16))) float nref_s[MAXTHR / LPC][CPL];
+  float* __restrict__ nref = nref_s[tid / LPC];
   bool live[CPL];
   int bad = 0;
 #pragma unroll
@@ -1296,6 +1313,7 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
     }
     nu[c] = group_sum<LPC>(s0 + s1);
     nu[c] = live[c] ? nu[c] : 0.0;
+    if (h == 0) nref[c] = (float)nu[c];
   }
   // candidate entries of waves that do not exist never win and add nothing
   for (int e = tid; e < 2 * NWMAX; e += blockDim.x) {
@@ -1326,6 +1344,11 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
     F2 += cand_r[1][v];
     nu0max = fmax(nu0max, cand_v[1][v]);
   }
+  // equal on every lane: held in scalar registers through the steps
+  F2 = readfirstlane_f64(F2);
+  nu0max = readfirstlane_f64(nu0max);
+  const double tol_f = readfirstlane_f64(tol * sqrt(F2));
+  const double floor2 = readfirstlane_f64(rank_floor * rank_floor * nu0max);
 
   int kcap = k_max;
   if (kcap > l) kcap = l;
@@ -1359,21 +1382,34 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
       double rw = 0.0;
       if (tol > 0.0 && s > 0) rw = live_sum();
       if ((my_j == bj) & (bj != 0x7fffffff)) {
-        // the lanes of the wave's winning column publish their rows of it
+        // the lanes of the wave's winning column publish their rows of it;
+        // they form one group, so its slot in the group is uniform
+        // and its residual norm^2 summed from those rows, which replaces the
+        // downdated value as the candidate's
+        const int bcu = __builtin_amdgcn_readfirstlane(bc);
+        double e0 = 0.0, e1 = 0.0;
 #pragma unroll
-        for (int i = 0; i < RPT; i += 2) {
-          double x0 = w[0][i], x1 = w[0][i + 1];
+        for (int c = 0; c < CPL; ++c) {
+          if (c != bcu) continue;
 #pragma unroll
-          for (int c = 1; c < CPL; ++c) {
-            x0 = bc == c ? w[c][i] : x0;
-            x1 = bc == c ? w[c][i + 1] : x1;
+          for (int i = 0; i < RPT; i += 2) {
+            *reinterpret_cast<f64x2*>(&slot[buf][wave][r0 + i]) = f64x2{w[c][i], w[c][i + 1]};
+            e0 += w[c][i] * w[c][i];
+            e1 += w[c][i + 1] * w[c][i + 1];
           }
-          *reinterpret_cast<f64x2*>(&slot[buf][wave][r0 + i]) = f64x2{x0, x1};
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        const double pn = group_sum<LPC>(e0 + e1);
+        if (h == 0) {
+          cand_v[buf][wave] = pn;
+          cand_i[buf][wave] = bj;
         }
       }
       if (lane == 0) {
-        cand_v[buf][wave] = bv;
-        cand_i[buf][wave] = bj;
+        if (bj == 0x7fffffff) {   // no live column in the wave
+          cand_v[buf][wave] = -1.0;
+          cand_i[buf][wave] = bj;
+        }
         cand_r[buf][wave] = rw;
       }
       // orders LDS only: the R stores of the previous step stay in flight
@@ -1384,8 +1420,12 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
       double best;
       int p;
       {
-        double cv = lane < NWMAX ? cand_v[buf][lane] : -1.0;
-        int ci = lane < NWMAX ? cand_i[buf][lane] : 0x7fffffff;
+        // the lane index is recomputed from an opaque copy every step, so
+        // the candidate addresses are not held (or spilled) across the steps
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        double cv = ln < NWMAX ? cand_v[buf][ln] : -1.0;
+        int ci = ln < NWMAX ? cand_i[buf][ln] : 0x7fffffff;
         argmax_dpp_level<0xB1>(cv, ci);
         argmax_dpp_level<0x4E>(cv, ci);
         argmax_dpp_level<0x141>(cv, ci);
@@ -1394,15 +1434,17 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
         p = __builtin_amdgcn_readfirstlane(ci);
       }
       if (tol > 0.0 && s > 0) {
-        double cr = lane < NWMAX ? cand_r[buf][lane] : 0.0;
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        double cr = ln < NWMAX ? cand_r[buf][ln] : 0.0;
         cr = group_sum<16>(cr);
-        if (sqrt(readfirstlane_f64(cr)) <= tol * sqrt(F2)) break;
+        if (sqrt(readfirstlane_f64(cr)) <= tol_f) break;
       }
       if (!(best > 0.0)) {
         status = 1;   // SPID_BLOCK_RANK_DEFICIENT
         break;
       }
-      if (rank_floor > 0.0 && best <= rank_floor * rank_floor * nu0max) {
+      if (rank_floor > 0.0 && best <= floor2) {
         status = 1;
         break;
       }
@@ -1429,7 +1471,10 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
         q[i] = qa[0];
         q[i + 1] = qa[1];
       }
-      double coef[CPL];
+      // per column: its product with the pivot, R(s, j), the update and the
+      // downdated norm (one column at a time: bounded registers)
+      bool need[CPL];
+      bool any_need = false;
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
         double d0 = 0.0, d1 = 0.0;
@@ -1440,22 +1485,31 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
         }
         const double d = live[c] ? group_sum<LPC>(d0 + d1) * inv_rss : 0.0;
         if (live[c] && h == 0) Rb[(int64_t)s * n + j0 + c] = d;
-        coef[c] = d * inv_rss;
-        __builtin_amdgcn_sched_barrier(0);   // one column at a time: bounded registers
-      }
+        const double coef = d * inv_rss;
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPT; i += 2) {
-          w[c][i] -= coef[c] * q[i];
-          w[c][i + 1] -= coef[c] * q[i + 1];
-          a0 += w[c][i] * w[c][i];
-          a1 += w[c][i + 1] * w[c][i + 1];
-        }
-        const double np = group_sum<LPC>(a0 + a1);
-        nu[c] = live[c] ? np : 0.0;
+        for (int i = 0; i < RPT; ++i) w[c][i] -= coef * q[i];
+        // group-uniform: nu, nref and d are equal on the group's lanes
+        const double nd = nu[c] - d * d;
+        need[c] = live[c] && nd < kNormRecompute * (double)nref[c];
+        any_need |= need[c];
+        nu[c] = live[c] ? nd : 0.0;
         __builtin_amdgcn_sched_barrier(0);
+      }
+      // recomputation, skipped by the whole wave when no column needs it
+      if (__builtin_amdgcn_ballot_w64(any_need) != 0) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+          for (int i = 0; i < RPT; i += 2) {
+            a0 += w[c][i] * w[c][i];
+            a1 += w[c][i + 1] * w[c][i + 1];
+          }
+          const double np = group_sum<LPC>(a0 + a1);
+          nu[c] = need[c] ? np : nu[c];
+          if (need[c] && h == 0) nref[c] = (float)np;
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
     ran_out = s == kcap;
@@ -1468,7 +1522,7 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
     lds_barrier();
     double tot = 0.0;
     for (int v = 0; v < nwaves; ++v) tot += cand_r[buf][v];
-    if (!(sqrt(tot) <= tol * sqrt(F2))) status = 3;   // SPID_BLOCK_TOL_NOT_MET
+    if (!(sqrt(tot) <= tol_f)) status = 3;   // SPID_BLOCK_TOL_NOT_MET
   }
   if (tid == 0) {
     k_ws[b] = taken;
@@ -1661,19 +1715,21 @@ static __global__ void select_export_kernel(int nblocks, int k_max, const int32_
 
 // ---------------------------------------------------------------------------
 // Coefficients: P_b(:, S[t]) = e_t, and for every other column j the
-// back-substitution R11 x = R12(:, j) (Section 2, Algorithm 1), FP64, done in
-// row blocks of 16.  One workgroup of kCoThreads per block: the non-skeleton
-// columns are listed in ascending order in LDS (the order the error pass
-// uses) and R11 is staged in LDS, padded to KB * 16 rows and columns with the
-// identity past k (the padded unknowns come out as exact zeros and add exact
-// zeros to the real rows).  A wave takes 16 non-skeleton columns at a time,
-// their right-hand sides R12(:, j) held as KB accumulator tiles of the FP64
-// matrix cores (16 rows each).  From the last row block up, the 16 x 16
-// diagonal system is solved by back-substitution, one lane per column through
-// a transpose in LDS (x_s = (b_s - sum_{t > s} R11(s, t) x_t) / R11(s, s), t
-// ascending within the block), and the solved block is taken off every row
-// block above by MFMA products with R11: the arithmetic of the row-by-row
-// back-substitution, the sum over t in blocks.  When `pt` is given (mixed
+// solution of R11 x = R12(:, j) (Section 2, Algorithm 1), FP64, by block
+// back-substitution in row blocks of 16.  One workgroup of kCoThreads per
+// block: the non-skeleton columns are listed in ascending order in LDS (the
+// order the error pass uses) and R11 is staged in LDS, padded to KB * 16 rows
+// and columns with the identity past k (the padded unknowns come out as exact
+// zeros and add exact zeros to the real rows).  The inverse of each 16 x 16
+// diagonal block of R11 is formed once per workgroup (back-substitution on
+// the unit vectors, one lane per column).  A wave takes 16 non-skeleton
+// columns at a time, their right-hand sides R12(:, j) held as KB accumulator
+// tiles of the FP64 matrix cores (16 rows each); from the last row block up,
+// the block's unknowns are its inverse times its right-hand side and are
+// taken off every row block above by products with R11, both on the matrix
+// cores.  Its error is that of a triangular solve, at most a small multiple
+// of the unit roundoff times the condition number of R11 (a diagonal block's
+// condition number is at most that of R11).  When `pt` is given (mixed
 // error pass on FP32 data) the wave also writes the three bfloat16 terms
 // (hi, mid, lo: 24 significant bits) of its columns' negated coefficients and
 // the compact column list, so the error pass stages them by plain copies.  Layouts: cols[col_off + q],
@@ -1694,14 +1750,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <int KB>
-__global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
+__global__ __launch_bounds__(kCoThreads) __attribute__((amdgpu_waves_per_eu(3))) void coeffs_kernel(
     const BlkInfo* __restrict__ blks, int l, int k_max, const double* __restrict__ R,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws, double* __restrict__ P,
     __bf16* __restrict__ pt, int KP, int32_t* __restrict__ cols_out, int32_t* __restrict__ ncols_out) {
   constexpr int KM = 16 * KB;          // padded rank
   constexpr int LD = KM + 1;           // R11 row stride in LDS (odd: spreads the banks)
   extern __shared__ double r11[];      // [KM][LD]
-  __shared__ double stage[kCoThreads / 64][16 * kCoSld];
+  __shared__ double tinv[KB][16 * kCoSld];   // inverses of the diagonal 16 x 16 blocks
+  __shared__ int s_sh[KM];
   __shared__ int cols[1024];
   __shared__ unsigned char is_sel[1024];
   __shared__ int wcount[kCoThreads / 64];
@@ -1713,18 +1770,48 @@ __global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
   const int32_t* S = S_ws + (int64_t)b * k_max;
   const double* Rb = R + bi.r_off;
   double* Pb = P + bi.p_off;
-  for (int e = tid; e < KM * KM; e += kCoThreads) {
-    const int s2 = e / KM, t = e - s2 * KM;
-    double v = 0.0;
-    if (s2 < k && t < k) v = (t >= s2) ? Rb[(int64_t)s2 * n + S[t]] : 0.0;
-    else if (s2 == t) v = 1.0;
-    r11[s2 * LD + t] = v;
+  for (int j = tid; j < n; j += kCoThreads) is_sel[j] = 0;
+  if (tid < KM) s_sh[tid] = tid < k ? S[tid] : 0;
+  __syncthreads();
+  if (tid < k) is_sel[s_sh[tid]] = 1;
+  {
+    // R11 with the identity past k: every load issued before the LDS stores
+    constexpr int NE = (KM * KM + kCoThreads - 1) / kCoThreads;
+    double v[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * kCoThreads;
+      const int s2 = e / KM, t = e - s2 * KM;
+      const bool in = e < KM * KM && s2 < k && t < k && t >= s2;
+      v[q] = Rb[in ? (int64_t)s2 * n + s_sh[t] : 0];
+      v[q] = in ? v[q] : (s2 == t ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + q * kCoThreads;
+      const int s2 = e / KM, t = e - s2 * KM;
+      if (e < KM * KM) r11[s2 * LD + t] = v[q];
+    }
+  }
+  __syncthreads();
+  // the inverse of every diagonal block (one column per lane, by
+  // back-substitution on the unit vectors; zero below the diagonal)
+  for (int B = wave; B < KB; B += kCoThreads / 64) {
+    if (lane < 16) {
+      double x[16];
+#pragma unroll
+      for (int i = 15; i >= 0; --i) {
+        const double* rr = r11 + (16 * B + i) * LD + 16 * B;
+        double a = i == lane ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = i + 1; t < 16; ++t) a -= rr[t] * x[t];
+        x[i] = a / rr[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) tinv[B][i * kCoSld + lane] = x[i];
+    }
   }
   // compact list of the non-skeleton columns (ascending)
-  for (int j = tid; j < n; j += kCoThreads) is_sel[j] = 0;
-  __syncthreads();
-  if (tid < k) is_sel[S[tid]] = 1;
-  __syncthreads();
   int ncols = 0;
   for (int base = 0; base < n; base += kCoThreads) {
     const int j = base + tid;
@@ -1744,11 +1831,10 @@ __global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
   const int64_t col_off = bi.y_off / l;
   if (pt && tid == 0) ncols_out[b] = ncols;
   // skeleton columns: exact unit vectors
-  for (int t = tid; t < k; t += kCoThreads) {
-    double* pc = Pb + (int64_t)S[t] * k_max;
-    for (int u = 0; u < k_max; ++u) pc[u] = (u == t) ? 1.0 : 0.0;
+  for (int e = tid; e < k * k_max; e += kCoThreads) {
+    const int t = e / k_max, u = e - t * k_max;
+    Pb[(int64_t)s_sh[t] * k_max + u] = (u == t) ? 1.0 : 0.0;
   }
-  double* st = stage[wave];
   const int c16 = lane & 15, g4 = lane >> 4;
   const int ntiles = (ncols + 15) / 16;
   for (int tile = wave; tile < ntiles; tile += kCoThreads / 64) {
@@ -1764,41 +1850,23 @@ __global__ __launch_bounds__(kCoThreads) void coeffs_kernel(
         const int row = 16 * r + g4 + 4 * v;
         acc[r][v] = (cok && row < k) ? Rb[(int64_t)row * n + j] : 0.0;
       }
+    // From the last row block up: x_B = inv(R11_BB) b_B, then the rows above
+    // lose R11(rows r, columns of B) x_B, all on the matrix cores.  Slot v of
+    // the accumulator layout (row g4 + 4 v) is the B operand of k-step v
+    // (row 4 v + g4), so the solved block feeds the products as it stands.
 #pragma unroll
     for (int B = KB - 1; B >= 0; --B) {
-      // row block B to one lane per column
+      f64x4 xb = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) st[(g4 + 4 * v) * kCoSld + c16] = acc[B][v];
-      wave_lds_sync();
-      if (lane < 16) {
-        double x[16];
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-          const double* rr = r11 + (16 * B + i) * LD + 16 * B;
-          double a = st[i * kCoSld + lane];
-#pragma unroll
-          for (int t = i + 1; t < 16; ++t) a -= rr[t] * x[t];
-          x[i] = a / rr[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) st[i * kCoSld + lane] = x[i];
-      }
-      wave_lds_sync();
-      // the solved block in accumulator layout (for the output) and as the
-      // MFMA B operand (k-step qk: rows 4 qk .. 4 qk + 3)
-      double bop[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[B][v] = st[(g4 + 4 * v) * kCoSld + c16];
-#pragma unroll
-      for (int qk = 0; qk < 4; ++qk) bop[qk] = st[(4 * qk + g4) * kCoSld + c16];
-      wave_lds_sync();   // the next transpose overwrites the staging tile
-      // rows above: b(rows r) -= R11(rows r, columns of B) x_B
+      for (int qk = 0; qk < 4; ++qk)
+        xb = mfma_f64(tinv[B][c16 * kCoSld + 4 * qk + g4], acc[B][qk], xb);
+      acc[B] = xb;
 #pragma unroll
       for (int r = 0; r < B; ++r)
 #pragma unroll
         for (int qk = 0; qk < 4; ++qk) {
           const double a = -r11[(16 * r + c16) * LD + 16 * B + 4 * qk + g4];
-          acc[r] = mfma_f64(a, bop[qk], acc[r]);
+          acc[r] = mfma_f64(a, acc[B][qk], acc[r]);
         }
     }
     if (!cok) continue;
