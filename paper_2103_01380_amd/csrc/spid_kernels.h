@@ -2135,6 +2135,14 @@ void recon_bf16x3_kernel(
     const int32_t* __restrict__ ncols_g, float* __restrict__ skel, double* __restrict__ part) {
   constexpr int KP = 32 * KS32;
   constexpr int kCols = rcbf_cols(KS32);
+  // two-step P staging (KS32 = 2): each step's terms copied from registers
+  // loaded a step earlier, so the copy never waits for the A prefetch;
+  // otherwise chunks of kCols columns copied straight from memory
+  constexpr bool kPipeP = KS32 == 2;
+  // steps of A loaded ahead: two on the two-step P staging, whose register
+  // budget (two waves per SIMD) leaves room for a third line buffer
+  constexpr int kPf = kPipeP ? 2 : 1;
+  static_assert(!kPipeP || (kCols == 64 && 3 * KP == 8 * 8 * 3), "two 32-column slots");
   // a column's three terms, 3 KP bfloat16 (a multiple of 32 dwords), then 8
   // bfloat16 of padding: the 16 columns one MFMA reads start 4 banks apart
   // instead of on one bank
@@ -2240,9 +2248,45 @@ void recon_bf16x3_kernel(
           else load_line_tail<float>(src, rbase, bi.m, p8, x[gq][h]);
         }
     };
+    // P terms of step s's 32 columns (pipelined form): thread t copies pieces
+    // 8 (t % 8) + 64 i .. + 7, i < 3, of column t / 8 (a column's 3 KP terms
+    // are contiguous, so 8 threads read its 384 bytes in three 128-byte
+    // runs), loaded into registers a step ahead of their copy into LDS slot
+    // s & 1; columns past ncols are zero.  The offsets are fixed per thread,
+    // the step only moves the (scalar) base.
+    constexpr int NPC = 3;
+    bf16x8 pv[kPipeP ? NPC : 1];
+    const int pq = tid >> 3, pr = 8 * (tid & 7);
+    auto load_p = [&](int s) {
+      const int c0 = 32 * s, cc = min(32, ncols - c0);
+      // the last step reads its last column for the columns past ncols, then zeroes them
+      const int qc = cc < 32 ? min(pq, cc - 1) : pq;
+      const __bf16* src = ptb + (int64_t)c0 * 3 * KP + (qc * 3 * KP + pr);
+#pragma unroll
+      for (int i = 0; i < NPC; ++i) pv[i] = *reinterpret_cast<const bf16x8*>(src + 64 * i);
+      if (cc < 32) {
+#pragma unroll
+        for (int i = 0; i < NPC; ++i) pv[i] = pq < cc ? pv[i] : bf16x8{};
+      }
+    };
+    auto store_p = [&](int s) {
+      __bf16* dst = pt + (s & 1) * 32 * kPtStride + (pq * kPtStride + pr);
+#pragma unroll
+      for (int i = 0; i < NPC; ++i) *reinterpret_cast<bf16x8*>(dst + 64 * i) = pv[i];
+    };
     auto step = [&](const float (&x)[2][2][4], float (&xn)[2][2][4], int s) {
-      if ((32 * s) % kCols == 0) stage_p(32 * s);
-      load(min(s + 1, nst - 1), xn);
+      if constexpr (kPipeP) {
+        // one barrier per step: every wave is done with slot (s + 1) & 1 (step
+        // s - 1) and sees slot s & 1.  Each step's P loads are issued before
+        // its A prefetch, so the copy never waits for A loads of later steps.
+        lds_barrier();
+        if (s + 1 < nst) store_p(s + 1);
+        if (s + 2 < nst) load_p(s + 2);
+        load(min(s + kPf, nst - 1), xn);
+      } else {
+        if ((32 * s) % kCols == 0) stage_p(32 * s);
+        load(min(s + 1, nst - 1), xn);
+      }
       float es = 0.0f, as = 0.0f;   // the step's squared residuals and squared entries
       // one 16-column group; MASK: some of its columns lie past ncols (the
       // block's last group only)
@@ -2296,14 +2340,37 @@ void recon_bf16x3_kernel(
       e2 += (double)es;
       a2 += (double)as;
     };
-    float xa[2][2][4], xb[2][2][4];
-    load(0, xa);
     int s = 0;
-    for (; s + 1 < nst; s += 2) {
-      step(xa, xb, s);
-      step(xb, xa, s + 1);
+    if constexpr (kPf == 1) {
+      float xa[2][2][4], xb[2][2][4];
+      if constexpr (kPipeP) {
+        load_p(0);
+        store_p(0);
+        if (nst > 1) load_p(1);
+      }
+      load(0, xa);
+      for (; s + 1 < nst; s += 2) {
+        step(xa, xb, s);
+        step(xb, xa, s + 1);
+      }
+      if (s < nst) step(xa, xb, s);
+    } else {
+      // two steps of A in flight: step s reads buffer s % 3 and loads step
+      // s + 2 into the buffer step s - 1 has finished with
+      float xa[2][2][4], xb[2][2][4], xc[2][2][4];
+      load_p(0);
+      store_p(0);
+      if (nst > 1) load_p(1);
+      load(0, xa);
+      load(min(1, nst - 1), xb);
+      for (; s + 3 <= nst; s += 3) {
+        step(xa, xc, s);
+        step(xb, xa, s + 1);
+        step(xc, xb, s + 2);
+      }
+      if (s < nst) step(xa, xc, s);
+      if (s + 1 < nst) step(xb, xa, s + 1);
     }
-    if (s < nst) step(xa, xb, s);
   };
   if (ncols > 0) {
     if (rbase + 16 * MTR <= bi.m) body(std::true_type{});
