@@ -1732,10 +1732,20 @@ static __global__ void select_export_kernel(int nblocks, int k_max, const int32_
 // condition number is at most that of R11).  When `pt` is given (mixed
 // error pass on FP32 data) the wave also writes the three bfloat16 terms
 // (hi, mid, lo: 24 significant bits) of its columns' negated coefficients and
-// the compact column list, so the error pass stages them by plain copies.  Layouts: cols[col_off + q],
-// pt[(col_off + q) * 3 * KP + term * KP + t] with col_off = y_off / l (the
-// block's first column in the batch), KP = 32 KS32.
+// the compact column list, so the error pass stages them by plain copies.
+// Layouts: cols[col_off + q], pt[(col_off + q) * 3 * KP + term * KP + 8 pi + v]
+// = term of -P(rcbf_sel(pi / 4, pi % 4, v), column q) with col_off = y_off / l
+// (the block's first column in the batch), KP = 32 KS32 = 32 ceil(KB / 2).
 // ---------------------------------------------------------------------------
+// Order of the split coefficient terms (mixed error pass): slot v of the
+// 16-byte piece 4 ks + g of a term holds coefficient row rcbf_sel(ks, g, v),
+// and the error pass gathers selected column rcbf_sel(ks, g, v) into the same
+// slot of its MFMA operand (the sum over the selected columns, permuted
+// alike on both sides).  Rows 16 r + g + 4 u (u < 4) are accumulator slots of
+// tile r in the coefficients kernel, so its lanes write whole pieces.
+__host__ __device__ constexpr int rcbf_sel(int ks, int g, int v) {
+  return 32 * ks + 16 * (v >> 2) + g + 4 * (v & 3);
+}
 constexpr int kCoThreads = 256;
 constexpr int kCoSld = 17;    // row stride of a wave's 16 x 16 staging tile (doubles)
 
@@ -1749,8 +1759,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
+// three workgroups per CU fit the LDS up to KB = 4 (one for KB = 6)
 template <int KB>
-__global__ __launch_bounds__(kCoThreads) __attribute__((amdgpu_waves_per_eu(3))) void coeffs_kernel(
+__global__ __launch_bounds__(kCoThreads) __attribute__((amdgpu_waves_per_eu(KB <= 4 ? 3 : 1))) void coeffs_kernel(
     const BlkInfo* __restrict__ blks, int l, int k_max, const double* __restrict__ R,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws, double* __restrict__ P,
     __bf16* __restrict__ pt, int KP, int32_t* __restrict__ cols_out, int32_t* __restrict__ ncols_out) {
@@ -1881,28 +1892,34 @@ __global__ __launch_bounds__(kCoThreads) __attribute__((amdgpu_waves_per_eu(3)))
       }
     if (pt) {
       if (g4 == 0) cols_out[col_off + cq] = j;
-      // three bfloat16 terms of every coefficient, rows past 16 KB zero up to KP
+      // three bfloat16 terms of every coefficient (rows past 16 KB zero up to
+      // KP), in 16-byte pieces: piece pi = 4 rho + g4 of a term holds rows
+      // 32 rho + 16 (v / 4) + g4 + 4 (v % 4), v < 8 -- accumulator slots
+      // v % 4 of tiles 2 rho and 2 rho + 1 of this lane -- so every lane
+      // writes whole pieces.  The error pass gathers its selected columns in
+      // the same order (sum over the selected columns permuted alike).
       __bf16* o = pt + (col_off + cq) * 3 * KP;
 #pragma unroll
-      for (int r = 0; r < KB; ++r)
+      for (int rho = 0; rho < (KB + 1) / 2; ++rho) {
+        bf16x8 th, tm, tl;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int t = 16 * r + g4 + 4 * v;
-          if (t < KP) {
-            const double pv = -acc[r][v];   // the error pass adds the products to A
-            const __bf16 hi = to_bf16((float)pv);
-            const double r1 = pv - (double)(float)hi;
-            const __bf16 md = to_bf16((float)r1);
-            const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
-            o[t] = hi;
-            o[KP + t] = md;
-            o[2 * KP + t] = lo;
-          }
+        for (int v = 0; v < 8; ++v) {
+          // row rcbf_sel(rho, g4, v) = 16 r + g4 + 4 (v % 4): slot v % 4 of tile r
+          static_assert(rcbf_sel(1, 2, 5) == 16 * 3 + 2 + 4 * 1, "piece order");
+          const int r = 2 * rho + (v >> 2);
+          const double pv = r < KB ? -acc[r < KB ? r : 0][v & 3] : 0.0;   // the error pass adds the products to A
+          const __bf16 hi = to_bf16((float)pv);
+          const double r1 = pv - (double)(float)hi;
+          const __bf16 md = to_bf16((float)r1);
+          const __bf16 lo = to_bf16((float)(r1 - (double)(float)md));
+          th[v] = hi;
+          tm[v] = md;
+          tl[v] = lo;
         }
-      for (int t = KM + g4; t < KP; t += 4) {
-        o[t] = to_bf16(0.0f);
-        o[KP + t] = to_bf16(0.0f);
-        o[2 * KP + t] = to_bf16(0.0f);
+        const int pi = 4 * rho + g4;
+        *reinterpret_cast<bf16x8*>(o + 8 * pi) = th;
+        *reinterpret_cast<bf16x8*>(o + KP + 8 * pi) = tm;
+        *reinterpret_cast<bf16x8*>(o + 2 * KP + 8 * pi) = tl;
       }
     }
   }
@@ -2177,8 +2194,9 @@ void recon_bf16x3_kernel(
 #pragma unroll
   for (int mt = 0; mt < MTR; ++mt) st_r[mt] = (int)(line_piece(st, c16, 4 * mt + g) - st);
 
-  // A operand: tile row c16, selected columns 32 ks + 8 g + v, three terms (k-steps past
-  // ksn are never read)
+  // A operand: tile row c16, slot v of k-step ks holds selected column
+  // rcbf_sel(ks, g, v) (the order of the coefficient terms' pieces), three
+  // terms (k-steps past ksn are never read)
   bf16x8 at[MTR][KS32][3];
   double a2 = 0.0, e2 = 0.0;
 #pragma unroll
@@ -2193,12 +2211,12 @@ void recon_bf16x3_kernel(
       float xv[8];
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        const int t = 32 * ks + 8 * g + v;
+        const int t = rcbf_sel(ks, g, v);
         xv[v] = A[(int64_t)S[t < k ? t : 0] * bi.lda + (iok ? i : 0)];
       }
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        const int t = 32 * ks + 8 * g + v;
+        const int t = rcbf_sel(ks, g, v);
         const bool ok = t < k && iok;
         const float x = ok ? xv[v] : 0.0f;
         if (skel && ok) skel[bi.sk_off + (int64_t)t * bi.m + i] = x;

@@ -69,6 +69,7 @@ bool launch_coeffs_t(spid_ctx* c, double* P, hipStream_t s) {
   const size_t lds = coeffs_lds_bytes(KB);
   if (!allow_lds((const void*)coeffs_kernel<KB>, lds)) return false;
   const bool bf = p.sh.rc_bf16 != 0;
+  if (bf && p.sh.KS32 != (KB + 1) / 2) return false;   // the terms' pieces cover 32 KS32 rows
   hipLaunchKernelGGL((coeffs_kernel<KB>), dim3(c->desc.nblocks), dim3(kCoThreads), lds, s,
                      c->at<BlkInfo>(p.off_blk), c->desc.l, c->desc.k_max, c->at<double>(p.off_R),
                      c->at<int32_t>(p.off_S), c->at<int32_t>(p.off_k), P,
