@@ -273,11 +273,11 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
   }
 }
 
-// The same argmax with the first four exchange levels by DPP lane moves within
-// each row of 16 lanes (quad permutations, then the half-row and row mirrors)
-// and the last two by lane shuffles.  The operation (max, lowest index on
-// equal values) is commutative, associative and idempotent, so every lane ends
-// with the argmax over the 64 lanes whatever the exchange pattern.
+// One exchange level of the same argmax by DPP lane moves within each row of
+// 16 lanes (CTRL: the quad permutations, then the half-row and row mirrors).
+// The operation (max, lowest index on equal values) is commutative,
+// associative and idempotent, so after the four levels every lane of a row
+// holds the row's argmax whatever the exchange pattern.
 template <int CTRL>
 __device__ __forceinline__ void argmax_dpp_level(double& v, int& idx) {
   const long long b = __double_as_longlong(v);
@@ -291,19 +291,35 @@ __device__ __forceinline__ void argmax_dpp_level(double& v, int& idx) {
   idx = take ? oi : idx;
 }
 
-__device__ __forceinline__ void wave_argmax_dpp(double& v, int& idx) {
-  argmax_dpp_level<0xB1>(v, idx);    // quad_perm [1,0,3,2]
-  argmax_dpp_level<0x4E>(v, idx);    // quad_perm [2,3,0,1]
-  argmax_dpp_level<0x141>(v, idx);   // row_half_mirror (lane i <-> 7 - i)
-  argmax_dpp_level<0x140>(v, idx);   // row_mirror (lane i <-> 15 - i)
+// The same argmax, made wave-uniform: the four DPP levels within each row of
+// 16 lanes, then the four row results combined through lane reads (rows in
+// ascending order) rather than lane-shuffle rounds through the LDS unit.
+__device__ __forceinline__ void wave_argmax_uniform(double& v, int& idx) {
+  argmax_dpp_level<0xB1>(v, idx);
+  argmax_dpp_level<0x4E>(v, idx);
+  argmax_dpp_level<0x141>(v, idx);
+  argmax_dpp_level<0x140>(v, idx);
+  const long long b = __double_as_longlong(v);
+  double bv = v;
+  int bi = idx;
 #pragma unroll
-  for (int off = 16; off <= 32; off <<= 1) {
-    const double ov = __shfl_xor(v, off, kWave);
-    const int oi = __shfl_xor(idx, off, kWave);
-    const bool take = (ov > v) | ((ov == v) & (oi < idx));
-    v = take ? ov : v;
-    idx = take ? oi : idx;
+  for (int r = 0; r < 4; ++r) {
+    const int lo = __builtin_amdgcn_readlane((int)b, 16 * r);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * r);
+    const double ov = __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                                       (unsigned)lo));
+    const int oi = __builtin_amdgcn_readlane(idx, 16 * r);
+    if (r == 0) {
+      bv = ov;
+      bi = oi;
+    } else {
+      const bool take = (ov > bv) | ((ov == bv) & (oi < bi));
+      bv = take ? ov : bv;
+      bi = take ? oi : bi;
+    }
   }
+  v = bv;
+  idx = bi;
 }
 
 // ---------------------------------------------------------------------------

@@ -1378,7 +1378,7 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
         bc = take ? c : bc;
       }
       const int my_j = bj;
-      wave_argmax_dpp(bv, bj);
+      wave_argmax_uniform(bv, bj);
       double rw = 0.0;
       if (tol > 0.0 && s > 0) rw = live_sum();
       if ((my_j == bj) & (bj != 0x7fffffff)) {
