@@ -1754,10 +1754,6 @@ __host__ __device__ constexpr size_t coeffs_lds_bytes(int KB) {
   return sizeof(double) * (size_t)(16 * KB) * (16 * KB + 1);
 }
 
-// wave-local ordering of LDS accesses (the wave's own writes before its reads)
-__device__ __forceinline__ void wave_lds_sync() {
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-}
 
 // three workgroups per CU fit the LDS up to KB = 4 (one for KB = 6)
 template <int KB>
@@ -2194,10 +2190,22 @@ void recon_bf16x3_kernel(
 #pragma unroll
   for (int mt = 0; mt < MTR; ++mt) st_r[mt] = (int)(line_piece(st, c16, 4 * mt + g) - st);
 
+  // the block's non-skeleton column indices (loads issued first: the item's
+  // first loads all overlap)
+  static_assert(kRcMaxCols == 4 * kRcThreads, "four column indices per thread");
+  int32_t cidx[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = tid + u * kRcThreads;
+    cidx[u] = colb[c < ncols ? c : 0];
+  }
   // A operand: tile row c16, slot v of k-step ks holds selected column
   // rcbf_sel(ks, g, v) (the order of the coefficient terms' pieces), three
-  // terms (k-steps past ksn are never read)
+  // terms (k-steps past ksn are never read).  The gather is issued without
+  // branches (out-of-range entries read row 0 / the first selected column,
+  // then are zeroed), behind the column-index loads, so both overlap.
   bf16x8 at[MTR][KS32][3];
+  float xsel[MTR][KS32][8];
   double a2 = 0.0, e2 = 0.0;
 #pragma unroll
   for (int mt = 0; mt < MTR; ++mt) {
@@ -2206,19 +2214,25 @@ void recon_bf16x3_kernel(
 #pragma unroll
     for (int ks = 0; ks < KS32; ++ks) {
       if (ks >= ksn) break;
-      // gather without branches (out-of-range entries read row 0 / the
-      // first selected column, then are zeroed), so the loads overlap
-      float xv[8];
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         const int t = rcbf_sel(ks, g, v);
-        xv[v] = A[(int64_t)S[t < k ? t : 0] * bi.lda + (iok ? i : 0)];
+        xsel[mt][ks][v] = A[(int64_t)S[t < k ? t : 0] * bi.lda + (iok ? i : 0)];
       }
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < MTR; ++mt) {
+    const int64_t i = rbase + 16 * mt + c16;
+    const bool iok = i < bi.m;
+#pragma unroll
+    for (int ks = 0; ks < KS32; ++ks) {
+      if (ks >= ksn) break;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         const int t = rcbf_sel(ks, g, v);
         const bool ok = t < k && iok;
-        const float x = ok ? xv[v] : 0.0f;
+        const float x = ok ? xsel[mt][ks][v] : 0.0f;
         if (skel && ok) skel[bi.sk_off + (int64_t)t * bi.m + i] = x;
         a2 += (double)x * (double)x;
         const __bf16 h = to_bf16(x);
@@ -2249,7 +2263,11 @@ void recon_bf16x3_kernel(
 
   const int nst = (ncols + 31) >> 5;   // 32-column steps
   // the block's non-skeleton column offsets, once per item (the loads index them)
-  for (int c = tid; c < ncols; c += kRcThreads) coff[c] = (int64_t)colb[c] * bi.lda;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = tid + u * kRcThreads;
+    if (c < ncols) coff[c] = (int64_t)cidx[u] * bi.lda;
+  }
   lds_barrier();
   auto body = [&](auto full_c) {
     constexpr bool kFull = decltype(full_c)::value;
@@ -2363,10 +2381,12 @@ void recon_bf16x3_kernel(
       float xa[2][2][4], xb[2][2][4];
       if constexpr (kPipeP) {
         load_p(0);
+        load(0, xa);
         store_p(0);
         if (nst > 1) load_p(1);
+      } else {
+        load(0, xa);
       }
-      load(0, xa);
       for (; s + 1 < nst; s += 2) {
         step(xa, xb, s);
         step(xb, xa, s + 1);
@@ -2376,10 +2396,12 @@ void recon_bf16x3_kernel(
       // two steps of A in flight: step s reads buffer s % 3 and loads step
       // s + 2 into the buffer step s - 1 has finished with
       float xa[2][2][4], xb[2][2][4], xc[2][2][4];
+      // step 0's P and A in flight while the selected columns are split;
+      // each step's P issued before its A (the copy waits for no later A)
       load_p(0);
+      load(0, xa);
       store_p(0);
       if (nst > 1) load_p(1);
-      load(0, xa);
       load(min(1, nst - 1), xb);
       for (; s + 3 <= nst; s += 3) {
         step(xa, xc, s);
