@@ -188,3 +188,29 @@ def test_tall_sketch_selection_variants_f64(l, k, shapes, tol):
     o = oracle_run(blocks, l, k, 14, tol=tol)
     st = compare(g, o)
     assert min(st["prefix"]) >= 10
+
+
+@pytest.mark.parametrize("l,k,shapes,decay", [
+    (16, 8, [(1000, 100, 12), (777, 50, 20)], 0.5),                # one 16-row coefficient block
+    (96, 80, [(3000, 200, 90), (1500, 130, 100), (641, 97, 95)], 0.07),   # six blocks, three k-steps
+])
+def test_bf16_coefficient_term_orders(l, k, shapes, decay):
+    """The split coefficient terms are written in 16-byte pieces of the coefficients
+    kernel's own rows and the error pass gathers its selected columns in that order:
+    ranks that fill one and six 16-row coefficient blocks (one and three 32-column
+    k-steps of the error pass), against the oracle and a direct evaluation.  Every
+    block has more than k singular values above the sketch's rounding, so the
+    selections stay well conditioned."""
+    rng = np.random.default_rng(27 + k)
+    blocks = []
+    for (m, n, r) in shapes:
+        U = np.linalg.qr(rng.standard_normal((m, r)))[0]
+        V = np.linalg.qr(rng.standard_normal((n, r)))[0]
+        blocks.append(np.asfortranarray(((U * 10.0 ** (-decay * np.arange(r))) @ V.T)
+                                        .astype(np.float32)))
+    print(f"case: bf16 coefficient terms l={l} k={k} shapes={shapes}", flush=True)
+    g = gpu_run(blocks, l, k, 15, prec="bf16", lp_terms=2)
+    o = oracle_run(blocks, l, k, 15, prec="bf16")
+    e_gpu, e_ora, r2 = _gates(blocks, g, o)
+    print(f"e_gpu={e_gpu:.3e} e_oracle={e_ora:.3e} R2={r2:.3e} k_gpu={g.k}")
+    assert e_gpu <= 1e-3 and r2 <= 1e-3
