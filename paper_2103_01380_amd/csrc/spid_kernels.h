@@ -2125,13 +2125,15 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
 // A work item is 128 rows (4 waves x 32) of one block; a wave's skeleton
 // terms (its 32 rows of A(:, S)) stay in registers.  The non-skeleton columns
 // are streamed in steps of 32: the step's A values arrive as whole 128-byte
-// lines (two load instructions per 16 columns) loaded one step ahead, and are
-// passed through a wave-private LDS tile into the MFMA output layout (lane
-// (g, c16) holds rows 4g..4g+3 of column c16 of each 16-row tile).  The P
-// terms (split once by the coefficients kernel, with the compact column list)
-// are staged rcbf_cols(KS32) columns at a time (about 26 KiB of LDS) by plain
-// 16-byte copies behind LDS-only barriers; the columns' element offsets are
-// staged whole at the start, so the prefetch runs across those barriers.
+// lines (two load instructions per 16 columns) loaded one step ahead (two at
+// KS32 = 2), and are passed through a wave-private LDS tile into the MFMA
+// output layout (lane (g, c16) holds rows 4g..4g+3 of column c16 of each
+// 16-row tile).  The P terms (split once by the coefficients kernel, with the
+// compact column list) are staged rcbf_cols(KS32) columns at a time (about 26
+// KiB of LDS) by plain 16-byte copies behind LDS-only barriers, or at KS32 = 2
+// a step at a time from registers loaded a step earlier; the columns' element
+// offsets are staged whole at the start, so the prefetch runs across the
+// barriers.
 // ---------------------------------------------------------------------------
 constexpr int kRcBfSubs = 1;
 constexpr int kRcMaxCols = 1024;   // widest block (the descriptor limit on n)
