@@ -1265,8 +1265,10 @@ __device__ __forceinline__ double readfirstlane_f64(double v) {
 
 constexpr double kNormRecompute = 1e-3;
 
+// two workgroups per CU at 256 threads, one at 512 or 768 (two or three waves per SIMD)
 template <typename TY, int RPT, int LPC, int CPL, int MAXTHR>
-__global__ __launch_bounds__(MAXTHR) void select_step_kernel(
+__global__ __launch_bounds__(MAXTHR) __attribute__((amdgpu_waves_per_eu(MAXTHR == 768 ? 3 : 2)))
+void select_step_kernel(
     const BlkInfo* __restrict__ blks, int l, int k_max, double tol, double rank_floor,
     const TY* __restrict__ Y, double* __restrict__ R, int32_t* __restrict__ S_ws,
     int32_t* __restrict__ k_ws, int32_t* __restrict__ st_ws) {
@@ -1295,25 +1297,26 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
   // by group: it is read once per step
   __shared__ __attribute__((aligned(16))) float nref_s[MAXTHR / LPC][CPL];
   float* __restrict__ nref = nref_s[tid / LPC];
-  bool live[CPL];
+  // a column past n or already selected carries nu = -1 (never the argmax,
+  // left out of the sums) and nref = -inf (never recomputed)
   int bad = 0;
 #pragma unroll
   for (int c = 0; c < CPL; ++c) {
     const int j = j0 + c;
-    live[c] = j < n;
+    const bool in = j < n;
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       double v = 0.0;
-      if (live[c] && r0 + i < l) v = (double)Yb[(int64_t)j * l + r0 + i];
+      if (in && r0 + i < l) v = (double)Yb[(int64_t)j * l + r0 + i];
       if (!isfinite(v)) bad = 1;
       w[c][i] = v;
       if (i & 1) s1 += v * v;
       else s0 += v * v;
     }
-    nu[c] = group_sum<LPC>(s0 + s1);
-    nu[c] = live[c] ? nu[c] : 0.0;
-    if (h == 0) nref[c] = (float)nu[c];
+    const double ns = group_sum<LPC>(s0 + s1);
+    nu[c] = in ? ns : -1.0;
+    if (h == 0) nref[c] = in ? (float)ns : -INFINITY;
   }
   // candidate entries of waves that do not exist never win and add nothing
   for (int e = tid; e < 2 * NWMAX; e += blockDim.x) {
@@ -1328,7 +1331,7 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
     double fs = 0.0, fm = 0.0;
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
-      fs += h == 0 ? nu[c] : 0.0;
+      fs += h == 0 ? fmax(nu[c], 0.0) : 0.0;
       fm = fmax(fm, nu[c]);
     }
     fs = wave_sum(fs);
@@ -1358,7 +1361,7 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
   auto live_sum = [&]() {  // sum of the live residual norms of the lane's group (once)
     double t = 0.0;
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) t += (h == 0 && live[c]) ? nu[c] : 0.0;
+    for (int c = 0; c < CPL; ++c) t += h == 0 ? fmax(nu[c], 0.0) : 0.0;
     return wave_sum(t);
   };
   if (any_bad) {
@@ -1372,7 +1375,7 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
       int bj = 0x7fffffff, bc = 0;
 #pragma unroll
       for (int c = 0; c < CPL; ++c) {
-        const bool take = live[c] & (nu[c] > bv);   // ties keep the lower column
+        const bool take = nu[c] > bv;   // ties keep the lower column
         bv = take ? nu[c] : bv;
         bj = take ? j0 + c : bj;
         bc = take ? c : bc;
@@ -1454,8 +1457,8 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
 #pragma unroll
       for (int c = 0; c < CPL; ++c)
         if (j0 + c == p) {
-          live[c] = false;
-          nu[c] = 0.0;
+          nu[c] = -1.0;
+          if (h == 0) nref[c] = -INFINITY;
         }
       if (h == 0 && p >= j0 && p < j0 + CPL) {
         Rb[(int64_t)s * n + p] = rss;
@@ -1483,16 +1486,18 @@ __global__ __launch_bounds__(MAXTHR) void select_step_kernel(
           d0 += q[i] * w[c][i];
           d1 += q[i + 1] * w[c][i + 1];
         }
-        const double d = live[c] ? group_sum<LPC>(d0 + d1) * inv_rss : 0.0;
-        if (live[c] && h == 0) Rb[(int64_t)s * n + j0 + c] = d;
+        // (columns already selected hold a residue of rounding size; their
+        // entries of R below the diagonal are never read)
+        const double d = group_sum<LPC>(d0 + d1) * inv_rss;
+        if (h == 0 && j0 + c < n) Rb[(int64_t)s * n + j0 + c] = d;
         const double coef = d * inv_rss;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) w[c][i] -= coef * q[i];
         // group-uniform: nu, nref and d are equal on the group's lanes
         const double nd = nu[c] - d * d;
-        need[c] = live[c] && nd < kNormRecompute * (double)nref[c];
+        need[c] = nd < kNormRecompute * (double)nref[c];
         any_need |= need[c];
-        nu[c] = live[c] ? nd : 0.0;
+        nu[c] = nd;
         __builtin_amdgcn_sched_barrier(0);
       }
       // recomputation, skipped by the whole wave when no column needs it
