@@ -1305,12 +1305,19 @@ void select_step_kernel(
     const int j = j0 + c;
     const bool in = j < n;
     double s0 = 0.0, s1 = 0.0;
+    // every load from a valid address (the block's first entry for rows and
+    // columns outside it) and the value selected after, so that the loads
+    // are all in flight together
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      double v = 0.0;
-      if (in && r0 + i < l) v = (double)Yb[(int64_t)j * l + r0 + i];
+      const bool ok = in && r0 + i < l;
+      const TY raw = Yb[ok ? (int64_t)j * l + r0 + i : 0];
+      w[c][i] = ok ? (double)raw : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const double v = w[c][i];
       if (!isfinite(v)) bad = 1;
-      w[c][i] = v;
       if (i & 1) s1 += v * v;
       else s0 += v * v;
     }
@@ -1570,17 +1577,24 @@ __global__ __launch_bounds__(MAXTHR) void select_hybrid_kernel(
   int bad = 0;
   double nu;
   {
+    // loads from valid addresses (the block's first entry outside it), values
+    // selected after, so that the loads are in flight together
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
-      double v = 0.0;
-      if (live && r < l) v = (double)Yb[(int64_t)j * l + r];
-      if (!isfinite(v)) bad = 1;
-      w[r] = v;
-      acc += v * v;
+      const bool ok = live && r < l;
+      const TY raw = Yb[ok ? (int64_t)j * l + r : 0];
+      w[r] = ok ? (double)raw : 0.0;
     }
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      if (!isfinite(w[r])) bad = 1;
+      acc += w[r] * w[r];
+    }
+#pragma unroll 8
     for (int r = 0; r < lr; ++r) {
-      const double v = live ? (double)Yb[(int64_t)j * l + RR + r] : 0.0;
+      const TY raw = Yb[live ? (int64_t)j * l + RR + r : 0];
+      const double v = live ? (double)raw : 0.0;
       if (!isfinite(v)) bad = 1;
       wl[r * nthr + tid] = v;
       acc += v * v;
