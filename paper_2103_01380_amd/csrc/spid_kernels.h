@@ -2023,7 +2023,7 @@ __device__ __forceinline__ void rc_load4(gptr<TA> __restrict__ colp, int64_t i0,
 // Dynamic LDS: pcap * 4 * KS doubles.
 // ---------------------------------------------------------------------------
 template <typename TA, int KS, int MTR, bool VEC>
-__global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
+__global__ __launch_bounds__(kRcThreads) __attribute__((amdgpu_waves_per_eu(2))) void recon_mfma_kernel(
     const BlkInfo* __restrict__ blks, const RcItem* __restrict__ items, XcdSplit xs, int k_max, int pcap,
     const int32_t* __restrict__ S_ws, const int32_t* __restrict__ k_ws,
     const double* __restrict__ P, TA* __restrict__ skel, double* __restrict__ part) {
@@ -2067,18 +2067,29 @@ __global__ __launch_bounds__(kRcThreads) void recon_mfma_kernel(
     __syncthreads();
     for (int rs = 0; rs < it.nsub; ++rs) {
       const int64_t rbase = it.i0 + (int64_t)rs * kSub + (int64_t)wave * 16 * MTR;
+      // gather without branches (entries outside the block or past k read the
+      // first selected column / row 0, then are zeroed), so the loads overlap
       double as[MTR][KS];
 #pragma unroll
       for (int mt = 0; mt < MTR; ++mt) {
         const int64_t i = rbase + 16 * mt + arow;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
+          as[mt][s] = 0.0;
+          if (4 * s >= k) continue;   // uniform: k-steps past the selected columns are never read
           const int t = 4 * s + g;
-          double v = 0.0;
-          if (t < k && i < bi.m) {
-            v = (double)A[(int64_t)S[t] * bi.lda + i];
-            if (skel && c0 == 0) skel[bi.sk_off + (int64_t)t * bi.m + i] = (TA)v;
-          }
+          as[mt][s] = (double)A[(int64_t)S[t < k ? t : 0] * bi.lda + (i < bi.m ? i : 0)];
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < MTR; ++mt) {
+        const int64_t i = rbase + 16 * mt + arow;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int t = 4 * s + g;
+          const bool ok = t < k && i < bi.m;
+          const double v = ok ? as[mt][s] : 0.0;
+          if (ok && skel && c0 == 0) skel[bi.sk_off + (int64_t)t * bi.m + i] = (TA)v;
           as[mt][s] = v;
           if (c0 == 0) a2 += v * v;
         }

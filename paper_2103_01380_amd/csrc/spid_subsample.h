@@ -655,16 +655,22 @@ __global__ __launch_bounds__(kRcThreads) void interp_mfma_kernel(
             w[c] = (a ? wz1 : wz0) * (bb ? wy1 : wy0) * (d ? wx1 : wx0);
           }
         }
+        // stencils gathered without branches (entries outside the block or
+        // past k read the first selected column, then are zeroed), so the
+        // loads overlap
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
+          as[mt][s] = 0.0;
+          if (4 * s >= k) continue;   // uniform: k-steps past the selected columns are never read
           const int t = 4 * s + g;
-          double v = 0.0;
-          if (t < k && row) {
-            const double* __restrict__ col = Yb + (int64_t)S[t] * l;
+          const double* __restrict__ col = Yb + (int64_t)S[t < k ? t : 0] * l;
+          double gv[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) v += w[c] * col[idx[c]];
-          }
-          as[mt][s] = v;
+          for (int c = 0; c < 8; ++c) gv[c] = col[idx[c]];
+          double v = 0.0;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) v += w[c] * gv[c];
+          as[mt][s] = (t < k && row) ? v : 0.0;
         }
       }
       for (int tq = 0; tq < ntile; ++tq) {
