@@ -1863,35 +1863,55 @@ __global__ __launch_bounds__(kCoThreads) __attribute__((amdgpu_waves_per_eu(KB <
   }
   const int c16 = lane & 15, g4 = lane >> 4;
   const int ntiles = (ncols + 15) / 16;
-  for (int tile = wave; tile < ntiles; tile += kCoThreads / 64) {
-    const int cq = tile * 16 + c16;          // compact index of the lane's column
+  // right-hand sides R12(:, j) of a tile: tile r, slot v holds row 16 r + g4 +
+  // 4 v; loaded from valid addresses with the values selected after, one
+  // tile ahead, so that the loads of the next tile are in flight during this
+  // tile's products and are issued before its stores (a wait for them then
+  // covers no store)
+  auto load_rhs = [&](int tile, f64x4 (&b)[KB]) {
+    const int cq = tile * 16 + c16;
     const bool cok = cq < ncols;
     const int j = cok ? cols[cq] : 0;
-    // right-hand sides R12(:, j): tile r, slot v holds row 16 r + g4 + 4 v
-    f64x4 acc[KB];
 #pragma unroll
     for (int r = 0; r < KB; ++r)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * r + g4 + 4 * v;
-        acc[r][v] = (cok && row < k) ? Rb[(int64_t)row * n + j] : 0.0;
+        const bool ok = cok && row < k;
+        const double x = Rb[ok ? (int64_t)row * n + j : 0];
+        b[r][v] = ok ? x : 0.0;
       }
+  };
+  f64x4 nxt[KB];
+  if (wave < ntiles) load_rhs(wave, nxt);
+  for (int tile = wave; tile < ntiles; tile += kCoThreads / 64) {
+    const int cq = tile * 16 + c16;          // compact index of the lane's column
+    const bool cok = cq < ncols;
+    const int j = cok ? cols[cq] : 0;
+    f64x4 acc[KB];
+#pragma unroll
+    for (int r = 0; r < KB; ++r) acc[r] = nxt[r];
+    if (tile + kCoThreads / 64 < ntiles) load_rhs(tile + kCoThreads / 64, nxt);
     // From the last row block up: x_B = inv(R11_BB) b_B, then the rows above
     // lose R11(rows r, columns of B) x_B, all on the matrix cores.  Slot v of
     // the accumulator layout (row g4 + 4 v) is the B operand of k-step v
     // (row 4 v + g4), so the solved block feeds the products as it stands.
+    // the operands are read from LDS in every tile (an opaque offset keeps
+    // the compiler from holding all of them in registers across tiles)
+    int lo = 0;
+    asm volatile("" : "+v"(lo));
 #pragma unroll
     for (int B = KB - 1; B >= 0; --B) {
       f64x4 xb = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int qk = 0; qk < 4; ++qk)
-        xb = mfma_f64(tinv[B][c16 * kCoSld + 4 * qk + g4], acc[B][qk], xb);
+        xb = mfma_f64(tinv[B][lo + c16 * kCoSld + 4 * qk + g4], acc[B][qk], xb);
       acc[B] = xb;
 #pragma unroll
       for (int r = 0; r < B; ++r)
 #pragma unroll
         for (int qk = 0; qk < 4; ++qk) {
-          const double a = -r11[(16 * r + c16) * LD + 16 * B + 4 * qk + g4];
+          const double a = -r11[lo + (16 * r + c16) * LD + 16 * B + 4 * qk + g4];
           acc[r] = mfma_f64(a, acc[B][qk], acc[r]);
         }
     }
